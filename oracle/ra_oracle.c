@@ -1,0 +1,562 @@
+/*
+ * ra_oracle.c — FP64 CPU oracle for replica-averaged Brownian dynamics.
+ *
+ * TEST INFRASTRUCTURE ONLY (see ra_oracle.h). Plain loops over replicas,
+ * beads and components in bead-position form, written for a reader to check
+ * against the paper by eye; no blocking, fusion or reordering.
+ *
+ * Paper: Kania, Nguyen, Oztekin, Webb, "Replica-Averaging: An algorithm to
+ * study mechano-reactive processes for polymers under flow conditions".
+ */
+#include "ra_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies, with a  */
+/* Weyl-sequence key schedule. The paper under study fixes only the moments  */
+/* of the random displacement (Eq. 1 text); the generator is our choice.     */
+/* ------------------------------------------------------------------------ */
+void rao_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;   /* round multipliers */
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;   /* key increments    */
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 32-bit word -> uniform in (0,1): the top 23 bits j give u = (j + 1/2) 2^-23,
+ * an odd multiple of 2^-24 that is exact in binary32 and binary64. */
+double rao_uniform(uint32_t x)
+{
+    return ((double)(x >> 9) + 0.5) * 0x1p-23;
+}
+
+/* Box-Muller: three standard normals from four uniforms (the second radius
+ * uses only its cosine branch). */
+void rao_normals(const uint32_t x[4], double xi[3])
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double u0 = rao_uniform(x[0]), u1 = rao_uniform(x[1]);
+    double u2 = rao_uniform(x[2]), u3 = rao_uniform(x[3]);
+    double r0 = sqrt(-2.0 * log(u0));
+    double r1 = sqrt(-2.0 * log(u2));
+    xi[0] = r0 * cos(two_pi * u1);
+    xi[1] = r0 * sin(two_pi * u1);
+    xi[2] = r1 * cos(two_pi * u3);
+}
+
+/* Counter layout: (step, bead-or-spring, replica, tag<<24 | group);
+ * key = (seed low 32 bits, seed high 32 bits). Each replica gets its own
+ * stream through the replica word, which plays the role of the paper's
+ * per-replica unique seed (RSF description, Sec. II). */
+void rao_noise(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
+               uint32_t tag, uint32_t group, double xi[3])
+{
+    uint32_t ctr[4] = { step, bead, replica, (tag << 24) | (group & 0xFFFFFFu) };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t x[4];
+    rao_philox4x32_10(ctr, key, x);
+    rao_normals(x, xi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spring law. Hookean: F = H Q. FENE: F = H Q / (1 - |Q|^2/Q0^2), with      */
+/* Q0^2 = b kT / H; s = |Q|^2/Q0^2 is clamped at 1 - delta (guard). The       */
+/* tension is the magnitude f = H g |Q| — Eq. (4) with zero rest length.     */
+/* Returns 1 when the guard clamped s.                                        */
+/* ------------------------------------------------------------------------ */
+static double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+static int spring_factor(int spring, double H, double b, double kT, const double Q[3],
+                         double* g, double* s_out)
+{
+    if (spring == RAO_HOOKEAN) { *g = 1.0; *s_out = 0.0; return 0; }
+    double q0sq = b * kT / H;
+    double s = dot3(Q, Q) / q0sq;
+    int clamped = 0;
+    if (s > 1.0 - RAO_FENE_DELTA) { s = 1.0 - RAO_FENE_DELTA; clamped = 1; }
+    *g = 1.0 / (1.0 - s);
+    *s_out = s;
+    return clamped;
+}
+
+int rao_spring(int spring, double H, double b, double kT, const double Q[3],
+               double F[3], double* g, double* f)
+{
+    double s;
+    int clamped = spring_factor(spring, H, b, kT, Q, g, &s);
+    for (int a = 0; a < 3; ++a) F[a] = H * (*g) * Q[a];
+    *f = H * (*g) * sqrt(dot3(Q, Q));
+    return clamped;
+}
+
+/* Homogeneous flow v = kappa . r. Shear follows the paper's convention
+ * v = gdot * z * x-hat (Sec. II); elongations are the standard forms. */
+void rao_flow_velocity(int flow, double rate, const double r[3], double v[3])
+{
+    v[0] = v[1] = v[2] = 0.0;
+    switch (flow) {
+    case RAO_UNIAXIAL: v[0] = rate * r[0]; v[1] = -0.5 * rate * r[1]; v[2] = -0.5 * rate * r[2]; break;
+    case RAO_PLANAR:   v[0] = rate * r[0]; v[1] = -rate * r[1]; v[2] = 0.0; break;
+    case RAO_SHEAR:    v[0] = rate * r[2]; break;
+    default: break;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Context                                                                    */
+/* ------------------------------------------------------------------------ */
+struct rao_ctx {
+    int32_t  n_groups;
+    rao_group* groups;
+    uint64_t seed;
+    int32_t  sample_every, max_windows, tsf, tangents;
+    int32_t* k_begin;      /* simulated replica range per group */
+    int32_t* k_end;
+    int64_t* pos_off;      /* offset (in doubles) of group g in pos[] */
+    int64_t* smp_off;      /* offset of group g in one window of samples */
+    int64_t* spr_off;      /* offset of group g in one window of the profile */
+    int64_t  n_pos, n_smp, n_spr;
+    double*  pos;          /* [g][k][i][3] */
+    double*  tan;          /* [p][g][k][i][3], p = rate, H, b */
+    double*  samples;      /* [w][smp] */
+    double*  tsf_samples;  /* [w][smp] */
+    double*  tsf_acc;      /* [smp] running window sums */
+    double*  dmu;          /* [w][spr][3] sum over replicas of df/dtheta */
+    int64_t* clamps;       /* per group */
+    int64_t  step;         /* steps taken since init */
+    int64_t  n_windows;
+    int      initialised;
+    char     err[256];
+};
+
+static int fail(rao_ctx* c, int code, const char* msg)
+{
+    if (c) snprintf(c->err, sizeof c->err, "%s", msg);
+    return code;
+}
+
+const char* ra_oracle_last_error(const rao_ctx* c) { return c ? c->err : "null context"; }
+
+void ra_oracle_destroy(rao_ctx* c)
+{
+    if (!c) return;
+    free(c->groups); free(c->k_begin); free(c->k_end);
+    free(c->pos_off); free(c->smp_off); free(c->spr_off);
+    free(c->pos); free(c->tan); free(c->samples); free(c->tsf_samples);
+    free(c->tsf_acc); free(c->dmu); free(c->clamps);
+    free(c);
+}
+
+static int layout(rao_ctx* c)
+{
+    int64_t p = 0, s = 0, q = 0;
+    for (int g = 0; g < c->n_groups; ++g) {
+        int64_t rs = c->k_end[g] - c->k_begin[g];
+        int64_t n = c->groups[g].n_beads;
+        c->pos_off[g] = p; p += rs * n * 3;
+        c->smp_off[g] = s; s += rs * (n - 1);
+        c->spr_off[g] = q; q += n - 1;
+    }
+    c->n_pos = p; c->n_smp = s; c->n_spr = q;
+    free(c->pos); free(c->tan); free(c->samples); free(c->tsf_samples);
+    free(c->tsf_acc); free(c->dmu);
+    c->pos = calloc((size_t)(p ? p : 1), sizeof(double));
+    c->tan = c->tangents ? calloc((size_t)(3 * p + 1), sizeof(double)) : NULL;
+    c->samples = calloc((size_t)(c->max_windows * s + 1), sizeof(double));
+    c->tsf_samples = c->tsf ? calloc((size_t)(c->max_windows * s + 1), sizeof(double)) : NULL;
+    c->tsf_acc = c->tsf ? calloc((size_t)(s + 1), sizeof(double)) : NULL;
+    c->dmu = c->tangents ? calloc((size_t)(c->max_windows * q * 3 + 1), sizeof(double)) : NULL;
+    if (!c->pos || !c->samples || (c->tangents && (!c->tan || !c->dmu)) ||
+        (c->tsf && (!c->tsf_samples || !c->tsf_acc)))
+        return fail(c, RAO_ENOMEM, "out of host memory");
+    c->initialised = 0;
+    return RAO_OK;
+}
+
+int ra_oracle_create(rao_ctx** out, const rao_group* groups, int32_t n_groups,
+                     uint64_t seed, int32_t sample_every, int32_t max_windows,
+                     int32_t tsf, int32_t tangents)
+{
+    if (!out) return RAO_EINVAL;
+    *out = NULL;
+    if (!groups || n_groups < 1 || sample_every < 1 || max_windows < 0) return RAO_EINVAL;
+    for (int g = 0; g < n_groups; ++g) {
+        const rao_group* d = &groups[g];
+        if (d->n_beads < 2 || d->n_replicas < 1 || !(d->dt > 0) || !(d->kT > 0) ||
+            !(d->zeta > 0) || !(d->H > 0) || d->spring < 0 || d->spring > 1 ||
+            d->flow < 0 || d->flow > 3 || d->stream_id > 0xFFFFFFu ||
+            (d->spring == RAO_FENE && !(d->b > 0)))
+            return RAO_EINVAL;
+    }
+    rao_ctx* c = calloc(1, sizeof *c);
+    if (!c) return RAO_ENOMEM;
+    c->n_groups = n_groups;
+    c->groups = malloc(sizeof(rao_group) * (size_t)n_groups);
+    c->k_begin = malloc(sizeof(int32_t) * (size_t)n_groups);
+    c->k_end = malloc(sizeof(int32_t) * (size_t)n_groups);
+    c->pos_off = malloc(sizeof(int64_t) * (size_t)n_groups);
+    c->smp_off = malloc(sizeof(int64_t) * (size_t)n_groups);
+    c->spr_off = malloc(sizeof(int64_t) * (size_t)n_groups);
+    c->clamps = calloc((size_t)n_groups, sizeof(int64_t));
+    if (!c->groups || !c->k_begin || !c->k_end || !c->pos_off || !c->smp_off ||
+        !c->spr_off || !c->clamps) { ra_oracle_destroy(c); return RAO_ENOMEM; }
+    memcpy(c->groups, groups, sizeof(rao_group) * (size_t)n_groups);
+    for (int g = 0; g < n_groups; ++g) { c->k_begin[g] = 0; c->k_end[g] = groups[g].n_replicas; }
+    c->seed = seed; c->sample_every = sample_every; c->max_windows = max_windows;
+    c->tsf = tsf ? 1 : 0; c->tangents = tangents ? 1 : 0;
+    int rc = layout(c);
+    if (rc != RAO_OK) { ra_oracle_destroy(c); return rc; }
+    *out = c;
+    return RAO_OK;
+}
+
+int ra_oracle_set_replicas(rao_ctx* c, int32_t g, int32_t k_begin, int32_t k_end)
+{
+    if (!c || g < 0 || g >= c->n_groups || k_begin < 0 || k_end <= k_begin ||
+        k_end > c->groups[g].n_replicas)
+        return fail(c, RAO_EINVAL, "bad replica range");
+    c->k_begin[g] = k_begin; c->k_end[g] = k_end;
+    return layout(c);
+}
+
+int64_t ra_oracle_n_windows(const rao_ctx* c) { return c ? c->n_windows : 0; }
+int64_t ra_oracle_total_springs(const rao_ctx* c) { return c ? c->n_spr : 0; }
+int64_t ra_oracle_clamps(const rao_ctx* c, int32_t g)
+{
+    return (c && g >= 0 && g < c->n_groups) ? c->clamps[g] : -1;
+}
+
+/* RSF clone (Sec. II): every replica starts from the parent conformation. */
+int ra_oracle_init_chains(rao_ctx* c, const double* parent_xyz)
+{
+    if (!c || !parent_xyz) return fail(c, RAO_EINVAL, "null argument");
+    int64_t par = 0;
+    for (int g = 0; g < c->n_groups; ++g) {
+        const rao_group* d = &c->groups[g];
+        int n = d->n_beads;
+        const double* p = parent_xyz + par;
+        if (d->spring == RAO_FENE) {
+            double q0sq = d->b * d->kT / d->H;
+            for (int j = 0; j + 1 < n; ++j) {
+                double Q[3] = { p[3 * (j + 1)] - p[3 * j], p[3 * (j + 1) + 1] - p[3 * j + 1],
+                                p[3 * (j + 1) + 2] - p[3 * j + 2] };
+                if (!(dot3(Q, Q) < q0sq))
+                    return fail(c, RAO_EINVAL, "parent FENE bond at or beyond full extension");
+            }
+        }
+        for (int i = 0; i < 3 * n; ++i)
+            if (!isfinite(p[i])) return fail(c, RAO_EINVAL, "non-finite parent coordinate");
+        int rs = c->k_end[g] - c->k_begin[g];
+        for (int k = 0; k < rs; ++k)
+            memcpy(c->pos + c->pos_off[g] + (int64_t)k * n * 3, p, sizeof(double) * 3 * (size_t)n);
+        par += 3 * n;
+        c->clamps[g] = 0;
+    }
+    if (c->tan) memset(c->tan, 0, sizeof(double) * (size_t)(3 * c->n_pos));
+    if (c->tsf_acc) memset(c->tsf_acc, 0, sizeof(double) * (size_t)c->n_smp);
+    c->step = 0; c->n_windows = 0; c->initialised = 1;
+    return RAO_OK;
+}
+
+/* Pathwise derivatives of the spring force for the forward-mode tangents.
+ * dF = (dF/dQ) dQ + dF/dtheta_p, p in {rate, H, b}. */
+static void spring_tangent(int spring, double H, double b, double kT, const double Q[3],
+                           double g, double s, int clamped, int p, const double dQ[3],
+                           double dF[3])
+{
+    int smooth = (spring == RAO_FENE) && !clamped;   /* dg/ds = g^2 only if unclamped */
+    double q0sq = (spring == RAO_FENE) ? b * kT / H : 1.0;
+    double qdq = dot3(Q, dQ);
+    for (int a = 0; a < 3; ++a) {
+        double v = H * g * dQ[a];
+        if (smooth) v += H * 2.0 * g * g * qdq / q0sq * Q[a];
+        if (p == 1) v += smooth ? g * Q[a] * (1.0 + g * s) : g * Q[a];
+        if (p == 2 && smooth) v += -H * g * g * (s / b) * Q[a];
+        dF[a] = v;
+    }
+}
+
+static double tension_tangent(int spring, double H, double b, double g, double s,
+                              int clamped, int p, const double Q[3], const double dQ[3])
+{
+    int smooth = (spring == RAO_FENE) && !clamped;
+    double q = sqrt(dot3(Q, Q));
+    double df = 0.0;
+    if (q > 0.0) df = H * (g + (smooth ? 2.0 * g * g * s : 0.0)) * dot3(Q, dQ) / q;
+    if (p == 1) df += smooth ? g * q * (1.0 + g * s) : g * q;
+    if (p == 2 && smooth) df += -H * g * g * (s / b) * q;
+    return df;
+}
+
+/* One Euler-Maruyama step of Eq. (1) with the free-draining tensor Eq. (2)
+ * for replica k of group g: all beads advance together from the step-n
+ * state; the random displacement has covariance 2 (kT/zeta) dt I. */
+static void em_step_replica(rao_ctx* c, int g, int kk, uint32_t n,
+                            double* Fbuf, double* Fnet, double* dF, double* dFnet)
+{
+    const rao_group* d = &c->groups[g];
+    const int N = d->n_beads;
+    const int k = c->k_begin[g] + kk;
+    const int rs = c->k_end[g] - c->k_begin[g];
+    double* r = c->pos + c->pos_off[g] + (int64_t)kk * N * 3;
+    const double sigma = d->noise_scale * sqrt(2.0 * d->kT * d->dt / d->zeta);
+
+    /* spring forces from the step-n positions */
+    for (int j = 0; j + 1 < N; ++j) {
+        double Q[3], F[3], gj, f, s;
+        for (int a = 0; a < 3; ++a) Q[a] = r[3 * (j + 1) + a] - r[3 * j + a];
+        int clamped = rao_spring(d->spring, d->H, d->b, d->kT, Q, F, &gj, &f);
+        spring_factor(d->spring, d->H, d->b, d->kT, Q, &gj, &s);
+        c->clamps[g] += clamped;
+        for (int a = 0; a < 3; ++a) Fbuf[3 * j + a] = F[a];
+        if (c->tangents) {
+            for (int p = 0; p < 3; ++p) {
+                const double* t = c->tan + (int64_t)p * c->n_pos + c->pos_off[g] + (int64_t)kk * N * 3;
+                double dQ[3];
+                for (int a = 0; a < 3; ++a) dQ[a] = t[3 * (j + 1) + a] - t[3 * j + a];
+                spring_tangent(d->spring, d->H, d->b, d->kT, Q, gj, s, clamped, p, dQ,
+                               dF + (int64_t)p * 3 * N + 3 * j);
+            }
+        }
+    }
+    /* net spring force on bead i: pulled forward by spring i, back by spring i-1 */
+    for (int i = 0; i < N; ++i)
+        for (int a = 0; a < 3; ++a) {
+            double v = 0.0;
+            if (i <= N - 2) v += Fbuf[3 * i + a];
+            if (i >= 1) v -= Fbuf[3 * (i - 1) + a];
+            Fnet[3 * i + a] = v;
+            if (c->tangents)
+                for (int p = 0; p < 3; ++p) {
+                    double w = 0.0;
+                    if (i <= N - 2) w += dF[(int64_t)p * 3 * N + 3 * i + a];
+                    if (i >= 1) w -= dF[(int64_t)p * 3 * N + 3 * (i - 1) + a];
+                    dFnet[(int64_t)p * 3 * N + 3 * i + a] = w;
+                }
+        }
+    /* position update */
+    for (int i = 0; i < N; ++i) {
+        double xi[3], v[3];
+        rao_noise(c->seed, n, (uint32_t)i, (uint32_t)k, RAO_TAG_REPLICA, d->stream_id, xi);
+        rao_flow_velocity(d->flow, d->rate, r + 3 * i, v);
+        if (c->tangents) {
+            for (int p = 0; p < 3; ++p) {
+                double* t = c->tan + (int64_t)p * c->n_pos + c->pos_off[g] + (int64_t)kk * N * 3;
+                double dv[3];
+                rao_flow_velocity(d->flow, d->rate, t + 3 * i, dv);
+                if (p == 0) {   /* d(kappa . r)/d rate = (kappa/rate) . r */
+                    double pat[3];
+                    rao_flow_velocity(d->flow, 1.0, r + 3 * i, pat);
+                    for (int a = 0; a < 3; ++a) dv[a] += pat[a];
+                }
+                for (int a = 0; a < 3; ++a)
+                    t[3 * i + a] += d->dt * (dv[a] + dFnet[(int64_t)p * 3 * N + 3 * i + a] / d->zeta);
+            }
+        }
+        for (int a = 0; a < 3; ++a)
+            Fnet[3 * i + a] = d->dt * (v[a] + Fnet[3 * i + a] / d->zeta) + sigma * xi[a];
+    }
+    for (int i = 0; i < 3 * N; ++i) r[i] += Fnet[i];
+    (void)rs;
+}
+
+/* Tension of every spring of replica kk (after the step), for RSF/TSF. */
+static void sample_replica(rao_ctx* c, int g, int kk, int window_end, int64_t w)
+{
+    const rao_group* d = &c->groups[g];
+    const int N = d->n_beads;
+    const int rs = c->k_end[g] - c->k_begin[g];
+    const double* r = c->pos + c->pos_off[g] + (int64_t)kk * N * 3;
+    for (int j = 0; j + 1 < N; ++j) {
+        double Q[3], F[3], gj, f, s;
+        for (int a = 0; a < 3; ++a) Q[a] = r[3 * (j + 1) + a] - r[3 * j + a];
+        int clamped = rao_spring(d->spring, d->H, d->b, d->kT, Q, F, &gj, &f);
+        spring_factor(d->spring, d->H, d->b, d->kT, Q, &gj, &s);
+        int64_t idx = c->smp_off[g] + (int64_t)kk * (N - 1) + j;
+        if (c->tsf) c->tsf_acc[idx] += f;
+        if (!window_end) continue;
+        c->samples[w * c->n_smp + idx] = f;
+        if (c->tsf) {
+            c->tsf_samples[w * c->n_smp + idx] = c->tsf_acc[idx] / (double)c->sample_every;
+            c->tsf_acc[idx] = 0.0;
+        }
+        if (c->tangents) {
+            for (int p = 0; p < 3; ++p) {
+                const double* t = c->tan + (int64_t)p * c->n_pos + c->pos_off[g] + (int64_t)kk * N * 3;
+                double dQ[3];
+                for (int a = 0; a < 3; ++a) dQ[a] = t[3 * (j + 1) + a] - t[3 * j + a];
+                c->dmu[(w * c->n_spr + c->spr_off[g] + j) * 3 + p] +=
+                    tension_tangent(d->spring, d->H, d->b, gj, s, clamped, p, Q, dQ) / (double)rs;
+            }
+        }
+    }
+}
+
+int ra_oracle_step(rao_ctx* c, int64_t n_steps)
+{
+    if (!c) return RAO_EINVAL;
+    if (!c->initialised) return fail(c, RAO_ESTATE, "step before init_chains");
+    if (n_steps < 0) return fail(c, RAO_EINVAL, "negative step count");
+    int64_t end = c->step + n_steps;
+    if (end > 0xFFFFFFFFll) return fail(c, RAO_EINVAL, "step counter exceeds 32 bits");
+    if (end / c->sample_every > c->max_windows) return fail(c, RAO_EINVAL, "window capacity exceeded");
+    int nmax = 2;
+    for (int g = 0; g < c->n_groups; ++g) if (c->groups[g].n_beads > nmax) nmax = c->groups[g].n_beads;
+    double* Fbuf = malloc(sizeof(double) * 3 * (size_t)nmax);
+    double* Fnet = malloc(sizeof(double) * 3 * (size_t)nmax);
+    double* dF = malloc(sizeof(double) * 9 * (size_t)nmax);
+    double* dFnet = malloc(sizeof(double) * 9 * (size_t)nmax);
+    if (!Fbuf || !Fnet || !dF || !dFnet) {
+        free(Fbuf); free(Fnet); free(dF); free(dFnet);
+        return fail(c, RAO_ENOMEM, "out of host memory");
+    }
+    for (; c->step < end; ++c->step) {
+        uint32_t n = (uint32_t)c->step;
+        int window_end = ((c->step + 1) % c->sample_every) == 0;
+        int64_t w = (c->step + 1) / c->sample_every - 1;
+        for (int g = 0; g < c->n_groups; ++g) {
+            int rs = c->k_end[g] - c->k_begin[g];
+            for (int kk = 0; kk < rs; ++kk) {
+                em_step_replica(c, g, kk, n, Fbuf, Fnet, dF, dFnet);
+                if (c->tsf || window_end) sample_replica(c, g, kk, window_end, w);
+            }
+        }
+        if (window_end) c->n_windows = w + 1;
+    }
+    free(Fbuf); free(Fnet); free(dF); free(dFnet);
+    return RAO_OK;
+}
+
+/* RSF estimate (Sec. II): replica mean of the sampled tension and the
+ * replica standard deviation (denominator R-1), two-pass. */
+static void replica_stats(const rao_ctx* c, const double* smp, double* mean, double* std)
+{
+    for (int64_t w = 0; w < c->n_windows; ++w)
+        for (int g = 0; g < c->n_groups; ++g) {
+            int N = c->groups[g].n_beads;
+            int rs = c->k_end[g] - c->k_begin[g];
+            for (int j = 0; j + 1 < N; ++j) {
+                double sum = 0.0;
+                for (int kk = 0; kk < rs; ++kk)
+                    sum += smp[w * c->n_smp + c->smp_off[g] + (int64_t)kk * (N - 1) + j];
+                double mu = sum / rs;
+                double ss = 0.0;
+                for (int kk = 0; kk < rs; ++kk) {
+                    double e = smp[w * c->n_smp + c->smp_off[g] + (int64_t)kk * (N - 1) + j] - mu;
+                    ss += e * e;
+                }
+                int64_t o = w * c->n_spr + c->spr_off[g] + j;
+                if (mean) mean[o] = mu;
+                if (std) std[o] = rs > 1 ? sqrt(ss / (rs - 1)) : 0.0;
+            }
+        }
+}
+
+int ra_oracle_average_forces(rao_ctx* c, double* mean, double* std,
+                             double* tsf_mean, double* tsf_std)
+{
+    if (!c) return RAO_EINVAL;
+    replica_stats(c, c->samples, mean, std);
+    if (tsf_mean || tsf_std) {
+        if (!c->tsf) return fail(c, RAO_ESTATE, "TSF not enabled");
+        replica_stats(c, c->tsf_samples, tsf_mean, tsf_std);
+    }
+    return RAO_OK;
+}
+
+/* Bell-type rate law (Sec. III): k = k0 exp(x_dagger f / kT) per spring, the
+ * summed rate per chain, and optionally one event draw per spring per window
+ * with probability 1 - exp(-k * window length). */
+int ra_oracle_bell_rates(rao_ctx* c, const double* mean, int64_t n_windows,
+                         double k0, double x_dagger, double* rates,
+                         double* rate_sum, uint8_t* events)
+{
+    if (!c || !mean || n_windows < 0) return RAO_EINVAL;
+    uint32_t key[2] = { (uint32_t)c->seed, (uint32_t)(c->seed >> 32) };
+    for (int64_t w = 0; w < n_windows; ++w)
+        for (int g = 0; g < c->n_groups; ++g) {
+            const rao_group* d = &c->groups[g];
+            double sum = 0.0;
+            for (int j = 0; j + 1 < d->n_beads; ++j) {
+                int64_t o = w * c->n_spr + c->spr_off[g] + j;
+                double k = k0 * exp(x_dagger * mean[o] / d->kT);
+                if (rates) rates[o] = k;
+                sum += k;
+                if (events) {
+                    uint32_t ctr[4] = { (uint32_t)w, (uint32_t)j, 0u,
+                                        ((uint32_t)RAO_TAG_EVENT << 24) | d->stream_id };
+                    uint32_t x[4];
+                    rao_philox4x32_10(ctr, key, x);
+                    double p = -expm1(-k * c->sample_every * d->dt);
+                    events[o] = rao_uniform(x[0]) < p ? 1 : 0;
+                }
+            }
+            if (rate_sum) rate_sum[w * c->n_groups + g] = sum;
+        }
+    return RAO_OK;
+}
+
+int ra_oracle_backward(rao_ctx* c, const double* grad_mean, const double* grad_rates,
+                       double k0, double x_dagger, double* grad_params)
+{
+    if (!c || !grad_params) return RAO_EINVAL;
+    if (!c->tangents) return fail(c, RAO_ESTATE, "tangents not enabled");
+    double* mean = malloc(sizeof(double) * (size_t)(c->n_windows * c->n_spr + 1));
+    if (!mean) return fail(c, RAO_ENOMEM, "out of host memory");
+    replica_stats(c, c->samples, mean, NULL);
+    for (int g = 0; g < c->n_groups; ++g) {
+        const rao_group* d = &c->groups[g];
+        double acc[3] = { 0.0, 0.0, 0.0 };
+        for (int64_t w = 0; w < c->n_windows; ++w)
+            for (int j = 0; j + 1 < d->n_beads; ++j) {
+                int64_t o = w * c->n_spr + c->spr_off[g] + j;
+                double lam = grad_mean ? grad_mean[o] : 0.0;
+                if (grad_rates) {
+                    double k = k0 * exp(x_dagger * mean[o] / d->kT);
+                    lam += grad_rates[o] * k * x_dagger / d->kT;
+                }
+                for (int p = 0; p < 3; ++p) acc[p] += lam * c->dmu[o * 3 + p];
+            }
+        for (int p = 0; p < 3; ++p) grad_params[3 * g + p] = acc[p];
+    }
+    free(mean);
+    return RAO_OK;
+}
+
+int ra_oracle_get_samples(const rao_ctx* c, double* out, double* tsf_out)
+{
+    if (!c) return RAO_EINVAL;
+    if (out) memcpy(out, c->samples, sizeof(double) * (size_t)(c->n_windows * c->n_smp));
+    if (tsf_out) {
+        if (!c->tsf) return RAO_ESTATE;
+        memcpy(tsf_out, c->tsf_samples, sizeof(double) * (size_t)(c->n_windows * c->n_smp));
+    }
+    return RAO_OK;
+}
+
+int ra_oracle_get_positions(const rao_ctx* c, double* out)
+{
+    if (!c || !out) return RAO_EINVAL;
+    memcpy(out, c->pos, sizeof(double) * (size_t)c->n_pos);
+    return RAO_OK;
+}

@@ -1,0 +1,103 @@
+/*
+ * ra_oracle.h — FP64 CPU oracle for replica-averaged Brownian dynamics.
+ *
+ * TEST INFRASTRUCTURE ONLY. This header and ra_oracle.c form a plain, slow,
+ * obviously-correct reference of what the GPU library computes. Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it. The product path never links, calls or falls back to it, and it shares
+ * no code, header, constant table or helper with the HIP library.
+ *
+ * Model (Kania, Nguyen, Oztekin, Webb, "Replica-Averaging", Sec. II):
+ *   - bead-spring chain of N beads, spring j joins beads j and j+1;
+ *   - Brownian-dynamics update Eq. (1) with only the self term Eq. (2) of the
+ *     diffusion tensor (free-draining): D_ii = kT/zeta * I, D_ij = 0 (i != j);
+ *   - random displacement with zero mean and covariance 2*D*dt (Eq. 1 text),
+ *     Gaussian, generated from a counter-based Philox4x32-10 stream;
+ *   - homogeneous flow v = kappa . r (Sec. II; shear v = gdot * z * x-hat);
+ *   - spring tension sampled per spring (Eq. 4, generalised to zero-rest-
+ *     length Hookean and FENE springs), averaged over replicas (RSF, Sec. II)
+ *     and over time within a window (TSF, Sec. II);
+ *   - Bell-type rate k = k0 * exp(x_dagger * f / kT) (Sec. III, vWF rate law).
+ *
+ * All arithmetic is IEEE double; the only library calls are libm's
+ * log/sqrt/cos/sin/exp/expm1.
+ */
+#ifndef RA_ORACLE_H
+#define RA_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { RAO_HOOKEAN = 0, RAO_FENE = 1 };
+enum { RAO_QUIESCENT = 0, RAO_UNIAXIAL = 1, RAO_PLANAR = 2, RAO_SHEAR = 3 };
+enum { RAO_OK = 0, RAO_EINVAL = -1, RAO_ENOMEM = -2, RAO_ESTATE = -5 };
+
+/* Philox counter tag (top 8 bits of the fourth counter word). */
+enum { RAO_TAG_REPLICA = 0, RAO_TAG_PARENT = 1, RAO_TAG_EVENT = 2 };
+
+typedef struct {
+    int32_t  n_beads;      /* N >= 2 */
+    int32_t  n_replicas;   /* R >= 1 */
+    int32_t  spring;       /* RAO_HOOKEAN | RAO_FENE */
+    int32_t  flow;         /* RAO_QUIESCENT | RAO_UNIAXIAL | RAO_PLANAR | RAO_SHEAR */
+    double   H;            /* spring constant */
+    double   b;            /* FENE extensibility; Q0^2 = b*kT/H */
+    double   rate;         /* strain rate (elongation) or shear rate */
+    double   kT, zeta, dt;
+    double   noise_scale;  /* 1 = physical noise, 0 = deterministic */
+    uint32_t stream_id;    /* group id in the Philox counter, < 2^24 */
+    uint32_t pad_;
+} rao_group;
+
+/* FENE guard: s = |Q|^2/Q0^2 is clamped at 1 - RAO_FENE_DELTA. */
+#define RAO_FENE_DELTA 1.0e-3
+
+/* ---- primitives ------------------------------------------------------- */
+void   rao_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double rao_uniform(uint32_t x);
+void   rao_normals(const uint32_t x[4], double xi[3]);
+void   rao_noise(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
+                 uint32_t tag, uint32_t group, double xi[3]);
+/* spring force F (on bead j, toward bead j+1), factor g, tension f; returns 1 if clamped */
+int    rao_spring(int spring, double H, double b, double kT, const double Q[3],
+                  double F[3], double* g, double* f);
+void   rao_flow_velocity(int flow, double rate, const double r[3], double v[3]);
+
+/* ---- context API mirroring the library's calls ------------------------ */
+typedef struct rao_ctx rao_ctx;
+
+int  ra_oracle_create(rao_ctx** out, const rao_group* groups, int32_t n_groups,
+                      uint64_t seed, int32_t sample_every, int32_t max_windows,
+                      int32_t tsf, int32_t tangents);
+/* simulate only replicas [k_begin, k_end) of group g (counters keep global k) */
+int  ra_oracle_set_replicas(rao_ctx* c, int32_t g, int32_t k_begin, int32_t k_end);
+/* clone: parent_xyz holds N_g*3 doubles per group, concatenated in group order */
+int  ra_oracle_init_chains(rao_ctx* c, const double* parent_xyz);
+int  ra_oracle_step(rao_ctx* c, int64_t n_steps);
+int64_t ra_oracle_n_windows(const rao_ctx* c);
+int64_t ra_oracle_total_springs(const rao_ctx* c);
+/* [W][sum_g (N_g-1)] FP64; std with R-1 (0 if R == 1); any pointer may be NULL */
+int  ra_oracle_average_forces(rao_ctx* c, double* mean, double* std,
+                              double* tsf_mean, double* tsf_std);
+/* rates[W][S], rate_sum[W][G]; events[W][S] (may be NULL) */
+int  ra_oracle_bell_rates(rao_ctx* c, const double* mean, int64_t n_windows,
+                          double k0, double x_dagger, double* rates,
+                          double* rate_sum, uint8_t* events);
+/* forward-mode pathwise gradient of J = sum gm*mean + sum gr*rates w.r.t.
+ * (rate, H, b) per group; needs tangents=1 at create; grad_rates may be NULL */
+int  ra_oracle_backward(rao_ctx* c, const double* grad_mean, const double* grad_rates,
+                        double k0, double x_dagger, double* grad_params);
+/* per-replica tension samples [W][sum_g Rsub_g*(N_g-1)] and TSF values */
+int  ra_oracle_get_samples(const rao_ctx* c, double* out, double* tsf_out);
+/* bead positions [sum_g Rsub_g*N_g*3] */
+int  ra_oracle_get_positions(const rao_ctx* c, double* out);
+int64_t ra_oracle_clamps(const rao_ctx* c, int32_t g);
+const char* ra_oracle_last_error(const rao_ctx* c);
+void ra_oracle_destroy(rao_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,161 @@
+"""Pins for the oracle's Bell-type rates (Sec. III rate law and the worked
+example in the supplementary vWF section) and for its pathwise gradients
+(forward-mode tangents) against central finite differences with common random
+numbers and against a bond-space closed form."""
+import numpy as np
+import pytest
+
+import closed_forms as cf
+from oracle import ora
+from paper_2206_05851_amd import workloads as wl
+
+
+def g(N, R, dt, **kw):
+    return wl.group(N, R, dt, **kw)
+
+
+def _ctx_with_springs(n_springs, kT=1.0):
+    o = ora.Oracle([g(n_springs + 1, 1, 1e-3, kT=kT)], seed=0, sample_every=1, max_windows=1)
+    return o
+
+
+def test_bell_worked_example_mftu():
+    # vWF: 25 A2 domains, k0 = 7e-4 /s, f_u = 1.1 pN, mean force 0.28 pN.
+    # Mean first passage time = 1/sum_j k_j = 1/[25 k0 exp(0.28/1.1)].
+    # The formula evaluates to 44.30 s; the printed "49.8 s" does not follow
+    # from it (a force of about 0.151 pN would be needed), so the formula is pinned.
+    o = _ctx_with_springs(25)
+    mean = np.full((1, 25), 0.28)
+    rates, rsum = o.bell_rates(mean, k0=7e-4, x_dagger=1.0 / 1.1)
+    mftu = 1.0 / rsum[0, 0]
+    assert np.isclose(mftu, 1.0 / (25 * 7e-4 * np.exp(0.28 / 1.1)), rtol=1e-14)
+    assert abs(mftu - 44.30) < 0.01
+    # zero force: 1/(25 k0) = 57.14 s, the "about 50 s" order of the main text
+    _, r0 = o.bell_rates(np.zeros((1, 25)), k0=7e-4, x_dagger=1.0 / 1.1)
+    assert abs(1.0 / r0[0, 0] - 57.142857) < 1e-5
+
+
+def test_bell_rate_law_and_jensen():
+    kT = 1.7
+    o = _ctx_with_springs(40, kT=kT)
+    rng = np.random.default_rng(0)
+    f = rng.normal(3.0, 2.0, size=(1, 40))
+    rates, rsum = o.bell_rates(f, k0=1e-6, x_dagger=0.1)
+    assert np.allclose(np.log(rates / 1e-6), 0.1 * f / kT, rtol=1e-13)
+    assert np.isclose(rsum[0, 0], rates.sum(), rtol=1e-14)
+    # exp is convex: mean of k(f) >= k(mean f)
+    _, rbar = o.bell_rates(np.full((1, 40), f.mean()), k0=1e-6, x_dagger=0.1)
+    assert rsum[0, 0] >= rbar[0, 0]
+    # lognormal identity for Gaussian f: E k = k0 exp(a mu + a^2 s^2 / 2)
+    big = _ctx_with_springs(20000, kT=1.0)
+    fs = rng.normal(1.0, 0.5, size=(1, 20000))
+    _, rs = big.bell_rates(fs, k0=1.0, x_dagger=2.0)
+    expect = np.exp(2.0 * 1.0 + 4.0 * 0.25 / 2)
+    assert abs(rs[0, 0] / 20000 - expect) < 0.05 * expect
+
+
+def test_bell_event_frequency():
+    # one uniform per (window, spring): P(event) = 1 - exp(-k * S * dt)
+    N, S, dt, W = 201, 10, 0.1, 50
+    o = ora.Oracle([g(N, 1, dt)], seed=5, sample_every=S, max_windows=W)
+    mean = np.full((W, N - 1), 3.0)
+    k = np.exp(0.1 * 3.0) * 0.5
+    rates, _, ev = o.bell_rates(mean, k0=0.5, x_dagger=0.1, events=True)
+    p = -np.expm1(-k * S * dt)
+    n = ev.size
+    assert abs(ev.mean() - p) < 4.5 * np.sqrt(p * (1 - p) / n)
+    # events use the tag-2 Philox stream: same draw for the same (window, spring)
+    _, _, ev2 = o.bell_rates(mean, k0=0.5, x_dagger=0.1, events=True)
+    assert np.array_equal(ev, ev2)
+
+
+def _objective(desc, parent, seed, steps, S, w_mean, w_rate, k0, xd):
+    o = ora.Oracle([desc], seed=seed, sample_every=S, max_windows=steps // S)
+    o.init_chains([parent])
+    o.step(steps)
+    mean, _ = o.average_forces()
+    rates, _ = o.bell_rates(mean, k0, xd)
+    return float((w_mean * mean).sum() + (w_rate * rates).sum())
+
+
+@pytest.mark.parametrize("spring,flow", [(ora.FENE, ora.UNIAXIAL), (ora.FENE, ora.SHEAR),
+                                         (ora.HOOKEAN, ora.PLANAR)])
+def test_forward_tangent_matches_central_fd_with_crn(spring, flow):
+    N, R, dt, steps, S = 8, 12, 1e-3, 300, 50
+    b = 12.0
+    base = g(N, R, dt, spring=spring, H=1.3, b=b if spring == ora.FENE else 0.0, flow=flow,
+             rate=0.9)
+    parent = wl.equilibrium_parent(N, spring, 1.3, b, seed=4)
+    W = steps // S
+    rng = np.random.default_rng(1)
+    wm = rng.normal(size=(W, N - 1))
+    wr = rng.normal(size=(W, N - 1)) * 1e5
+    k0, xd = 1e-6, 0.1
+    o = ora.Oracle([base], seed=7, sample_every=S, max_windows=W, tangents=True)
+    o.init_chains([parent])
+    o.step(steps)
+    grad = o.backward(wm, wr, k0, xd)[0]
+    h = 1e-4
+    for p, key in enumerate(("rate", "H", "b")):
+        if key == "b" and spring == ora.HOOKEAN:
+            assert grad[p] == 0.0
+            continue
+        up, dn = dict(base), dict(base)
+        up[key] *= 1 + h
+        dn[key] *= 1 - h
+        fd = (_objective(up, parent, 7, steps, S, wm, wr, k0, xd) -
+              _objective(dn, parent, 7, steps, S, wm, wr, k0, xd)) / (2 * h * base[key])
+        assert np.isclose(grad[p], fd, rtol=2e-6, atol=1e-9 * abs(fd) + 1e-12), (key, grad[p], fd)
+
+
+def test_hookean_noise_off_gradient_closed_form():
+    # J = sum_w sum_j c_wj H |Q_j(n_w)| with Q(n) = M(rate, H)^n Q0 exactly;
+    # derivatives of the matrix power evaluated in bond space.
+    N, dt, S, W = 6, 2e-3, 40, 3
+    H, rate, flow = 1.4, 0.6, ora.UNIAXIAL
+    parent = wl.equilibrium_parent(N, seed=8)
+    Q0 = cf.bonds_of(parent)
+    c = np.random.default_rng(2).normal(size=(W, N - 1))
+
+    def J(rate_, H_):
+        M, _ = cf.em_matrices(N, H_, 1.0, 1.0, dt, flow, rate_)
+        tot = 0.0
+        for w in range(W):
+            Q = (np.linalg.matrix_power(M, S * (w + 1)) @ Q0).reshape(3, N - 1)
+            tot += (c[w] * H_ * np.linalg.norm(Q, axis=0)).sum()
+        return tot
+
+    def dJ(which):
+        # exact derivative via d(M^n) = sum_k M^k dM M^(n-1-k)
+        M, _ = cf.em_matrices(N, H, 1.0, 1.0, dt, flow, rate)
+        if which == "rate":
+            dM = dt * np.kron(cf.flow_matrix(flow, 1.0), np.eye(N - 1))
+        else:
+            dM = -(dt / 1.0) * np.kron(np.eye(3), cf.rouse_B(N - 1))
+        tot = 0.0
+        for w in range(W):
+            n = S * (w + 1)
+            pw = [np.eye(len(Q0))]
+            for _ in range(n):
+                pw.append(M @ pw[-1])
+            dMn = sum(pw[k] @ dM @ pw[n - 1 - k] for k in range(n))
+            Q = (pw[n] @ Q0).reshape(3, N - 1)
+            dQ = (dMn @ Q0).reshape(3, N - 1)
+            q = np.linalg.norm(Q, axis=0)
+            df = H * (Q * dQ).sum(axis=0) / q
+            if which == "H":
+                df += q
+            tot += (c[w] * df).sum()
+        return tot
+
+    o = ora.Oracle([g(N, 1, dt, H=H, flow=flow, rate=rate, noise_scale=0.0)], seed=0,
+                   sample_every=S, max_windows=W, tangents=True)
+    o.init_chains([parent])
+    o.step(S * W)
+    grad = o.backward(c)[0]
+    assert np.isclose(grad[0], dJ("rate"), rtol=1e-9)
+    assert np.isclose(grad[1], dJ("H"), rtol=1e-9)
+    assert grad[2] == 0.0
+    # and the matrix-power derivative itself against finite differences of J
+    e = 1e-6
+    assert np.isclose(dJ("rate"), (J(rate + e, H) - J(rate - e, H)) / (2 * e), rtol=1e-6)
