@@ -1,0 +1,181 @@
+/*
+ * ra.h — C ABI of the MI355X (gfx950) replica-averaged Brownian-dynamics library.
+ *
+ * Method (Kania, Nguyen, Oztekin, Webb, "Replica-Averaging: An algorithm to
+ * study mechano-reactive processes for polymers under flow conditions"):
+ *   - a parent bead-spring chain is halted and cloned into N_R replicas,
+ *     each driven by its own random stream (RSF description, Sec. II);
+ *   - every replica is advanced by the Brownian-dynamics update of Eq. (1),
+ *     here with only the self term of the diffusion tensor, Eq. (2)
+ *     (free-draining), under a homogeneous flow v = kappa . r;
+ *   - after an evolution time S the tension of each spring (Eq. (4) with a
+ *     zero-rest-length Hookean or FENE spring) is sampled once per replica
+ *     and averaged over replicas (RSF); optionally it is also averaged over
+ *     the steps of the window (TSF, Sec. II);
+ *   - the averaged tension feeds a Bell-type rate k = k0 exp(x_dagger f/kT)
+ *     (Sec. III, the A2-domain unfolding rate law).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers (hipMalloc'd or torch CUDA tensors)
+ *     unless marked "host". The caller owns every argument buffer; the
+ *     library owns the context, chain state, samples and checkpoints.
+ *   - Work is enqueued on the stream given to ra_create and is asynchronous:
+ *     outputs are valid after that stream is synchronised. Calls on one
+ *     context must not overlap from several host threads.
+ *   - Errors are returned as ra_status codes, never by exit or exception;
+ *     ra_last_error returns a text for the last failure on a context.
+ *     Errors found on the device (an invalid parent chain, a non-finite
+ *     tension) are latched in the context and reported by ra_sync_status.
+ *   - Layout of a profile: [window][spring], springs of all groups
+ *     concatenated in group order, sum_g (N_g - 1) per window, FP64.
+ *   - Spring j of a chain joins beads j and j+1 (0-based), N-1 springs.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key =
+ *     (seed low, seed high) and counter = (step, bead, replica,
+ *     tag<<24 | stream_id); tag 0 drives replica noise, tag 2 Bell events.
+ *     A group's results depend only on its descriptor, its parent, the seed
+ *     and the step count: never on which other groups share the context.
+ */
+#ifndef RA_H
+#define RA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RA_API __attribute__((visibility("default")))
+
+typedef struct ra_ctx ra_ctx;
+
+typedef enum {
+    RA_OK = 0,
+    RA_EINVAL = -1,     /* invalid argument or descriptor; nothing changed */
+    RA_ENOMEM = -2,     /* device or host allocation failed */
+    RA_EDEVICE = -3,    /* a HIP call failed (text in ra_last_error) */
+    RA_EUNSTABLE = -4,  /* a sampled tension was NaN/Inf */
+    RA_ESTATE = -5      /* call out of order (e.g. ra_step before ra_init_chains) */
+} ra_status;
+
+typedef enum { RA_HOOKEAN = 0, RA_FENE = 1 } ra_spring;
+typedef enum { RA_QUIESCENT = 0, RA_UNIAXIAL = 1, RA_PLANAR = 2, RA_SHEAR = 3 } ra_flow;
+
+/* One group = one parent chain and its replicas (host struct, 80 bytes).
+ * Spring force on bead j from spring j: F = H g Q, Q = r_{j+1} - r_j,
+ * g = 1 (Hookean) or 1/(1 - min(|Q|^2/Q0^2, 1 - 1e-3)) (FENE, Q0^2 = b kT/H).
+ * Flow: uniaxial kappa = rate*diag(1,-1/2,-1/2); planar rate*diag(1,-1,0);
+ * shear v_x = rate * z (the paper's convention, Sec. II). */
+typedef struct {
+    int32_t  n_beads;      /* N, 2 <= N <= 1024 (FP64: N <= 256) */
+    int32_t  n_replicas;   /* R >= 1 */
+    int32_t  spring;       /* ra_spring */
+    int32_t  flow;         /* ra_flow */
+    double   H;            /* spring constant > 0 */
+    double   b;            /* FENE extensibility > 0 (ignored for Hookean) */
+    double   rate;         /* strain rate or shear rate (not a Weissenberg number) */
+    double   kT;           /* thermal energy > 0 */
+    double   zeta;         /* bead friction > 0 */
+    double   dt;           /* time step > 0 */
+    double   noise_scale;  /* 1 = physical noise; 0 = deterministic */
+    uint32_t stream_id;    /* group id in the random counter, < 2^24 */
+    uint32_t pad_;
+} ra_chain_desc;
+
+/* Run options (host struct, 48 bytes). */
+typedef struct {
+    uint64_t seed;              /* Philox key */
+    int32_t  precision;         /* 32: FP32 state, FP64 averages; 64: all FP64 */
+    int32_t  sample_every;      /* S >= 1: sample after every S-th step */
+    int32_t  max_windows;       /* capacity of the per-replica sample store */
+    int32_t  tsf;               /* 1: also keep per-replica window time averages */
+    int32_t  checkpoint_every;  /* K > 0 enables ra_backward (precision 32 only) */
+    int32_t  max_steps;         /* steps since ra_init_chains the checkpoints must hold */
+    int32_t  plain;             /* 1: plain path, one launch per step, state in HBM */
+    int32_t  use_graph;         /* 1: capture ra_step's launch sequence in a hipGraph */
+    int32_t  tile_policy;       /* 0 cost model; 1 autotune by timing; m > 1 000: force
+                                   m - 1000 beads per lane where legal */
+    int32_t  waves_per_block;   /* 0 = default (4) */
+} ra_run_desc;
+
+/* Create a context: validates every descriptor (RA_EINVAL with nothing
+ * allocated on any violation), chooses a tile per group, allocates all device
+ * memory it will use, and records the HIP stream (NULL = null stream). */
+RA_API ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
+                           const ra_run_desc* run, void* hip_stream);
+
+/* RSF clone (Sec. II): every replica of group g starts from its parent.
+ * parent_xyz: device FP64, N_g*3 values per group (x,y,z per bead), groups
+ * concatenated. Resets the step counter, windows, TSF sums and guard counts.
+ * A FENE bond with |Q| >= Q0 or a non-finite coordinate is detected on the
+ * device; ra_sync_status then returns RA_EINVAL and ra_step does no work. */
+RA_API ra_status ra_init_chains(ra_ctx* ctx, const double* parent_xyz);
+
+/* Advance every replica of every group by n_steps Euler-Maruyama steps of
+ * Eq. (1) (free-draining, Eq. (2)), sampling spring tensions after each
+ * step whose 1-based index since init is a multiple of S. Fails with
+ * RA_EINVAL if the window capacity, the checkpoint capacity or 2^32 total
+ * steps would be exceeded. */
+RA_API ra_status ra_step(ra_ctx* ctx, int64_t n_steps);
+
+/* RSF estimate (Sec. II): replica mean of the sampled tensions and their
+ * replica standard deviation (denominator R-1; 0 when R = 1), FP64, for all
+ * windows sampled since init. mean/std: device [W][sum_g(N_g-1)]; tsf_mean,
+ * tsf_std the same for the window time averages (need tsf=1). Any output may
+ * be NULL. n_windows (host, may be NULL) receives W. */
+RA_API ra_status ra_average_forces(ra_ctx* ctx, double* mean, double* std,
+                                   double* tsf_mean, double* tsf_std, int64_t* n_windows);
+
+/* Bell-type rates (Sec. III): rates[w][s] = k0 exp(x_dagger mean[w][s] / kT_g),
+ * rate_sum[w][g] = sum over the springs of group g (its inverse is the mean
+ * first-passage time to any event). events[w][s] (uint8, may be NULL) = 1
+ * with probability 1 - exp(-rates * S * dt_g), from one tag-2 uniform per
+ * (window, spring, group). mean: device [n_windows][sum_g(N_g-1)]. */
+RA_API ra_status ra_bell_rates(ra_ctx* ctx, const double* mean, int64_t n_windows,
+                               double k0, double x_dagger, double* rates,
+                               double* rate_sum, uint8_t* events);
+
+/* Pathwise adjoint with the noise held fixed: gradient of
+ *   J = sum_{w,s} grad_mean[w][s] * mean[w][s] + sum_{w,s} grad_rates[w][s] * rates[w][s]
+ * with respect to (rate, H, b) of every group, through all steps since init.
+ * mean: the profile from ra_average_forces (device, used for the rates term);
+ * grad_rates may be NULL; grad_params: device FP64 [n_groups][3]. Needs
+ * checkpoint_every > 0; replays each K-step segment from its checkpoint.
+ * FENE springs on the guard are treated as having ds = 0. */
+RA_API ra_status ra_backward(ra_ctx* ctx, const double* mean, const double* grad_mean,
+                             const double* grad_rates, double k0, double x_dagger,
+                             double* grad_params);
+
+/* Synchronise the context's stream and report device-side errors:
+ * RA_EINVAL (invalid parent), RA_EUNSTABLE (non-finite tension) or RA_OK. */
+RA_API ra_status ra_sync_status(ra_ctx* ctx);
+
+/* Host copy of the per-group FENE guard counts (synchronises). out: host int64[n_groups]. */
+RA_API ra_status ra_guard_counts(ra_ctx* ctx, int64_t* out);
+
+/* Per-replica tension samples since init, device FP64
+ * [W][sum_g R_g (N_g-1)] ([replica][spring] per group); tsf_out likewise. */
+RA_API ra_status ra_get_samples(ra_ctx* ctx, double* out, double* tsf_out);
+
+/* Current bond vectors Q_j = r_{j+1} - r_j of every replica, device FP64
+ * [sum_g R_g (N_g-1) 3]. */
+RA_API ra_status ra_get_bonds(ra_ctx* ctx, double* out);
+
+/* Tile chosen per group (host int32[n_groups] each): beads per lane and
+ * replicas per wavefront. */
+RA_API ra_status ra_tile_info(ra_ctx* ctx, int32_t* beads_per_lane, int32_t* replicas_per_wave);
+
+/* Noise stream check: for n counters (device uint32 [n][4]) and key = seed,
+ * writes the Philox words (device uint32 [n][4]) and the three normals in
+ * FP32 and FP64 (device [n][3]); NULL outputs are skipped. Uses the same
+ * device functions as the simulation kernels. */
+RA_API ra_status ra_debug_noise(const uint32_t* counters, int64_t n, uint64_t seed,
+                                uint32_t* words, float* normals32, double* normals64,
+                                void* hip_stream);
+
+RA_API const char* ra_last_error(const ra_ctx* ctx);
+RA_API void ra_destroy(ra_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

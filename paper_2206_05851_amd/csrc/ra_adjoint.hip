@@ -1,0 +1,284 @@
+// ra_adjoint.hip — pathwise adjoint of the fused forward path (FP32 state).
+//
+// Objective J = sum_{w,j} lam_mu[w][j] * mean_k f_j^{w,k}, where lam_mu is
+// dJ/d(replica-mean tension) (Bell-rate cotangents are folded into it first).
+// With the noise held fixed, every EM step Q^{n+1} = Phi(Q^n; rate, H, b) is
+// a smooth map, and reverse mode runs
+//   lambda^n = (dPhi/dQ)^T lambda^{n+1} + dJ/dQ^n (sample injections),
+//   dJ/dtheta += lambda^{n+1} . dPhi/dtheta + direct dJ/dtheta at samples.
+// The forward stored Q every K steps; each K-step segment is recomputed
+// from its checkpoint with the same step function (bitwise-identical
+// trajectory) into a per-wavefront HBM buffer, then swept backwards.
+//
+// Bond form: Phi_j = Q_j + dt kappa Q_j + cF [G_{j+1} - 2 G_j + G_{j-1}] + noise,
+// G_j = g_j Q_j. The Laplacian is symmetric, so
+//   (dPhi/dQ)^T lambda at j = lambda_j + (dt kappa)^T lambda_j + cF J_j mu_j,
+//   mu_j = lambda_{j+1} - 2 lambda_j + lambda_{j-1},
+//   J_j = dG_j/dQ_j = g I + 2 g^2 / Q0^2 Q Q^T (FENE off the guard), g I on it.
+#include "ra_chain.hpp"
+#include "ra_launch.hpp"
+
+namespace ra {
+
+// g, s and the guard flag, computed exactly as the forward computes g.
+template <bool FENE>
+__device__ __forceinline__ void factor_gs(float qx, float qy, float qz, const GroupDev& G, float& g, float& s,
+                                          bool& smooth) {
+    if constexpr (!FENE) {
+        g = 1.0f; s = 0.0f; smooth = false;
+        return;
+    } else {
+        const float q2 = fmadd(qx, qx, fmadd(qy, qy, qz * qz));
+        const float sf = q2 * G.inv_q0sq;
+        if (sf > FENE_FP64_BAND) {
+            const double dx = qx, dy = qy, dz = qz;
+            double sd = (dx * dx + dy * dy + dz * dz) * G.inv_q0sq_d;
+            smooth = !(sd > 1.0 - FENE_DELTA);
+            if (!smooth) sd = 1.0 - FENE_DELTA;
+            g = (float)(1.0 / (1.0 - sd));
+            s = (float)sd;
+        } else {
+            g = fast_rcp(1.0f - sf);
+            s = sf;
+            smooth = true;
+        }
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void seg_store(float* seg, int step, const Lane<float, M>& s, int lane) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float* p = seg + ((int64_t)(step * M + m) * 3) * WAVE + lane;
+        p[0] = s.qx[m];
+        p[WAVE] = s.qy[m];
+        p[2 * WAVE] = s.qz[m];
+    }
+}
+template <int M>
+__device__ __forceinline__ void seg_load(const float* seg, int step, Lane<float, M>& s, int lane) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const float* p = seg + ((int64_t)(step * M + m) * 3) * WAVE + lane;
+        s.qx[m] = p[0];
+        s.qy[m] = p[WAVE];
+        s.qz[m] = p[2 * WAVE];
+    }
+}
+
+// dJ/dQ and direct dJ/dtheta of the sampled tension f = H g |Q| at window w.
+template <int M, bool FENE>
+__device__ __forceinline__ void inject(const Lane<float, M>& q, const bool (&valid)[M], const GroupDev& G,
+                                       const AdjArgs& a, const TileGeom& tg, int64_t w, float (&lx)[M],
+                                       float (&ly)[M], float (&lz)[M], double& gH, double& gb) {
+    const float H = G.H;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const float c = valid[m] ? (float)(a.lam_mu[w * a.spr_total + G.spr_off + tg.j0 + m] / (double)G.R)
+                                 : 0.0f;
+        float g, s;
+        bool smooth;
+        factor_gs<FENE>(q.qx[m], q.qy[m], q.qz[m], G, g, s, smooth);
+        const float q2 = fmadd(q.qx[m], q.qx[m], fmadd(q.qy[m], q.qy[m], q.qz[m] * q.qz[m]));
+        const float len = fast_sqrt(q2);
+        // df/dQ = H (g + 2 g^2 s) Q/|Q| off the guard, H g Q/|Q| on it (Hookean: s = 0)
+        const float coef = len > 0.0f ? H * (smooth ? fmadd(2.0f * g * g, s, g) : g) / len : 0.0f;
+        lx[m] = fmadd(c * coef, q.qx[m], lx[m]);
+        ly[m] = fmadd(c * coef, q.qy[m], ly[m]);
+        lz[m] = fmadd(c * coef, q.qz[m], lz[m]);
+        // df/dH = g |Q| (1 + g s), df/db = -H g^2 (s/b) |Q| off the guard
+        const float dH = smooth ? g * len * fmadd(g, s, 1.0f) : g * len;
+        const float db = (FENE && smooth) ? -H * g * g * (s / (float)G.b) * len : 0.0f;
+        gH += (double)(c * dH);
+        gb += (double)(c * db);
+    }
+}
+
+// Reverse step through Phi at the state q = Q^n; lambda holds lambda^{n+1}.
+template <int M, bool FENE>
+__device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const bool (&valid)[M], const GroupDev& G,
+                                             float (&lx)[M], float (&ly)[M], float (&lz)[M], double& gr,
+                                             double& gH, double& gb) {
+    const float kx = G.kx, ky = G.ky, kz = G.kz, kxz = G.kxz, cF = G.cF;
+    // d(dt kappa)/d rate, per flow
+    float px = 0.f, py = 0.f, pz = 0.f, pxz = 0.f;
+    const float dt = (float)G.dt;
+    if (G.flow == 1) { px = dt; py = -0.5f * dt; pz = -0.5f * dt; }
+    else if (G.flow == 2) { px = dt; py = -dt; }
+    else if (G.flow == 3) { pxz = dt; }
+    const float dtz = (float)(G.dt / G.zeta);
+    const float plx = from_prev_lane(lx[M - 1]), ply = from_prev_lane(ly[M - 1]), plz = from_prev_lane(lz[M - 1]);
+    const float nlx = from_next_lane(lx[0]), nly = from_next_lane(ly[0]), nlz = from_next_lane(lz[0]);
+    float ux[M], uy[M], uz[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const float nx = (m + 1 < M) ? lx[m + 1 < M ? m + 1 : m] : nlx;
+        const float ny = (m + 1 < M) ? ly[m + 1 < M ? m + 1 : m] : nly;
+        const float nz = (m + 1 < M) ? lz[m + 1 < M ? m + 1 : m] : nlz;
+        const float qx = (m > 0) ? lx[m > 0 ? m - 1 : 0] : plx;
+        const float qy = (m > 0) ? ly[m > 0 ? m - 1 : 0] : ply;
+        const float qz = (m > 0) ? lz[m > 0 ? m - 1 : 0] : plz;
+        ux[m] = fmadd(-2.0f, lx[m], nx + qx);
+        uy[m] = fmadd(-2.0f, ly[m], ny + qy);
+        uz[m] = fmadd(-2.0f, lz[m], nz + qz);
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float g, s;
+        bool smooth;
+        factor_gs<FENE>(q.qx[m], q.qy[m], q.qz[m], G, g, s, smooth);
+        const float Qx = q.qx[m], Qy = q.qy[m], Qz = q.qz[m];
+        // theta terms with lambda^{n+1}
+        gr += (double)fmadd(lx[m], fmadd(px, Qx, pxz * Qz), fmadd(ly[m], py * Qy, lz[m] * pz * Qz));
+        const float muQ = fmadd(ux[m], Qx, fmadd(uy[m], Qy, uz[m] * Qz));
+        const float wH = (FENE && smooth) ? dtz * g * fmadd(g, s, 1.0f) : dtz * g;
+        const float wb = (FENE && smooth) ? -cF * g * g * (s / (float)G.b) : 0.0f;
+        gH += (double)(wH * muQ);
+        gb += (double)(wb * muQ);
+        // lambda^n = lambda + (dt kappa)^T lambda + cF J mu
+        const float ex = (FENE && smooth) ? 2.0f * g * g * G.inv_q0sq * muQ : 0.0f;
+        const float jx = fmadd(g, ux[m], ex * Qx);
+        const float jy = fmadd(g, uy[m], ex * Qy);
+        const float jz = fmadd(g, uz[m], ex * Qz);
+        const float nx = lx[m] + fmadd(kx, lx[m], cF * jx);
+        const float ny = ly[m] + fmadd(ky, ly[m], cF * jy);
+        const float nz = lz[m] + fmadd(kz, lz[m], fmadd(kxz, lx[m], cF * jz));
+        lx[m] = valid[m] ? nx : 0.0f;
+        ly[m] = valid[m] ? ny : 0.0f;
+        lz[m] = valid[m] ? nz : 0.0f;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+template <int M, bool FENE>
+__device__ void run_adjoint(const AdjArgs& a, const GroupDev& G, int item, int k_first) {
+    const TileGeom tg = tile_geom(G, k_first, M);
+    const int lane = threadIdx.x & (WAVE - 1);
+    Lane<float, M> s, q;
+    bool valid[M];
+    float lx[M], ly[M], lz[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) lx[m] = ly[m] = lz[m] = 0.0f;
+    double gr = 0.0, gH = 0.0, gb = 0.0;
+    float* seg = a.segbuf + a.seg_off[item];
+    const int K = a.K;
+    const int64_t n_seg = (a.n_end + K - 1) / K;
+    int dummy = 0;
+    for (int64_t sgi = n_seg - 1; sgi >= 0; --sgi) {
+        const int64_t s0 = sgi * K;
+        const int64_t s1 = min(a.n_end, s0 + K);
+        load_lane<float, M>(s, valid, (const float*)a.ckpt + sgi * a.state_total, G, tg);
+        for (int64_t n = s0; n < s1; ++n) {
+            seg_store<M>(seg, (int)(n - s0), s, lane);
+            em_step<float, M, FENE>(s, G, valid, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, a.key0, a.key1,
+                                    dummy);
+        }
+        // s = Q^{s1}; sweep n = s1-1 .. s0, injecting at states n+1 that were sampled
+        for (int64_t n = s1 - 1; n >= s0; --n) {
+            if ((n + 1) % a.S == 0) inject<M, FENE>(s, valid, G, a, tg, (n + 1) / a.S - 1, lx, ly, lz, gH, gb);
+            seg_load<M>(seg, (int)(n - s0), q, lane);
+            reverse_step<M, FENE>(q, valid, G, lx, ly, lz, gr, gH, gb);
+            s = q;
+        }
+    }
+    gr = wave_sum(gr);
+    gH = wave_sum(gH);
+    gb = wave_sum(gb);
+    if (lane == 0) {
+        a.partial[3 * item] = gr;
+        a.partial[3 * item + 1] = gH;
+        a.partial[3 * item + 2] = gb;
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void adj_dispatch(const AdjArgs& a, const GroupDev& G, int item, int k0) {
+    if (G.spring == 1) run_adjoint<M, true>(a, G, item, k0);
+    else run_adjoint<M, false>(a, G, item, k0);
+}
+
+template <int FAMILY>
+__global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int item = (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
+    if (item >= a.n_items) return;
+    const Item it = a.items[item];
+    const GroupDev& G = a.groups[it.g];
+    if constexpr (FAMILY == 4) {
+        switch (G.M) {
+        case 1: adj_dispatch<1>(a, G, item, it.k0); break;
+        case 2: adj_dispatch<2>(a, G, item, it.k0); break;
+        case 3: adj_dispatch<3>(a, G, item, it.k0); break;
+        case 4: adj_dispatch<4>(a, G, item, it.k0); break;
+        default: break;
+        }
+    } else {
+        switch (G.M) {
+        case 6: adj_dispatch<6>(a, G, item, it.k0); break;
+        case 8: adj_dispatch<8>(a, G, item, it.k0); break;
+        case 12: adj_dispatch<12>(a, G, item, it.k0); break;
+        case 16: adj_dispatch<16>(a, G, item, it.k0); break;
+        default: break;
+        }
+    }
+}
+
+// lam_mu[w][s] = grad_mean + grad_rates * dk/dmean, dk/dmean = k * x_dagger / kT.
+__global__ __launch_bounds__(64) void lam_mu_kernel(const GroupDev* __restrict__ groups, const double* __restrict__ mean,
+                                                    const double* __restrict__ gm, const double* __restrict__ grt,
+                                                    double k0, double xd, int64_t spr_total, double* __restrict__ out) {
+    const GroupDev& G = groups[blockIdx.x];
+    const int64_t w = blockIdx.y;
+    for (int j = threadIdx.x; j < G.N - 1; j += WAVE) {
+        const int64_t o = w * spr_total + G.spr_off + j;
+        double v = gm ? gm[o] : 0.0;
+        if (grt) v += grt[o] * k0 * exp(xd * mean[o] / G.kT) * xd / G.kT;
+        out[o] = v;
+    }
+}
+
+// grad[g][p] = sum over the group's work items, in work-list order.
+__global__ void grad_reduce_kernel(const int32_t* __restrict__ begin_count, int n_groups,
+                                   const double* __restrict__ partial, double* __restrict__ grad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 3 * n_groups) return;
+    const int g = e / 3, p = e - 3 * g;
+    const int b = begin_count[2 * g], n = begin_count[2 * g + 1];
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += partial[3 * (b + i) + p];
+    grad[e] = acc;
+}
+
+hipError_t launch_adjoint(const AdjArgs& a, int family, int waves_per_block, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    const int wpb = waves_per_block;
+    dim3 grid((a.n_items + wpb - 1) / wpb), block(WAVE * wpb);
+    if (family == 4) hipLaunchKernelGGL(adjoint_kernel<4>, grid, block, 0, st, a);
+    else hipLaunchKernelGGL(adjoint_kernel<16>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lam_mu(const GroupDev* groups, int n_groups, int64_t n_windows, const double* mean,
+                         const double* grad_mean, const double* grad_rates, double k0, double xd,
+                         int64_t spr_total, double* lam_mu, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    if (n_windows == 0) return hipSuccess;
+    hipLaunchKernelGGL(lam_mu_kernel, dim3((unsigned)n_groups, (unsigned)n_windows), dim3(64), 0, st, groups,
+                       mean, grad_mean, grad_rates, k0, xd, spr_total, lam_mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const int32_t* item_begin, int n_groups, const double* partial,
+                              double* grad_params, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((3 * n_groups + 63) / 64)), dim3(64), 0, st,
+                       item_begin, n_groups, partial, grad_params);
+    return hipGetLastError();
+}
+
+}  // namespace ra

@@ -1,0 +1,548 @@
+// ra_kernels.hip — gfx950 kernels of the replica-averaged BD library.
+//
+// Fused forward path (one launch per ra_step):
+//   one wavefront per work item = P replicas of one group; a replica occupies
+//   L = ceil(N/M) consecutive lanes, lane t holding beads/springs
+//   [t*M, t*M + M). The chain lives in VGPRs as bond vectors Q_j = r_{j+1} - r_j
+//   for the whole time loop; neighbour springs and neighbour-bead noise come
+//   from the adjacent lane by DPP wave shifts. Every slot past the last spring
+//   of a replica holds Q = 0 (so its force is 0), which makes the chain ends
+//   and the seams between packed replicas need no extra masking.
+// The step itself (bond form of Eq. (1) with Eq. (2)) is in ra_chain.hpp.
+#include "ra_chain.hpp"
+#include "ra_launch.hpp"
+
+namespace ra {
+
+// ---------------------------------------------------------------------------
+// Fused persistent forward: all n_steps of one work item in registers.
+// ---------------------------------------------------------------------------
+template <typename T, int M, bool FENE>
+__device__ void run_forward(const FwdArgs& a, const GroupDev& G, int k_first, int64_t n0) {
+    const TileGeom tg = tile_geom(G, k_first, M);
+    Lane<T, M> s;
+    bool valid[M];
+    load_lane<T, M>(s, valid, (const T*)a.state, G, tg);
+    const int nm1 = G.N - 1;
+    double tacc[M];
+    const bool tsf = a.tsf != nullptr;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        tacc[m] = 0.0;
+        if (tsf && valid[m]) tacc[m] = a.tsf_acc[G.smp_off + (int64_t)tg.k * nm1 + tg.j0 + m];
+    }
+    int clamps = 0;
+    int smp_ctr = (int)(n0 % a.S);
+    int ck_ctr = a.K > 0 ? (int)(n0 % a.K) : 1;
+    T* __restrict__ samples = (T*)a.samples;
+    T* __restrict__ tsfo = (T*)a.tsf;
+    T* __restrict__ ckpt = (T*)a.ckpt;
+    for (int64_t i = 0; i < a.n_steps; ++i) {
+        const int64_t n = n0 + i;
+        if (a.K > 0) {
+            if (ck_ctr == 0) store_lane<T, M>(s, valid, ckpt + (n / a.K) * a.state_total, G, tg);
+            if (++ck_ctr == a.K) ck_ctr = 0;
+        }
+        em_step<T, M, FENE>(s, G, valid, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, a.key0, a.key1,
+                            clamps);
+        const bool window_end = (++smp_ctr == a.S);
+        if (window_end) smp_ctr = 0;
+        if (tsf || window_end) {
+            T f[M];
+            tensions<T, M, FENE>(s, G, f);
+            const int64_t w = (n + 1) / a.S - 1;
+            bool bad = false;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (!valid[m]) continue;
+                const int64_t o = w * a.smp_total + G.smp_off + (int64_t)tg.k * nm1 + tg.j0 + m;
+                if (tsf) tacc[m] += (double)f[m];
+                if (window_end) {
+                    samples[o] = f[m];
+                    bad |= !__builtin_isfinite(f[m]);
+                    if (tsf) {
+                        tsfo[o] = (T)(tacc[m] / (double)a.S);
+                        tacc[m] = 0.0;
+                    }
+                }
+            }
+            if (bad) atomicOr(a.status, 2);
+        }
+    }
+    store_lane<T, M>(s, valid, (T*)a.state, G, tg);
+    if (tsf) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (valid[m]) a.tsf_acc[G.smp_off + (int64_t)tg.k * nm1 + tg.j0 + m] = tacc[m];
+    }
+    flush_clamps(clamps, a.clamps + (&G - a.groups));
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void dispatch_spring(const FwdArgs& a, const GroupDev& G, int k_first, int64_t n0) {
+    if (G.spring == 1) run_forward<T, M, true>(a, G, k_first, n0);
+    else run_forward<T, M, false>(a, G, k_first, n0);
+}
+
+template <typename T, int FAMILY>
+__global__ __launch_bounds__(256) void fwd_kernel(FwdArgs a) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int item = (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
+    if (item >= a.n_items) return;
+    if (*(const volatile int*)a.status & 1) return;   // invalid parent: no work
+    const Item it = a.items[item];
+    const GroupDev& G = a.groups[it.g];
+    const int64_t n0 = *a.step0;
+    if constexpr (FAMILY == 4) {
+        switch (G.M) {
+        case 1: dispatch_spring<T, 1>(a, G, it.k0, n0); break;
+        case 2: dispatch_spring<T, 2>(a, G, it.k0, n0); break;
+        case 3: dispatch_spring<T, 3>(a, G, it.k0, n0); break;
+        case 4: dispatch_spring<T, 4>(a, G, it.k0, n0); break;
+        default: break;
+        }
+    } else {
+        switch (G.M) {
+        case 6: dispatch_spring<T, 6>(a, G, it.k0, n0); break;
+        case 8: dispatch_spring<T, 8>(a, G, it.k0, n0); break;
+        case 12: dispatch_spring<T, 12>(a, G, it.k0, n0); break;
+        case 16: dispatch_spring<T, 16>(a, G, it.k0, n0); break;
+        default: break;
+        }
+    }
+}
+
+__global__ void advance_kernel(int64_t* step, int64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += n;
+}
+
+// ---------------------------------------------------------------------------
+// Clone (RSF, Sec. II): Q_j = parent_{j+1} - parent_j in FP64, then rounded to
+// the state precision, for every replica; the parent is validated here.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void clone_kernel(const GroupDev* __restrict__ groups, const double* __restrict__ parent,
+                             const int64_t* __restrict__ par_off, T* __restrict__ state,
+                             double* __restrict__ tsf_acc, int32_t* status) {
+    const GroupDev& G = groups[blockIdx.y];
+    const int nm1 = G.N - 1;
+    const int64_t total = (int64_t)G.R * nm1;
+    const double* p = parent + par_off[blockIdx.y];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / nm1;
+        const int j = (int)(e - k * nm1);
+        const double qx = p[3 * (j + 1)] - p[3 * j];
+        const double qy = p[3 * (j + 1) + 1] - p[3 * j + 1];
+        const double qz = p[3 * (j + 1) + 2] - p[3 * j + 2];
+        bool bad = !(__builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz));
+        if (G.spring == 1 && !((qx * qx + qy * qy + qz * qz) * G.inv_q0sq_d < 1.0)) bad = true;
+        if (bad && k == 0) atomicOr(status, 1);
+        const int64_t o = G.state_off + e * 3;
+        state[o] = (T)qx;
+        state[o + 1] = (T)qy;
+        state[o + 2] = (T)qz;
+        if (tsf_acc) tsf_acc[G.smp_off + e] = 0.0;
+    }
+}
+
+// Plain path clone: bead positions of every replica = parent.
+template <typename T>
+__global__ void clone_pos_kernel(const GroupDev* __restrict__ groups, const double* __restrict__ parent,
+                                 const int64_t* __restrict__ par_off, T* __restrict__ pos,
+                                 double* __restrict__ tsf_acc, int32_t* status) {
+    const GroupDev& G = groups[blockIdx.y];
+    const int64_t per = (int64_t)G.N * 3;
+    const int64_t total = (int64_t)G.R * per;
+    const double* p = parent + par_off[blockIdx.y];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e % per;
+        pos[G.pos_off + e] = (T)p[c];
+        if (e < per) {
+            bool bad = !__builtin_isfinite(p[c]);
+            if (G.spring == 1 && c % 3 == 0 && c + 3 < per) {
+                const double qx = p[c + 3] - p[c], qy = p[c + 4] - p[c + 1], qz = p[c + 5] - p[c + 2];
+                if (!((qx * qx + qy * qy + qz * qz) * G.inv_q0sq_d < 1.0)) bad = true;
+            }
+            if (bad) atomicOr(status, 1);
+        }
+    }
+    if (tsf_acc) {
+        const int64_t ns = (int64_t)G.R * (G.N - 1);
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ns;
+             e += (int64_t)gridDim.x * blockDim.x)
+            tsf_acc[G.smp_off + e] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain path: one launch per step per group, bead positions in HBM, one
+// thread per (replica, bead), bead form of Eq. (1) with the same counters.
+// ---------------------------------------------------------------------------
+template <typename T, bool FENE>
+__device__ __forceinline__ void bond_force(const T* r0, const T* r1, const GroupDev& G, T& fx, T& fy,
+                                           T& fz, int& clamps) {
+    const T qx = r1[0] - r0[0], qy = r1[1] - r0[1], qz = r1[2] - r0[2];
+    T g = (T)1;
+    if constexpr (FENE) {
+        const T q2 = fmadd(qx, qx, fmadd(qy, qy, qz * qz));
+        g = fene_g(qx, qy, qz, q2, (T)G.inv_q0sq, G.inv_q0sq_d, clamps);
+    }
+    fx = g * qx;
+    fy = g * qy;
+    fz = g * qz;
+}
+
+template <typename T, bool FENE>
+__global__ __launch_bounds__(256) void plain_step_kernel(const GroupDev* __restrict__ groups, int g,
+                                                         const T* __restrict__ rin, T* __restrict__ rout,
+                                                         const int32_t* status, uint32_t n, uint32_t key0,
+                                                         uint32_t key1, unsigned long long* clamp_ctr) {
+    const GroupDev& G = groups[g];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)G.R * G.N) return;
+    if (*status & 1) return;
+    const int64_t k = e / G.N;
+    const int i = (int)(e - k * G.N);
+    const T* r = rin + G.pos_off + k * G.N * 3;
+    const Co<T> c{G};
+    int clamps = 0;
+    T fx = 0, fy = 0, fz = 0;
+    if (i <= G.N - 2) {
+        T ax, ay, az;
+        bond_force<T, FENE>(r + 3 * i, r + 3 * (i + 1), G, ax, ay, az, clamps);
+        fx += ax; fy += ay; fz += az;
+    }
+    if (i >= 1) {
+        T bx, by, bz;
+        int dummy = 0;
+        bond_force<T, FENE>(r + 3 * (i - 1), r + 3 * i, G, bx, by, bz, dummy);
+        fx -= bx; fy -= by; fz -= bz;
+    }
+    T ex, ey, ez;
+    normals3(philox10(n, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), ex, ey, ez);
+    const T x = r[3 * i], y = r[3 * i + 1], z = r[3 * i + 2];
+    const T ix = fmadd(c.kx(), x, fmadd(c.kxz(), z, fmadd(c.cF(), fx, c.sigma() * ex)));
+    const T iy = fmadd(c.ky(), y, fmadd(c.cF(), fy, c.sigma() * ey));
+    const T iz = fmadd(c.kz(), z, fmadd(c.cF(), fz, c.sigma() * ez));
+    T* o = rout + G.pos_off + k * G.N * 3 + 3 * i;
+    o[0] = x + ix;
+    o[1] = y + iy;
+    o[2] = z + iz;
+    if (clamps) atomicAdd(clamp_ctr + g, (unsigned long long)clamps);
+}
+
+template <typename T, bool FENE>
+__global__ __launch_bounds__(256) void plain_sample_kernel(const GroupDev* __restrict__ groups, int g,
+                                                           const T* __restrict__ pos, T* __restrict__ samples,
+                                                           T* __restrict__ tsfo, double* __restrict__ tsf_acc,
+                                                           int window_end, int S, int32_t* status) {
+    const GroupDev& G = groups[g];
+    const int nm1 = G.N - 1;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)G.R * nm1) return;
+    const int64_t k = e / nm1;
+    const int j = (int)(e - k * nm1);
+    const T* r = pos + G.pos_off + k * G.N * 3 + 3 * j;
+    int dummy = 0;
+    T fx, fy, fz;
+    bond_force<T, FENE>(r, r + 3, G, fx, fy, fz, dummy);
+    const T f = Co<T>{G}.H() * fast_sqrt(fmadd(fx, fx, fmadd(fy, fy, fz * fz)));
+    const int64_t o = G.smp_off + e;
+    if (tsf_acc) {
+        const double acc = tsf_acc[o] + (double)f;
+        if (window_end) {
+            tsfo[o] = (T)(acc / (double)S);
+            tsf_acc[o] = 0.0;
+        } else {
+            tsf_acc[o] = acc;
+        }
+    }
+    if (window_end) {
+        samples[o] = f;
+        if (!__builtin_isfinite(f)) atomicOr(status, 2);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Replica reduction (RSF estimate, Sec. II): per (window, spring) the replica
+// mean and the R-1 standard deviation, FP64, two passes, fixed order:
+// wave v sums replicas [v*R/W, (v+1)*R/W) in order, waves combine in order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_kernel(const GroupDev* __restrict__ groups,
+                                                     const ColTile* __restrict__ tiles,
+                                                     const T* __restrict__ smp, int64_t smp_total,
+                                                     int64_t spr_total, double* __restrict__ mean,
+                                                     double* __restrict__ stdv) {
+    __shared__ double part[4][WAVE];
+    const ColTile tile = tiles[blockIdx.x];
+    const int64_t w = blockIdx.y;
+    const GroupDev& G = groups[tile.g];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x >> 6;
+    const int nm1 = G.N - 1;
+    const int j = tile.j0 + lane;
+    const bool ok = j < nm1;
+    const int chunk = (G.R + 3) / 4;
+    const int kb = wv * chunk;
+    const int ke = min(G.R, kb + chunk);
+    const T* base = smp + w * smp_total + G.smp_off + (ok ? j : 0);
+    double acc = 0.0;
+    if (ok)
+        for (int k = kb; k < ke; ++k) acc += (double)base[(int64_t)k * nm1];
+    part[wv][lane] = acc;
+    __syncthreads();
+    const double mu = (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) / (double)G.R;
+    __syncthreads();
+    double ss = 0.0;
+    if (ok)
+        for (int k = kb; k < ke; ++k) {
+            const double d = (double)base[(int64_t)k * nm1] - mu;
+            ss = fmadd(d, d, ss);
+        }
+    part[wv][lane] = ss;
+    __syncthreads();
+    if (wv == 0 && ok) {
+        const double tot = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        const int64_t o = w * spr_total + G.spr_off + j;
+        if (mean) mean[o] = mu;
+        if (stdv) stdv[o] = G.R > 1 ? sqrt(tot / (double)(G.R - 1)) : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bell-type rates (Sec. III) and event draws, one wavefront per (group, window).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void bell_kernel(const GroupDev* __restrict__ groups, int n_groups,
+                                                  const double* __restrict__ mean, int64_t spr_total,
+                                                  double k0, double xd, double* __restrict__ rates,
+                                                  double* __restrict__ rate_sum, uint8_t* __restrict__ events,
+                                                  int S, uint32_t key0, uint32_t key1) {
+    const int g = blockIdx.x;
+    const int64_t w = blockIdx.y;
+    const GroupDev& G = groups[g];
+    const int lane = threadIdx.x;
+    double acc = 0.0;
+    for (int j = lane; j < G.N - 1; j += WAVE) {
+        const int64_t o = w * spr_total + G.spr_off + j;
+        const double k = k0 * exp(xd * mean[o] / G.kT);
+        if (rates) rates[o] = k;
+        acc += k;
+        if (events) {
+            const Words u = philox10((uint32_t)w, (uint32_t)j, 0u, (2u << 24) | (G.stream & 0xFFFFFFu), key0, key1);
+            const double p = -expm1(-k * (double)S * G.dt);
+            events[o] = u01_f64(u.x) < p ? 1 : 0;
+        }
+    }
+    // fixed-order butterfly over the 64 lanes
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, WAVE);
+    if (lane == 0 && rate_sum) rate_sum[w * n_groups + g] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Inspection helpers.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void to_f64_kernel(const T* __restrict__ src, double* __restrict__ dst, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = (double)src[e];
+}
+
+template <typename T>
+__global__ void pos_to_bonds_kernel(const GroupDev* __restrict__ groups, const T* __restrict__ pos,
+                                    double* __restrict__ out) {
+    const GroupDev& G = groups[blockIdx.y];
+    const int nm1 = G.N - 1;
+    const int64_t total = (int64_t)G.R * nm1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / nm1;
+        const int j = (int)(e - k * nm1);
+        const T* r = pos + G.pos_off + k * G.N * 3 + 3 * j;
+        for (int a = 0; a < 3; ++a) out[G.state_off + e * 3 + a] = (double)r[3 + a] - (double)r[a];
+    }
+}
+
+__global__ void debug_noise_kernel(const uint32_t* __restrict__ ctr, int64_t n, uint32_t key0, uint32_t key1,
+                                   uint32_t* __restrict__ words, float* __restrict__ n32,
+                                   double* __restrict__ n64) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const Words w = philox10(ctr[4 * e], ctr[4 * e + 1], ctr[4 * e + 2], ctr[4 * e + 3], key0, key1);
+    if (words) {
+        words[4 * e] = w.x;
+        words[4 * e + 1] = w.y;
+        words[4 * e + 2] = w.z;
+        words[4 * e + 3] = w.w;
+    }
+    if (n32) {
+        float a, b, c;
+        normals3(w, a, b, c);
+        n32[3 * e] = a;
+        n32[3 * e + 1] = b;
+        n32[3 * e + 2] = c;
+    }
+    if (n64) {
+        double a, b, c;
+        normals3(w, a, b, c);
+        n64[3 * e] = a;
+        n64[3 * e + 1] = b;
+        n64[3 * e + 2] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+static dim3 grid1d(int64_t n, int block) {
+    int64_t b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > 65535) b = 65535;
+    return dim3((unsigned)b);
+}
+
+hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    const int wpb = waves_per_block;
+    dim3 grid((a.n_items + wpb - 1) / wpb), block(WAVE * wpb);
+    if (precision == 64) {
+        hipLaunchKernelGGL((fwd_kernel<double, 4>), grid, block, 0, st, a);
+    } else if (family == 4) {
+        hipLaunchKernelGGL((fwd_kernel<float, 4>), grid, block, 0, st, a);
+    } else {
+        hipLaunchKernelGGL((fwd_kernel<float, 16>), grid, block, 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(int64_t* step, int64_t n, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, st, step, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_clone(const GroupDev* groups, int n_groups, int64_t max_elems, const double* parent,
+                        const int64_t* par_off, void* state, double* tsf_acc, int32_t* status, int precision,
+                        bool plain, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    dim3 grid((unsigned)std::min<int64_t>((max_elems + 255) / 256, 4096), (unsigned)n_groups), block(256);
+    if (plain) {
+        if (precision == 64)
+            hipLaunchKernelGGL(clone_pos_kernel<double>, grid, block, 0, st, groups, parent, par_off,
+                               (double*)state, tsf_acc, status);
+        else
+            hipLaunchKernelGGL(clone_pos_kernel<float>, grid, block, 0, st, groups, parent, par_off,
+                               (float*)state, tsf_acc, status);
+    } else {
+        if (precision == 64)
+            hipLaunchKernelGGL(clone_kernel<double>, grid, block, 0, st, groups, parent, par_off,
+                               (double*)state, tsf_acc, status);
+        else
+            hipLaunchKernelGGL(clone_kernel<float>, grid, block, 0, st, groups, parent, par_off,
+                               (float*)state, tsf_acc, status);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_step(const GroupDev* groups, int g, int64_t n_threads, bool fene, const void* rin,
+                             void* rout, const int32_t* status, uint32_t n, uint32_t key0, uint32_t key1,
+                             unsigned long long* clamps, int precision, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    dim3 grid((unsigned)((n_threads + 255) / 256)), block(256);
+    if (precision == 64) {
+        if (fene) hipLaunchKernelGGL((plain_step_kernel<double, true>), grid, block, 0, st, groups, g,
+                                     (const double*)rin, (double*)rout, status, n, key0, key1, clamps);
+        else hipLaunchKernelGGL((plain_step_kernel<double, false>), grid, block, 0, st, groups, g,
+                                (const double*)rin, (double*)rout, status, n, key0, key1, clamps);
+    } else {
+        if (fene) hipLaunchKernelGGL((plain_step_kernel<float, true>), grid, block, 0, st, groups, g,
+                                     (const float*)rin, (float*)rout, status, n, key0, key1, clamps);
+        else hipLaunchKernelGGL((plain_step_kernel<float, false>), grid, block, 0, st, groups, g,
+                                (const float*)rin, (float*)rout, status, n, key0, key1, clamps);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_sample(const GroupDev* groups, int g, int64_t n_threads, bool fene, const void* pos,
+                               void* samples_w, void* tsf_w, double* tsf_acc, int window_end, int S,
+                               int32_t* status, int precision, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    dim3 grid((unsigned)((n_threads + 255) / 256)), block(256);
+    if (precision == 64) {
+        if (fene) hipLaunchKernelGGL((plain_sample_kernel<double, true>), grid, block, 0, st, groups, g,
+                                     (const double*)pos, (double*)samples_w, (double*)tsf_w, tsf_acc,
+                                     window_end, S, status);
+        else hipLaunchKernelGGL((plain_sample_kernel<double, false>), grid, block, 0, st, groups, g,
+                                (const double*)pos, (double*)samples_w, (double*)tsf_w, tsf_acc,
+                                window_end, S, status);
+    } else {
+        if (fene) hipLaunchKernelGGL((plain_sample_kernel<float, true>), grid, block, 0, st, groups, g,
+                                     (const float*)pos, (float*)samples_w, (float*)tsf_w, tsf_acc,
+                                     window_end, S, status);
+        else hipLaunchKernelGGL((plain_sample_kernel<float, false>), grid, block, 0, st, groups, g,
+                                (const float*)pos, (float*)samples_w, (float*)tsf_w, tsf_acc,
+                                window_end, S, status);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const GroupDev* groups, const ColTile* tiles, int n_tiles, int64_t n_windows,
+                         const void* smp, int64_t smp_total, int64_t spr_total, double* mean, double* stdv,
+                         int precision, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    if (n_tiles == 0 || n_windows == 0) return hipSuccess;
+    dim3 grid((unsigned)n_tiles, (unsigned)n_windows), block(256);
+    if (precision == 64)
+        hipLaunchKernelGGL(reduce_kernel<double>, grid, block, 0, st, groups, tiles, (const double*)smp,
+                           smp_total, spr_total, mean, stdv);
+    else
+        hipLaunchKernelGGL(reduce_kernel<float>, grid, block, 0, st, groups, tiles, (const float*)smp,
+                           smp_total, spr_total, mean, stdv);
+    return hipGetLastError();
+}
+
+hipError_t launch_bell(const GroupDev* groups, int n_groups, int64_t n_windows, const double* mean,
+                       int64_t spr_total, double k0, double xd, double* rates, double* rate_sum,
+                       uint8_t* events, int S, uint32_t key0, uint32_t key1, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    if (n_windows == 0) return hipSuccess;
+    dim3 grid((unsigned)n_groups, (unsigned)n_windows), block(64);
+    hipLaunchKernelGGL(bell_kernel, grid, block, 0, st, groups, n_groups, mean, spr_total, k0, xd, rates,
+                       rate_sum, events, S, key0, key1);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f64(const void* src, double* dst, int64_t n, int precision, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    if (n == 0) return hipSuccess;
+    if (precision == 64)
+        hipLaunchKernelGGL(to_f64_kernel<double>, grid1d(n, 256), dim3(256), 0, st, (const double*)src, dst, n);
+    else
+        hipLaunchKernelGGL(to_f64_kernel<float>, grid1d(n, 256), dim3(256), 0, st, (const float*)src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pos_to_bonds(const GroupDev* groups, int n_groups, int64_t max_elems, const void* pos,
+                               double* out, int precision, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    dim3 grid((unsigned)std::min<int64_t>((max_elems + 255) / 256, 4096), (unsigned)n_groups), block(256);
+    if (precision == 64)
+        hipLaunchKernelGGL(pos_to_bonds_kernel<double>, grid, block, 0, st, groups, (const double*)pos, out);
+    else
+        hipLaunchKernelGGL(pos_to_bonds_kernel<float>, grid, block, 0, st, groups, (const float*)pos, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_noise(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
+                              float* n32, double* n64, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_noise_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ctr, n, key0,
+                       key1, words, n32, n64);
+    return hipGetLastError();
+}
+
+}  // namespace ra

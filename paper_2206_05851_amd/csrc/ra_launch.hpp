@@ -1,0 +1,76 @@
+// ra_launch.hpp — kernel argument blocks and host launchers (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <algorithm>
+
+#include "ra_types.hpp"
+
+namespace ra {
+
+struct FwdArgs {
+    const GroupDev* groups;
+    const Item* items;
+    int32_t n_items;
+    int32_t S;                 // sample every S steps
+    int32_t K;                 // checkpoint every K steps (0: none)
+    uint32_t key0, key1;       // Philox key = seed
+    void* state;               // bond state, T[state_total]
+    void* samples;             // T[max_windows][smp_total]
+    void* tsf;                 // T[max_windows][smp_total] or nullptr
+    double* tsf_acc;           // running window sums [smp_total] or nullptr
+    void* ckpt;                // T[n_ckpt][state_total] or nullptr
+    int64_t smp_total;         // sample elements per window
+    int64_t state_total;       // bond-state elements
+    const int64_t* step0;      // device: steps since init before this launch
+    int64_t n_steps;
+    int32_t* status;           // bit 0: invalid parent, bit 1: non-finite tension
+    unsigned long long* clamps;
+};
+
+struct AdjArgs {
+    const GroupDev* groups;
+    const Item* items;
+    int32_t n_items;
+    int32_t S, K;
+    uint32_t key0, key1;
+    const void* ckpt;          // forward checkpoints T[n_ckpt][state_total]
+    int64_t state_total;
+    int64_t n_end;             // steps since init covered by the adjoint
+    const double* lam_mu;      // dJ/d mean [W][spr_total]
+    int64_t spr_total;
+    float* segbuf;             // per item: K states of the wave's lanes
+    const int64_t* seg_off;    // per item offset into segbuf (floats)
+    double* partial;           // per item [3]: d/d(rate, H, b)
+};
+
+hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, hipStream_t st);
+hipError_t launch_advance(int64_t* step, int64_t n, hipStream_t st);
+hipError_t launch_clone(const GroupDev* groups, int n_groups, int64_t max_elems, const double* parent,
+                        const int64_t* par_off, void* state, double* tsf_acc, int32_t* status, int precision,
+                        bool plain, hipStream_t st);
+hipError_t launch_plain_step(const GroupDev* groups, int g, int64_t n_threads, bool fene, const void* rin,
+                             void* rout, const int32_t* status, uint32_t n, uint32_t key0, uint32_t key1,
+                             unsigned long long* clamps, int precision, hipStream_t st);
+hipError_t launch_plain_sample(const GroupDev* groups, int g, int64_t n_threads, bool fene, const void* pos,
+                               void* samples_w, void* tsf_w, double* tsf_acc, int window_end, int S,
+                               int32_t* status, int precision, hipStream_t st);
+hipError_t launch_reduce(const GroupDev* groups, const ColTile* tiles, int n_tiles, int64_t n_windows,
+                         const void* smp, int64_t smp_total, int64_t spr_total, double* mean, double* stdv,
+                         int precision, hipStream_t st);
+hipError_t launch_bell(const GroupDev* groups, int n_groups, int64_t n_windows, const double* mean,
+                       int64_t spr_total, double k0, double xd, double* rates, double* rate_sum,
+                       uint8_t* events, int S, uint32_t key0, uint32_t key1, hipStream_t st);
+hipError_t launch_to_f64(const void* src, double* dst, int64_t n, int precision, hipStream_t st);
+hipError_t launch_pos_to_bonds(const GroupDev* groups, int n_groups, int64_t max_elems, const void* pos,
+                               double* out, int precision, hipStream_t st);
+hipError_t launch_debug_noise(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
+                              float* n32, double* n64, hipStream_t st);
+hipError_t launch_adjoint(const AdjArgs& a, int family, int waves_per_block, hipStream_t st);
+hipError_t launch_lam_mu(const GroupDev* groups, int n_groups, int64_t n_windows, const double* mean,
+                         const double* grad_mean, const double* grad_rates, double k0, double xd,
+                         int64_t spr_total, double* lam_mu, hipStream_t st);
+hipError_t launch_grad_reduce(const int32_t* item_begin, int n_groups, const double* partial,
+                              double* grad_params, hipStream_t st);
+
+}  // namespace ra

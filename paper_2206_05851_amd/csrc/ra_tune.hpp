@@ -1,0 +1,27 @@
+// ra_tune.hpp — tile selection: beads per lane M for each group.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ra.h"
+
+namespace ra {
+
+// Beads-per-lane values compiled into each kernel family.
+const std::vector<int>& family_beads_per_lane(int family);
+
+// Cost model: a wavefront of P = floor(64 / ceil(N/M)) replicas costs M lane
+// slots per bead-step, so a group costs M * ceil(R/P); the cheapest legal M
+// wins, ties going to the smaller M (more wavefronts in flight). `forced`
+// (> 0) is used when it is legal for N.
+int choose_beads_per_lane(int n_beads, int n_replicas, int family, int forced);
+
+// Times every legal M for each distinct (N, spring) of the batch with a short
+// run of the fused kernel on 256 replicas and keeps the fastest. Results are cached in
+// memory and, if RA_AUTOTUNE_CACHE names a file, in that JSON file.
+ra_status autotune_tiles(const std::vector<ra_chain_desc>& descs, const ra_run_desc& run, int family,
+                         int waves_per_block, hipStream_t stream, std::vector<int>& Ms, std::string& why);
+
+}  // namespace ra

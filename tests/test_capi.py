@@ -1,0 +1,90 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol that
+include/ra.h declares, and rejects invalid descriptors on the host before any
+device work (no GPU needed for these paths)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2206_05851_amd import ra
+    if not os.path.exists(ra.LIB_PATH):
+        from paper_2206_05851_amd import build
+        build.build()
+    return ra.library()
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "ra.h")).read()
+    return sorted(set(re.findall(r"RA_API\s+[\w\s\*]+?\b(ra_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_five_calls():
+    syms = header_symbols()
+    for name in ("ra_init_chains", "ra_step", "ra_average_forces", "ra_bell_rates", "ra_backward"):
+        assert name in syms
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2206_05851_amd import ra
+    syms = header_symbols()
+    assert sorted(ra.EXPORTS) == syms
+    for name in syms:
+        assert hasattr(lib, name), name
+    # and nothing from the oracle leaks into the product library
+    with pytest.raises(AttributeError):
+        getattr(lib, "rao_philox4x32_10")
+
+
+def test_struct_sizes_match_header():
+    from paper_2206_05851_amd import ra
+    text = open(os.path.join(ROOT, "include", "ra.h")).read()
+    assert "80 bytes" in text and "48 bytes" in text
+    assert ctypes.sizeof(ra.ChainDesc) == 80
+    assert ctypes.sizeof(ra.RunDesc) == 48
+
+
+def _create(lib, desc_kw, run_kw):
+    from paper_2206_05851_amd import ra
+    d = ra.make_desc(dict(dict(n_beads=10, n_replicas=4, dt=1e-3), **desc_kw), 0)
+    arr = (ra.ChainDesc * 1)(d)
+    run = ra.RunDesc(**dict(dict(seed=0, precision=32, sample_every=10, max_windows=4), **run_kw))
+    p = ctypes.c_void_p()
+    rc = lib.ra_create(ctypes.byref(p), arr, 1, ctypes.byref(run), None)
+    return rc, lib.ra_last_error(None).decode()
+
+
+@pytest.mark.parametrize("desc_kw,run_kw,frag", [
+    (dict(n_beads=1), {}, "n_beads"),
+    (dict(n_beads=2000), {}, "n_beads"),
+    (dict(n_beads=300), dict(precision=64), "n_beads"),
+    (dict(n_replicas=0), {}, "n_replicas"),
+    (dict(dt=0.0), {}, "dt"),
+    (dict(dt=float("nan")), {}, "dt"),
+    (dict(spring=1, b=0.0), {}, "FENE"),
+    (dict(spring=7), {}, "spring"),
+    (dict(flow=9), {}, "flow"),
+    (dict(stream_id=1 << 24), {}, "stream_id"),
+    (dict(noise_scale=-1.0), {}, "noise_scale"),
+    ({}, dict(precision=16), "precision"),
+    ({}, dict(sample_every=0), "sample_every"),
+    ({}, dict(checkpoint_every=10, precision=64), "adjoint"),
+    ({}, dict(checkpoint_every=10, plain=1), "adjoint"),
+    ({}, dict(waves_per_block=3), "waves_per_block"),
+])
+def test_invalid_descriptors_rejected_on_host(lib, desc_kw, run_kw, frag):
+    rc, msg = _create(lib, desc_kw, run_kw)
+    assert rc == -1
+    assert frag in msg
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    assert lib.ra_step(None, 10) == -1
+    assert lib.ra_init_chains(None, None) == -1
+    assert lib.ra_backward(None, None, None, None, 0.0, 0.0, None) == -1
+    lib.ra_destroy(None)

@@ -1,0 +1,111 @@
+"""Full-size workloads in the launch configuration the benchmark times:
+per-replica samples of chosen replicas against the oracle run one replica at
+a time (counters carry the global replica index), plus properties that hold
+at any size (profile = reduction of the samples, ordering of std/mean)."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_err, require_gpu, run_gpu
+from paper_2206_05851_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def oracle_replicas(groups, parents, seed, steps, S, picks, tsf=False):
+    """{(g, k): samples [W][N-1]} (and TSF) from the oracle, one replica of one
+    group per context: a group's results do not depend on the rest of the
+    batch, and its counters carry the global replica index."""
+    from oracle import ora
+    out = {}
+    for g, k in picks:
+        o = ora.Oracle([groups[g]], seed, S, steps // S, tsf=tsf)
+        o.set_replicas(0, k, k + 1)
+        o.init_chains([parents[g]])
+        o.step(steps)
+        if tsf:
+            a, b = o.samples(tsf=True)
+            out[(g, k)] = (a[0][:, 0], b[0][:, 0])
+        else:
+            out[(g, k)] = o.samples()[0][:, 0]
+    return out
+
+
+def check_profile_is_reduction(mean, std, samples_list):
+    # property: mean/std are the FP64 replica statistics of the samples
+    off = 0
+    for s in samples_list:
+        n = s.shape[2]
+        m = s.mean(axis=1)
+        sd = s.std(axis=1, ddof=1) if s.shape[1] > 1 else np.zeros_like(m)
+        assert rel_err(mean[:, off:off + n], m) < 1e-12
+        assert np.max(np.abs(std[:, off:off + n] - sd) / np.maximum(sd, 1e-300)) < 1e-9
+        off += n
+
+
+def test_fene50_full_size():
+    groups, parents, run = wl.fene50()
+    steps, S = run["steps"], run["sample_every"]
+    announce("fene50 full: R=1024 N=50 %d steps" % steps)
+    rep = run_gpu(groups, parents, run["seed"], steps, S)
+    mean, std = rep.average_forces()
+    rates, rsum = rep.bell_rates(mean, run["k0"], run["x_dagger"])
+    smp = rep.samples()[0].cpu().numpy()
+    rep.sync_status()
+    picks = [(0, 0), (0, 333), (0, 1023)]
+    ref = oracle_replicas(groups, parents, run["seed"], steps, S, picks)
+    for (g, k), s in ref.items():
+        e = rel_err(smp[:, k], s)
+        announce("replica %d over %d windows: max rel err %.2e" % (k, s.shape[0], e))
+        assert e < 1e-4
+    check_profile_is_reduction(mean.cpu().numpy(), std.cpu().numpy(), [smp])
+    r = rates.cpu().numpy()
+    assert np.allclose(r, run["k0"] * np.exp(run["x_dagger"] * mean.cpu().numpy()), rtol=1e-13)
+    assert np.allclose(rsum.cpu().numpy()[:, 0], r.sum(axis=1), rtol=1e-13)
+
+
+def test_batched512_full_size():
+    groups, parents, run = wl.batched512()
+    steps, S = run["steps"], run["sample_every"]
+    announce("batched512 full: 512 groups %d steps" % steps)
+    rep = run_gpu(groups, parents, run["seed"], steps, S, use_graph=True)
+    mean, std = rep.average_forces()
+    smp = [s.cpu().numpy() for s in rep.samples()]
+    rep.sync_status()
+    picks = [(0, 0), (100, 5), (300, 1), (511, 0)]
+    picks = [(g, min(k, groups[g]["n_replicas"] - 1)) for g, k in picks]
+    ref = oracle_replicas(groups, parents, run["seed"], steps, S, picks)
+    for (g, k), s in ref.items():
+        e = rel_err(smp[g][:, k], s)
+        announce("group %d (N=%d) replica %d: max rel err %.2e" % (g, groups[g]["n_beads"], k, e))
+        assert e < 1e-4
+    check_profile_is_reduction(mean.cpu().numpy(), std.cpu().numpy(), smp)
+
+
+def test_large1000_full_size():
+    groups, parents, run = wl.large1000()
+    steps, S = run["steps"], run["sample_every"]
+    announce("large1000 full: R=8192 N=1000 %d steps, TSF" % steps)
+    rep = run_gpu(groups, parents, run["seed"], steps, S, tsf=True)
+    mean, std, tm, ts = rep.average_forces(tsf=True)
+    rates, rsum, ev = rep.bell_rates(mean, run["k0"], run["x_dagger"], events=True)
+    smp, tsmp = rep.samples(tsf=True)
+    smp = smp[0][:, [0, 8191]].cpu().numpy()
+    tsmp = tsmp[0][:, [0, 8191]].cpu().numpy()
+    rep.sync_status()
+    ref = oracle_replicas(groups, parents, run["seed"], steps, S, [(0, 0), (0, 8191)], tsf=True)
+    for i, k in enumerate((0, 8191)):
+        s, t = ref[(0, k)]
+        e1 = rel_err(smp[:, i], s)
+        e2 = rel_err(tsmp[:, i], t)
+        announce("N=1000 replica %d: samples %.2e tsf %.2e" % (k, e1, e2))
+        assert e1 < 1e-4 and e2 < 1e-4
+    m = mean.cpu().numpy()
+    assert m.shape == (40, 999) and np.all(std.cpu().numpy() > 0)
+    # TSF averages over the window: its replica spread is smaller than RSF's
+    assert np.median(ts.cpu().numpy() / std.cpu().numpy()) < 1.0
+    assert ev.dtype.is_floating_point is False

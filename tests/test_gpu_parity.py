@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs. Tolerance for FP32 state: relative 1e-4 on per-replica
+samples and on the replica-averaged profile over windows of at most 200 steps;
+FP64 state: relative 1e-10. Integer work (Philox words, events) is bit-exact."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_err, require_gpu, run_gpu, run_oracle
+from paper_2206_05851_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-4
+TOL64 = 1e-10
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def test_noise_words_bit_exact_and_normals():
+    import torch
+    from oracle import ora
+    from paper_2206_05851_amd import ra
+    rng = np.random.default_rng(0)
+    n = 20000
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:8] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [1, 2, 3, 4], [99, 7, 1023, 1], [0, 1, 0, 0],
+               [5, 0, 0, 2 << 24], [12345, 49, 1023, 0], [0, 0, 0xFFFFFFFF, 0]]
+    seed = 0x0123456789ABCDEF
+    announce("debug_noise n=%d" % n)
+    words, n32, n64 = ra.debug_noise(torch.from_numpy(ctr.view(np.int32)).cuda(), seed)
+    torch.cuda.synchronize()
+    words = words.cpu().numpy().view(np.uint32)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    ref_w = np.array([ora.philox(c, key) for c in ctr], dtype=np.uint32)
+    assert np.array_equal(words, ref_w)
+    ref_n = np.array([ora.normals(w) for w in ref_w])
+    e32 = np.max(np.abs(n32.cpu().numpy() - ref_n))
+    e64 = np.max(np.abs(n64.cpu().numpy() - ref_n))
+    announce("normals max abs err fp32 %.3e fp64 %.3e" % (e32, e64))
+    assert e32 < 5e-6
+    assert e64 < 1e-13
+
+
+def test_fp64_rouse_n10_full_parity():
+    groups, parents, run = wl.rouse_fp64_small(n_replicas=64)
+    announce("C1 shape FP64: N=10 R=64 5000 steps")
+    rep = run_gpu(groups, parents, run["seed"], run["steps"], run["sample_every"], precision=64)
+    mean, std = rep.average_forces()
+    smp = rep.samples()[0].cpu().numpy()
+    rep.sync_status()
+    o = run_oracle(groups, parents, run["seed"], run["steps"], run["sample_every"])
+    rm, rs = o.average_forces()
+    e = (rel_err(smp, o.samples()[0]), rel_err(mean.cpu().numpy(), rm), rel_err(std.cpu().numpy(), rs))
+    announce("fp64 rel err samples %.2e mean %.2e std %.2e" % e)
+    assert max(e) < TOL64
+    assert mean.shape == (50, 9)
+
+
+def test_fp32_fene50_parity_200_steps():
+    groups, parents, run = wl.fene50(n_replicas=1024, steps=200)
+    announce("C2 shape: FENE N=50 R=1024 200 steps")
+    rep = run_gpu(groups, parents, run["seed"], 200, 100)
+    mean, std = rep.average_forces()
+    smp = rep.samples()[0].cpu().numpy()
+    rep.sync_status()
+    o = run_oracle(groups, parents, run["seed"], 200, 100)
+    rm, rs = o.average_forces()
+    e = (rel_err(smp, o.samples()[0]), rel_err(mean.cpu().numpy(), rm), rel_err(std.cpu().numpy(), rs))
+    announce("fp32 rel err samples %.2e mean %.2e std %.2e" % e)
+    assert max(e) < TOL32
+    assert rep.tile_info() == ([1], [1])
+
+
+@pytest.mark.parametrize("precision,tol", [(32, TOL32), (64, TOL64)])
+def test_plain_path_parity(precision, tol):
+    N = 30
+    g = wl.group(N, 96, 1e-4, wl.FENE, 1.0, 60.0, wl.SHEAR, 40.0)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 60.0, seed=7)
+    announce("plain path precision %d" % precision)
+    rep = run_gpu([g], [parent], 11, 200, 50, plain=True, precision=precision)
+    mean, std = rep.average_forces()
+    smp = rep.samples()[0].cpu().numpy()
+    bonds = rep.bonds()[0].cpu().numpy()
+    rep.sync_status()
+    o = run_oracle([g], [parent], 11, 200, 50)
+    rm, rs = o.average_forces()
+    ob = np.diff(o.positions()[0], axis=1)
+    e = (rel_err(smp, o.samples()[0]), rel_err(mean.cpu().numpy(), rm), rel_err(std.cpu().numpy(), rs),
+         rel_err(bonds, ob, floor=1.0))
+    announce("plain rel err samples %.2e mean %.2e std %.2e bonds %.2e" % e)
+    assert max(e) < tol
+
+
+def test_tile_choice_is_bitwise_invariant():
+    N, R = 37, 50
+    g = wl.group(N, R, 1e-4, wl.FENE, 1.0, 80.0, wl.SHEAR, 20.0)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 80.0, seed=9)
+    ref = None
+    for M in (1, 2, 3, 4):
+        announce("tile M=%d" % M)
+        rep = run_gpu([g], [parent], 5, 150, 50, tile_policy=1000 + M)
+        assert rep.tile_info()[0] == [M]
+        smp = rep.samples()[0].cpu().numpy()
+        rep.sync_status()
+        if ref is None:
+            ref = smp
+            o = run_oracle([g], [parent], 5, 150, 50)
+            assert rel_err(smp, o.samples()[0]) < TOL32
+        else:
+            assert np.array_equal(smp, ref), M
+
+
+def test_batch_is_bitwise_invariant():
+    gs = [wl.group(20, 40, 1e-4, wl.FENE, 1.0, 50.0, wl.PLANAR, 0.5, stream_id=4),
+          wl.group(63, 17, 2e-4, wl.HOOKEAN, 2.0, 0.0, wl.UNIAXIAL, 0.01, stream_id=9),
+          wl.group(150, 9, 1e-4, wl.FENE, 1.0, 150.0, wl.SHEAR, 5.0, stream_id=1)]
+    ps = [wl.equilibrium_parent(g["n_beads"], g["spring"], g["H"], g["b"], seed=i) for i, g in enumerate(gs)]
+    announce("batch of 3 vs alone")
+    rep = run_gpu(gs, ps, 21, 100, 25)
+    both = [s.cpu().numpy() for s in rep.samples()]
+    rep.sync_status()
+    for i in range(3):
+        alone = run_gpu([gs[i]], [ps[i]], 21, 100, 25)
+        a = alone.samples()[0].cpu().numpy()
+        alone.sync_status()
+        assert np.array_equal(both[i], a), i
+    o = run_oracle(gs, ps, 21, 100, 25)
+    for i, s in enumerate(o.samples()):
+        assert rel_err(both[i], s) < TOL32, i
+
+
+def test_graph_replay_matches_eager_bitwise():
+    N = 50
+    g = wl.group(N, 128, 1e-4, wl.FENE, 1.0, 100.0, wl.UNIAXIAL, 0.05)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 100.0, seed=3)
+    announce("graph replay")
+    eager = run_gpu([g], [parent], 8, 0, 50, max_windows=8)
+    graph = run_gpu([g], [parent], 8, 0, 50, max_windows=8, use_graph=True)
+    for _ in range(4):
+        eager.step(100)
+        graph.step(100)
+    a = eager.samples()[0].cpu().numpy()
+    b = graph.samples()[0].cpu().numpy()
+    eager.sync_status()
+    graph.sync_status()
+    assert np.array_equal(a, b)
+    assert a.shape[0] == 8
+
+
+def test_long_chain_parity():
+    N = 1000
+    g = wl.group(N, 12, 5e-5, wl.FENE, 1.0, 400.0, wl.UNIAXIAL, wl.wi_to_rate(10.0, N))
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 400.0, seed=103)
+    announce("N=1000 R=12 200 steps")
+    rep = run_gpu([g], [parent], 4, 200, 100)
+    assert rep.tile_info()[0] == [16]
+    mean, std = rep.average_forces()
+    smp = rep.samples()[0].cpu().numpy()
+    rep.sync_status()
+    o = run_oracle([g], [parent], 4, 200, 100)
+    rm, rs = o.average_forces()
+    e = (rel_err(smp, o.samples()[0]), rel_err(mean.cpu().numpy(), rm), rel_err(std.cpu().numpy(), rs))
+    announce("N=1000 rel err samples %.2e mean %.2e std %.2e" % e)
+    assert max(e) < TOL32
+
+
+def test_mixed_batch_parity():
+    groups, parents, run = wl.batched512(n_groups=512, steps=200)
+    pick = [0, 1, 17, 255, 256, 300, 511]
+    gs = [groups[i] for i in pick]
+    for g in gs:
+        g["n_replicas"] = min(g["n_replicas"], 32)
+    ps = [parents[i] for i in pick]
+    announce("mixed batch of %d groups, 200 steps" % len(gs))
+    rep = run_gpu(gs, ps, run["seed"], 200, 100)
+    mean, std = rep.average_forces()
+    smp = [s.cpu().numpy() for s in rep.samples()]
+    rep.sync_status()
+    o = run_oracle(gs, ps, run["seed"], 200, 100)
+    rm, rs = o.average_forces()
+    for i, s in enumerate(o.samples()):
+        assert rel_err(smp[i], s) < TOL32, i
+    assert rel_err(mean.cpu().numpy(), rm) < TOL32
+    assert rel_err(std.cpu().numpy(), rs) < TOL32
+
+
+def test_tsf_parity():
+    N = 40
+    g = wl.group(N, 32, 1e-4, wl.FENE, 1.0, 100.0, wl.UNIAXIAL, 0.5)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 100.0, seed=5)
+    announce("TSF")
+    for plain in (False, True):
+        rep = run_gpu([g], [parent], 6, 200, 50, tsf=True, plain=plain)
+        m, s, tm, ts = rep.average_forces(tsf=True)
+        smp, tsmp = rep.samples(tsf=True)
+        rep.sync_status()
+        o = run_oracle([g], [parent], 6, 200, 50, tsf=True)
+        rm, rs, rtm, rts = o.average_forces(tsf=True)
+        osm, otsm = o.samples(tsf=True)
+        assert rel_err(tsmp[0].cpu().numpy(), otsm[0]) < TOL32
+        assert rel_err(tm.cpu().numpy(), rtm) < TOL32
+        assert rel_err(ts.cpu().numpy(), rts) < TOL32
+        assert rel_err(m.cpu().numpy(), rm) < TOL32
+
+
+def test_tsf_window_straddles_calls():
+    N = 25
+    g = wl.group(N, 16, 1e-4, wl.FENE, 1.0, 100.0, wl.SHEAR, 3.0)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 100.0, seed=2)
+    rep = run_gpu([g], [parent], 3, 0, 40, max_windows=5, tsf=True)
+    for n in (13, 27, 60, 100):
+        rep.step(n)
+    smp, tsmp = rep.samples(tsf=True)
+    rep.sync_status()
+    o = run_oracle([g], [parent], 3, 200, 40, tsf=True)
+    osm, otsm = o.samples(tsf=True)
+    assert rel_err(tsmp[0].cpu().numpy(), otsm[0]) < TOL32
+    assert rel_err(smp[0].cpu().numpy(), osm[0]) < TOL32
+
+
+def test_bell_rates_and_events_parity():
+    import torch
+    groups, parents, run = wl.fene50(n_replicas=64, steps=300)
+    groups = groups + [wl.group(12, 8, 1e-4, wl.HOOKEAN, 1.0, 0.0, wl.PLANAR, 0.2, kT=1.5, stream_id=5)]
+    parents = parents + [wl.equilibrium_parent(12, seed=1)]
+    o = run_oracle(groups, parents, run["seed"], 300, 100)
+    rm, _ = o.average_forces()
+    rep = run_gpu(groups, parents, run["seed"], 300, 100)
+    announce("Bell rates on the oracle's profile")
+    for k0, xd in ((1e-6, 0.1), (0.3, 2.0)):
+        mean = torch.from_numpy(rm).cuda()
+        rates, rsum, ev = rep.bell_rates(mean, k0, xd, events=True)
+        r_rates, r_rsum, r_ev = o.bell_rates(rm, k0, xd, events=True)
+        assert rel_err(rates.cpu().numpy(), r_rates) < 1e-13
+        assert rel_err(rsum.cpu().numpy(), r_rsum) < 1e-13
+        assert np.array_equal(ev.cpu().numpy(), r_ev)
+    rep.sync_status()
+
+
+def test_fene_guard_counts_and_fp64_band():
+    N = 6
+    Q0 = 10.0
+    parent = np.zeros((N, 3))
+    steps = [0.5, np.sqrt(0.9995) * Q0, 1.0, np.sqrt(0.95) * Q0, 0.7]
+    parent[1:, 0] = np.cumsum(steps)
+    g = wl.group(N, 64, 1e-4, wl.FENE, 1.0, 100.0, wl.UNIAXIAL, 0.1)
+    announce("FENE guard")
+    rep = run_gpu([g], [parent], 13, 100, 50)
+    smp = rep.samples()[0].cpu().numpy()
+    counts = rep.guard_counts()
+    rep.sync_status()
+    o = run_oracle([g], [parent], 13, 100, 50)
+    assert counts[0] == o.clamps(0) and counts[0] >= 64
+    assert rel_err(smp, o.samples()[0]) < TOL32
+
+
+def test_invalid_parent_detected_on_device():
+    from paper_2206_05851_amd import ra
+    N = 4
+    parent = np.zeros((N, 3))
+    parent[1:, 0] = [1.0, 12.0, 13.0]            # bond of 11 > Q0 = 10
+    g = wl.group(N, 8, 1e-4, wl.FENE, 1.0, 100.0)
+    rep = run_gpu([g], [parent], 1, 50, 50)
+    with pytest.raises(ra.RAError) as ei:
+        rep.sync_status()
+    assert ei.value.code == ra.RA_EINVAL
+    # a valid parent on the same context clears the flag
+    parent[1:, 0] = [1.0, 2.0, 3.0]
+    rep.init_chains([parent])
+    rep.step(50)
+    rep.sync_status()
+
+
+def test_errors_on_capacity_and_order():
+    from paper_2206_05851_amd import ra
+    g = wl.group(5, 4, 1e-3)
+    rep = ra.Replicas([g], 0, sample_every=10, max_windows=2)
+    with pytest.raises(ra.RAError) as ei:
+        rep.step(5)
+    assert ei.value.code == ra.RA_ESTATE
+    rep.init_chains([wl.equilibrium_parent(5)])
+    rep.step(20)
+    with pytest.raises(ra.RAError) as ei:
+        rep.step(10)
+    assert ei.value.code == ra.RA_EINVAL
+    with pytest.raises(ra.RAError):
+        rep.backward(None, None)
