@@ -1,0 +1,291 @@
+"""Benchmark: replica-averaged Brownian dynamics on one MI355X.
+
+Headline workload (one "step" = the whole hot path once):
+  FENE chain, N = 50 beads, b = 100, uniaxial elongation at Wi = 2,
+  dt = 1e-4, 1024 replicas cloned from one equilibrium parent,
+  10^4 Euler-Maruyama steps, tension sampled every 100 steps (100 windows),
+  FP32 state, FP64 replica mean/std, Bell rates k0 = 1e-6, x = 0.1.
+  = ra_init_chains + ra_step(10^4) + ra_average_forces + ra_bell_rates,
+  inputs (parent conformation) resident in HBM before the timed region.
+
+value = replica*bead*steps per second (1024 * 50 * 10^4 per step / time).
+
+Also reported, each measured once after warm-up: the plain unbatched GPU path
+on the same workload (one launch per EM step, state in HBM; speedup), the
+adjoint (N = 100, 4096 replicas, 2000 steps, checkpoints every 100), the
+batched run (512 uneven FENE chains, one graph-captured persistent launch)
+and the 1000-bead transient (8192 replicas, 2e4 steps, RSF + TSF).
+The roofline object is for the fused forward kernel; its time is taken with
+HIP events on the stream the kernel runs on. cpu_baseline is the FP64 oracle
+on a bounded sample of the same workload, on the host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "replica·bead·steps/s and adjoint steps/s vs plain GPU path at 1e-4 rel err"
+
+# Peak VALU issue of one MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU lane-slots per replica*bead*step (quarter-rate ops count 4):
+# Philox4x32-10 100, uniform maps 16, Box-Muller 33, FENE bond update 34.
+SLOTS_PER_BEAD_STEP_FENE = 183
+SLOTS_PER_BEAD_STEP_HOOKEAN = 174
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
+def cpu_baseline(groups, parents, run, n_replicas):
+    """FP64 oracle on replicas [0, n_replicas) of the headline workload, all
+    steps, plus the replica averages and Bell rates (single thread)."""
+    from oracle import ora
+    g = dict(groups[0])
+    t0 = time.perf_counter()
+    o = ora.Oracle([g], run["seed"], run["sample_every"], run["steps"] // run["sample_every"])
+    o.set_replicas(0, 0, n_replicas)
+    o.init_chains(parents)
+    o.step(run["steps"])
+    mean, std = o.average_forces()
+    o.bell_rates(mean, run["k0"], run["x_dagger"])
+    dt = time.perf_counter() - t0
+    work = n_replicas * g["n_beads"] * run["steps"]
+    return work / dt, dt, o.samples()[0]
+
+
+def time_once(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-replicas", type=int, default=192)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2206_05851_amd import ra
+    from paper_2206_05851_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    groups, parents, run = wl.fene50()
+    g = groups[0]
+    R, N, T, S = g["n_replicas"], g["n_beads"], run["steps"], run["sample_every"]
+    W = T // S
+    parent = torch.from_numpy(np.ascontiguousarray(parents[0]).reshape(-1)).to(dev)
+    rep = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W, device=dev)
+    mean = torch.empty((W, N - 1), dtype=torch.float64, device=dev)
+    std = torch.empty_like(mean)
+    stream = torch.cuda.current_stream()
+    ev = []
+
+    def one_step(record):
+        rep.init_chains(parent)
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        rep.step(T)
+        if record:
+            e1.record(stream)
+            ev.append((e0, e1))
+        rep.average_forces(out=(mean, std))
+        return rep.bell_rates(mean, run["k0"], run["x_dagger"])
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        one_step(False)
+    rep.sync_status()
+    torch.cuda.synchronize()
+    log("timing %d steps" % args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rates, rsum = one_step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    rep.sync_status()
+    work_per_step = R * N * T
+    value = work_per_step * args.steps / elapsed
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    achieved = SLOTS_PER_BEAD_STEP_FENE * work_per_step / (kernel_ms * 1e-3)
+    log("fused: %.3f ms/step, kernel %.3f ms, %.3e replica-bead-steps/s" %
+        (1e3 * elapsed / args.steps, kernel_ms, value))
+    gpu_samples = rep.samples()[0]
+    tiles = rep.tile_info()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "replica·bead·steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded FENE equilibrium parent; Philox noise)",
+        "config": {"workload": "fene50: FENE N=50 b=100, uniaxial Wi=2 (rate=%.6g), dt=1e-4, "
+                               "R=1024, 10^4 steps, sample every 100, FP64 averages, Bell rates"
+                               % g["rate"],
+                   "global_batch": R, "seq_len": N, "parallelism": "none (1 GPU)",
+                   "beads_per_lane": tiles[0][0], "replicas_per_wave": tiles[1][0]},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+                     "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK_SLOTS,
+                     "traffic": None, "kernel": "fwd_kernel<float,4>", "kernel_ms": kernel_ms,
+                     "slots_per_replica_bead_step": SLOTS_PER_BEAD_STEP_FENE},
+    }
+
+    if not args.no_extras:
+        # plain unbatched path, same workload and counters
+        plain = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W,
+                            plain=True, device=dev)
+        pm = torch.empty_like(mean)
+        ps = torch.empty_like(mean)
+
+        def plain_step():
+            plain.init_chains(parent)
+            plain.step(T)
+            plain.average_forces(out=(pm, ps))
+            plain.bell_rates(pm, run["k0"], run["x_dagger"])
+
+        plain_step()
+        tp = min(time_once(plain_step) for _ in range(2))
+        plain.sync_status()
+        diff = torch.max(torch.abs(pm - mean) / mean).item()
+        out["plain_path"] = {"value": work_per_step / tp, "ms_per_step": 1e3 * tp,
+                             "speedup_fused_over_plain": (work_per_step / (elapsed / args.steps)) /
+                             (work_per_step / tp),
+                             "max_rel_diff_profile_vs_fused": diff}
+        plain.close()
+        log("plain: %.3f ms/step" % (1e3 * tp))
+
+        # adjoint workload
+        ag, ap_, arun = wl.adjoint100()
+        ga = ag[0]
+        apar = torch.from_numpy(np.ascontiguousarray(ap_[0]).reshape(-1)).to(dev)
+        adj = ra.Replicas(ag, arun["seed"], precision=32, sample_every=arun["sample_every"],
+                          max_windows=arun["steps"] // arun["sample_every"],
+                          checkpoint_every=arun["checkpoint_every"], max_steps=arun["steps"], device=dev)
+        gm = torch.ones((arun["steps"] // arun["sample_every"], ga["n_beads"] - 1),
+                        dtype=torch.float64, device=dev)
+
+        def adj_fwd():
+            adj.init_chains(apar)
+            adj.step(arun["steps"])
+
+        def adj_bwd():
+            m, _ = adj.average_forces()
+            return adj.backward(m, gm, None)
+
+        adj_fwd()
+        adj_bwd()
+        tf = time_once(adj_fwd)
+        tb = time_once(adj_bwd)
+        adj.sync_status()
+        awork = ga["n_replicas"] * ga["n_beads"] * arun["steps"]
+        out["adjoint"] = {"workload": "adjoint100: FENE N=100 b=100, uniaxial Wi=4, R=4096, dt=1e-4, "
+                                      "2000 steps, checkpoints every 100",
+                          "value": awork / tb, "unit": "replica·bead·steps/s (backward incl. recompute)",
+                          "forward_value": awork / tf, "backward_ms": 1e3 * tb, "forward_ms": 1e3 * tf}
+        adj.close()
+        log("adjoint: fwd %.2f ms bwd %.2f ms" % (1e3 * tf, 1e3 * tb))
+
+        # batched uneven chains, one graph-captured persistent launch per call
+        bg, bp, brun = wl.batched512()
+        bpar = torch.from_numpy(np.concatenate([np.ascontiguousarray(p).reshape(-1) for p in bp])).to(dev)
+        bat = ra.Replicas(bg, brun["seed"], precision=32, sample_every=brun["sample_every"],
+                          max_windows=brun["steps"] // brun["sample_every"], use_graph=True, device=dev)
+
+        def bat_step():
+            bat.init_chains(bpar)
+            bat.step(brun["steps"])
+            m, s = bat.average_forces()
+            bat.bell_rates(m, brun["k0"], brun["x_dagger"])
+
+        bat_step()
+        tbat = min(time_once(bat_step) for _ in range(2))
+        bat.sync_status()
+        bwork = sum(x["n_replicas"] * x["n_beads"] for x in bg) * brun["steps"]
+        out["batched"] = {"workload": "batched512: 512 FENE chains N~U{20..200}, b~U[50,200], planar "
+                                      "Wi~U[0.5,5] / shear Wi~U[1,50], R~U{16..256}, 5000 steps",
+                          "value": bwork / tbat, "ms_per_step": 1e3 * tbat, "graph": True}
+        bat.close()
+        log("batched: %.2f ms" % (1e3 * tbat))
+
+        # 1000-bead transient with TSF
+        lg, lp, lrun = wl.large1000()
+        lpar = torch.from_numpy(np.ascontiguousarray(lp[0]).reshape(-1)).to(dev)
+        big = ra.Replicas(lg, lrun["seed"], precision=32, sample_every=lrun["sample_every"],
+                          max_windows=lrun["steps"] // lrun["sample_every"], tsf=True, device=dev)
+
+        def big_step():
+            big.init_chains(lpar)
+            big.step(lrun["steps"])
+            m, s, tm, ts = big.average_forces(tsf=True)
+            big.bell_rates(m, lrun["k0"], lrun["x_dagger"], events=True)
+
+        big_step()
+        tbig = time_once(big_step)
+        big.sync_status()
+        lwork = lg[0]["n_replicas"] * lg[0]["n_beads"] * lrun["steps"]
+        out["large1000"] = {"workload": "large1000: FENE N=1000 b=400, start-up uniaxial Wi=10, R=8192, "
+                                        "dt=5e-5, 2e4 steps, RSF+TSF windows of 500, Bell events",
+                            "value": lwork / tbig, "ms_per_step": 1e3 * tbig}
+        big.close()
+        log("large1000: %.1f ms" % (1e3 * tbig))
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    if not args.no_cpu_baseline:
+        nr = args.cpu_replicas
+        log("cpu baseline: oracle on %d replicas x %d steps" % (nr, T))
+        rate, secs, ref = cpu_baseline(groups, parents, run, nr)
+        got = gpu_samples[:, :nr].cpu().numpy()
+        err = float(np.max(np.abs(got - ref) / np.abs(ref)))
+        out["cpu_baseline"] = {"value": rate, "unit": "replica·bead·steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "FP64 oracle, replicas 0..%d of 1024, all 10^4 steps, averages and "
+                                         "Bell rates, single thread (%.1f s; host has %d cores)"
+                                         % (nr - 1, secs, cpu_cores())}
+        out["max_rel_err_vs_oracle"] = err
+        log("cpu: %.3e replica-bead-steps/s, GPU vs oracle max rel err %.2e" % (rate, err))
+
+    rep.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,53 +62,107 @@ __device__ __forceinline__ void spring_factors(const Lane<T, M>& s, const GroupD
     }
 }
 
-// One Euler-Maruyama step of every slot of the lane, at global step n.
-// valid[m] masks slots that are not a spring of an active replica.
+// Normals of the M beads of the lane at one step (bead j uses the counter
+// (step, bead j, replica, tag|group)); independent of the chain state, so the
+// forward kernel generates several steps ahead for instruction-level parallelism.
+template <typename T, int M> struct Noise {
+    T x[M], y[M], z[M];
+};
+
+template <typename T, int M>
+__device__ __forceinline__ void gen_noise(Noise<T, M>& e, const GroupDev& G, uint32_t n, uint32_t bead0,
+                                          uint32_t replica, const RoundKeys& keys) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const Words w = philox10(n, bead0 + (uint32_t)m, replica, G.stream, keys);
+        normals3(w, e.x[m], e.y[m], e.z[m]);
+    }
+}
+
+// G_j = g_j Q_j of slot m (spring factor evaluated once per slot and step).
 template <typename T, int M, bool FENE>
-__device__ __forceinline__ void em_step(Lane<T, M>& s, const GroupDev& G, const bool (&valid)[M],
-                                        uint32_t n, uint32_t bead0, uint32_t replica,
-                                        uint32_t key0, uint32_t key1, int& clamps) {
+__device__ __forceinline__ void slot_force(const Lane<T, M>& s, const GroupDev& G, int m, T& fx, T& fy, T& fz,
+                                           int& clamps) {
+    T g = (T)1;
+    if constexpr (FENE) {
+        const T q2 = fmadd(s.qx[m], s.qx[m], fmadd(s.qy[m], s.qy[m], s.qz[m] * s.qz[m]));
+        g = fene_g(s.qx[m], s.qy[m], s.qz[m], q2, (T)G.inv_q0sq, G.inv_q0sq_d, clamps);
+    }
+    fx = g * s.qx[m];
+    fy = g * s.qy[m];
+    fz = g * s.qz[m];
+}
+
+// One Euler-Maruyama step of every slot of the lane. xi(m, x, y, z) yields
+// the normals of bead j0 + m (precomputed or generated on demand — the value
+// is the same). The update of slot m needs G and xi of slots m-1..m+1 only,
+// so both roll through three-slot windows; the lane's first/last slots meet
+// the neighbour lanes' through DPP. valid[m] masks slots that are not a
+// spring of an active replica.
+template <typename T, int M, bool FENE, typename NoiseFn>
+__device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, const GroupDev& G,
+                                             const bool (&valid)[M], int& clamps) {
     const Co<T> c{G};
-    T g[M];
-    spring_factors<T, M, FENE>(s, G, g, clamps);
-    T fx[M], fy[M], fz[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        fx[m] = g[m] * s.qx[m];
-        fy[m] = g[m] * s.qy[m];
-        fz[m] = g[m] * s.qz[m];
+    T f0x, f0y, f0z, flx, fly, flz;
+    slot_force<T, M, FENE>(s, G, 0, f0x, f0y, f0z, clamps);
+    if constexpr (M > 1) {
+        slot_force<T, M, FENE>(s, G, M - 1, flx, fly, flz, clamps);
+    } else {
+        flx = f0x; fly = f0y; flz = f0z;
     }
-    const T fpx = from_prev_lane(fx[M - 1]), fpy = from_prev_lane(fy[M - 1]), fpz = from_prev_lane(fz[M - 1]);
-    const T fnx = from_next_lane(fx[0]), fny = from_next_lane(fy[0]), fnz = from_next_lane(fz[0]);
-    T ex[M], ey[M], ez[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const Words w = philox10(n, bead0 + (uint32_t)m, replica, G.stream, key0, key1);
-        normals3(w, ex[m], ey[m], ez[m]);
-    }
-    const T enx = from_next_lane(ex[0]), eny = from_next_lane(ey[0]), enz = from_next_lane(ez[0]);
+    const T fpx = from_prev_lane(flx), fpy = from_prev_lane(fly), fpz = from_prev_lane(flz);
+    const T fnx = from_next_lane(f0x), fny = from_next_lane(f0y), fnz = from_next_lane(f0z);
+    T e0x, e0y, e0z;
+    xi(0, e0x, e0y, e0z);
+    const T enx = from_next_lane(e0x), eny = from_next_lane(e0y), enz = from_next_lane(e0z);
     const T kx = c.kx(), ky = c.ky(), kz = c.kz(), kxz = c.kxz(), cF = c.cF(), sg = c.sigma();
+    T Px = fpx, Py = fpy, Pz = fpz;   // G of slot m-1
+    T Cx = f0x, Cy = f0y, Cz = f0z;   // G of slot m
+    T Ex = e0x, Ey = e0y, Ez = e0z;   // xi of bead m
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        const T nx = (m + 1 < M) ? fx[m + 1 < M ? m + 1 : m] : fnx;
-        const T ny = (m + 1 < M) ? fy[m + 1 < M ? m + 1 : m] : fny;
-        const T nz = (m + 1 < M) ? fz[m + 1 < M ? m + 1 : m] : fnz;
-        const T px = (m > 0) ? fx[m > 0 ? m - 1 : 0] : fpx;
-        const T py = (m > 0) ? fy[m > 0 ? m - 1 : 0] : fpy;
-        const T pz = (m > 0) ? fz[m > 0 ? m - 1 : 0] : fpz;
-        const T lx = fmadd((T)-2, fx[m], nx + px);
-        const T ly = fmadd((T)-2, fy[m], ny + py);
-        const T lz = fmadd((T)-2, fz[m], nz + pz);
-        const T xnx = (m + 1 < M) ? ex[m + 1 < M ? m + 1 : m] : enx;
-        const T xny = (m + 1 < M) ? ey[m + 1 < M ? m + 1 : m] : eny;
-        const T xnz = (m + 1 < M) ? ez[m + 1 < M ? m + 1 : m] : enz;
-        const T ix = fmadd(kx, s.qx[m], fmadd(kxz, s.qz[m], fmadd(cF, lx, sg * (xnx - ex[m]))));
-        const T iy = fmadd(ky, s.qy[m], fmadd(cF, ly, sg * (xny - ey[m])));
-        const T iz = fmadd(kz, s.qz[m], fmadd(cF, lz, sg * (xnz - ez[m])));
+        T Nx, Ny, Nz, Xx, Xy, Xz;     // G of slot m+1, xi of bead m+1
+        if (m + 1 < M) {
+            if (m + 1 == M - 1) { Nx = flx; Ny = fly; Nz = flz; }
+            else slot_force<T, M, FENE>(s, G, m + 1 < M ? m + 1 : m, Nx, Ny, Nz, clamps);
+            xi(m + 1, Xx, Xy, Xz);
+        } else {
+            Nx = fnx; Ny = fny; Nz = fnz;
+            Xx = enx; Xy = eny; Xz = enz;
+        }
+        const T lx = fmadd((T)-2, Cx, Nx + Px);
+        const T ly = fmadd((T)-2, Cy, Ny + Py);
+        const T lz = fmadd((T)-2, Cz, Nz + Pz);
+        const T ix = fmadd(kx, s.qx[m], fmadd(kxz, s.qz[m], fmadd(cF, lx, sg * (Xx - Ex))));
+        const T iy = fmadd(ky, s.qy[m], fmadd(cF, ly, sg * (Xy - Ey)));
+        const T iz = fmadd(kz, s.qz[m], fmadd(cF, lz, sg * (Xz - Ez)));
         s.qx[m] = valid[m] ? s.qx[m] + ix : (T)0;
         s.qy[m] = valid[m] ? s.qy[m] + iy : (T)0;
         s.qz[m] = valid[m] ? s.qz[m] + iz : (T)0;
+        Px = Cx; Py = Cy; Pz = Cz;
+        Cx = Nx; Cy = Ny; Cz = Nz;
+        Ex = Xx; Ey = Xy; Ez = Xz;
     }
+}
+
+template <typename T, int M, bool FENE>
+__device__ __forceinline__ void physics_step(Lane<T, M>& s, const Noise<T, M>& e, const GroupDev& G,
+                                             const bool (&valid)[M], int& clamps) {
+    physics_step_fn<T, M, FENE>(
+        s, [&](int m, T& x, T& y, T& z) { x = e.x[m]; y = e.y[m]; z = e.z[m]; }, G, valid, clamps);
+}
+
+// One full Euler-Maruyama step at global step n (noise + update).
+template <typename T, int M, bool FENE>
+__device__ __forceinline__ void em_step(Lane<T, M>& s, const GroupDev& G, const bool (&valid)[M],
+                                        uint32_t n, uint32_t bead0, uint32_t replica,
+                                        const RoundKeys& keys, int& clamps) {
+    physics_step_fn<T, M, FENE>(
+        s,
+        [&](int m, T& x, T& y, T& z) {
+            normals3(philox10(n, bead0 + (uint32_t)m, replica, G.stream, keys), x, y, z);
+        },
+        G, valid, clamps);
 }
 
 // Tension f_j = H g_j |Q_j| (Eq. 4, zero rest length) of every slot.

@@ -20,28 +20,51 @@ struct Words {
     uint32_t x, y, z, w;
 };
 
+// Round keys of one seed: key + r * (Weyl increments), r = 0..9. Built once
+// per kernel so the step loop does not redo the key schedule.
+struct RoundKeys {
+    uint32_t k0[10], k1[10];
+};
+
+__device__ __forceinline__ RoundKeys round_keys(uint32_t key0, uint32_t key1) {
+    RoundKeys k;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        k.k0[r] = key0 + (uint32_t)r * 0x9E3779B9u;
+        k.k1[r] = key1 + (uint32_t)r * 0xBB67AE85u;
+    }
+    return k;
+}
+
 __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                          uint32_t k0, uint32_t k1) {
+                                          const RoundKeys& k) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k.k0[round];
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k.k1[round];
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
         c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
     }
     return Words{c0, c1, c2, c3};
 }
 
+__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t key0, uint32_t key1) {
+    return philox10(c0, c1, c2, c3, round_keys(key0, key1));
+}
+
 // Uniform in (0,1): the top 23 bits j of a word give (2j + 1) 2^-24 — an odd
 // integer below 2^24 times a power of two, hence exact in binary32 and binary64.
+// FP32: one v_alignbit_b32 forms the binary32 word of 1 + j 2^-23 (exponent
+// bits 0x7F above the top 23 bits of x); subtracting 1 - 2^-24 is exact
+// (Sterbenz) and leaves (2j + 1) 2^-24.
 __device__ __forceinline__ float u01_f32(uint32_t x) {
-    return (float)((x >> 8) | 1u) * 0x1p-24f;
+    const uint32_t one_plus = __builtin_amdgcn_alignbit(0x7Fu, x, 9u);
+    return __builtin_bit_cast(float, one_plus) - 0x1.fffffep-1f;
 }
 __device__ __forceinline__ double u01_f64(uint32_t x) {
     return (double)((x >> 8) | 1u) * 0x1p-24;

@@ -354,11 +354,15 @@ static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps) {
     a.smp_total = c->smp_total;
     a.state_total = c->state_total;
     a.step0 = c->dstep;
-    a.n_steps = n_steps;
     a.status = c->status;
     a.clamps = c->clamps;
-    HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->stream));
-    HIPCHK(c, launch_advance(c->dstep, n_steps, c->stream));
+    // the kernel counts steps in 32-bit ints: split very long calls
+    const int64_t chunk = (int64_t)1 << 30;
+    for (int64_t done = 0; done < n_steps; done += chunk) {
+        a.n_steps = std::min(chunk, n_steps - done);
+        HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->stream));
+        HIPCHK(c, launch_advance(c->dstep, a.n_steps, c->stream));
+    }
     return RA_OK;
 }
 

@@ -17,63 +17,94 @@ namespace ra {
 // ---------------------------------------------------------------------------
 // Fused persistent forward: all n_steps of one work item in registers.
 // ---------------------------------------------------------------------------
+// Noise run-ahead per beads-per-lane: with one bead per lane the wave has
+// little independent work per step, so U steps of noise (U independent Philox
+// chains per lane) are generated before the U physics steps consume them.
+template <int M> struct RunAhead { static constexpr int U = M == 1 ? 4 : (M == 2 ? 2 : 1); };
+
 template <typename T, int M, bool FENE>
-__device__ void run_forward(const FwdArgs& a, const GroupDev& G, int k_first, int64_t n0) {
+__device__ void run_forward(const FwdArgs& a, const GroupDev& G, int k_first, int64_t n0_64) {
+    constexpr int U = RunAhead<M>::U;
     const TileGeom tg = tile_geom(G, k_first, M);
+    const RoundKeys keys = round_keys(a.key0, a.key1);
     Lane<T, M> s;
     bool valid[M];
     load_lane<T, M>(s, valid, (const T*)a.state, G, tg);
     const int nm1 = G.N - 1;
-    double tacc[M];
+    const uint32_t n0 = (uint32_t)n0_64;       // total steps stay below 2^32
+    const int S = a.S, K = a.K;
     const bool tsf = a.tsf != nullptr;
+    // per-lane output cursors, bumped once per window / checkpoint
+    const int64_t lane_off = G.smp_off + (int64_t)tg.k * nm1 + tg.j0;
+    T* smp_w = (T*)a.samples + (int64_t)(n0 / (uint32_t)S) * a.smp_total + lane_off;
+    T* tsf_w = tsf ? (T*)a.tsf + (int64_t)(n0 / (uint32_t)S) * a.smp_total + lane_off : nullptr;
+    T* ck_w = K > 0 ? (T*)a.ckpt + (int64_t)((n0 + (uint32_t)K - 1) / (uint32_t)K) * a.state_total : nullptr;
+    int smp_ctr = (int)(n0 % (uint32_t)S);
+    int ck_ctr = K > 0 ? (int)(n0 % (uint32_t)K) : 1;
+    double tacc[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        tacc[m] = 0.0;
-        if (tsf && valid[m]) tacc[m] = a.tsf_acc[G.smp_off + (int64_t)tg.k * nm1 + tg.j0 + m];
-    }
+    for (int m = 0; m < M; ++m) tacc[m] = (tsf && valid[m]) ? a.tsf_acc[lane_off + m] : 0.0;
     int clamps = 0;
-    int smp_ctr = (int)(n0 % a.S);
-    int ck_ctr = a.K > 0 ? (int)(n0 % a.K) : 1;
-    T* __restrict__ samples = (T*)a.samples;
-    T* __restrict__ tsfo = (T*)a.tsf;
-    T* __restrict__ ckpt = (T*)a.ckpt;
-    for (int64_t i = 0; i < a.n_steps; ++i) {
-        const int64_t n = n0 + i;
-        if (a.K > 0) {
-            if (ck_ctr == 0) store_lane<T, M>(s, valid, ckpt + (n / a.K) * a.state_total, G, tg);
-            if (++ck_ctr == a.K) ck_ctr = 0;
+
+    auto one_step = [&](auto&& xi) {
+        if (K > 0) {
+            if (ck_ctr == 0) {
+                store_lane<T, M>(s, valid, ck_w, G, tg);
+                ck_w += a.state_total;
+            }
+            if (++ck_ctr == K) ck_ctr = 0;
         }
-        em_step<T, M, FENE>(s, G, valid, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, a.key0, a.key1,
-                            clamps);
-        const bool window_end = (++smp_ctr == a.S);
+        physics_step_fn<T, M, FENE>(s, xi, G, valid, clamps);
+        const bool window_end = (++smp_ctr == S);
         if (window_end) smp_ctr = 0;
         if (tsf || window_end) {
             T f[M];
             tensions<T, M, FENE>(s, G, f);
-            const int64_t w = (n + 1) / a.S - 1;
             bool bad = false;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                if (!valid[m]) continue;
-                const int64_t o = w * a.smp_total + G.smp_off + (int64_t)tg.k * nm1 + tg.j0 + m;
                 if (tsf) tacc[m] += (double)f[m];
-                if (window_end) {
-                    samples[o] = f[m];
+                if (window_end && valid[m]) {
+                    smp_w[m] = f[m];
                     bad |= !__builtin_isfinite(f[m]);
-                    if (tsf) {
-                        tsfo[o] = (T)(tacc[m] / (double)a.S);
-                        tacc[m] = 0.0;
-                    }
+                    if (tsf) tsf_w[m] = (T)(tacc[m] / (double)S);
                 }
+                if (window_end) tacc[m] = 0.0;
+            }
+            if (window_end) {
+                smp_w += a.smp_total;
+                if (tsf) tsf_w += a.smp_total;
             }
             if (bad) atomicOr(a.status, 2);
         }
+    };
+
+    const int nsteps = (int)a.n_steps;
+    int i = 0;
+    if constexpr (U > 1) {
+        for (; i + U <= nsteps; i += U) {
+            Noise<T, M> e[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                gen_noise<T, M>(e[u], G, n0 + (uint32_t)(i + u), (uint32_t)tg.j0, (uint32_t)tg.k, keys);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const Noise<T, M>& eu = e[u];
+                one_step([&](int m, T& x, T& y, T& z) { x = eu.x[m]; y = eu.y[m]; z = eu.z[m]; });
+            }
+        }
+    }
+    for (; i < nsteps; ++i) {
+        const uint32_t n = n0 + (uint32_t)i;
+        one_step([&](int m, T& x, T& y, T& z) {
+            normals3(philox10(n, (uint32_t)(tg.j0 + m), (uint32_t)tg.k, G.stream, keys), x, y, z);
+        });
     }
     store_lane<T, M>(s, valid, (T*)a.state, G, tg);
     if (tsf) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            if (valid[m]) a.tsf_acc[G.smp_off + (int64_t)tg.k * nm1 + tg.j0 + m] = tacc[m];
+            if (valid[m]) a.tsf_acc[lane_off + m] = tacc[m];
     }
     flush_clamps(clamps, a.clamps + (&G - a.groups));
 }
@@ -84,8 +115,11 @@ __device__ __forceinline__ void dispatch_spring(const FwdArgs& a, const GroupDev
     else run_forward<T, M, false>(a, G, k_first, n0);
 }
 
-template <typename T, int FAMILY>
-__global__ __launch_bounds__(256) void fwd_kernel(FwdArgs a) {
+// WAVES_PER_EU = 1 leaves register allocation to the compiler. (Asking the
+// 16-bead family for 3-4 resident waves makes it spill inside the step loop.)
+template <typename T, int FAMILY, int WAVES_PER_EU>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
+void fwd_kernel(FwdArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int item = (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
     if (item >= a.n_items) return;
@@ -404,16 +438,20 @@ static dim3 grid1d(int64_t n, int block) {
     return dim3((unsigned)b);
 }
 
+#ifndef FAMILY16_WAVES
+#define FAMILY16_WAVES 1
+#endif
+
 hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     const int wpb = waves_per_block;
     dim3 grid((a.n_items + wpb - 1) / wpb), block(WAVE * wpb);
     if (precision == 64) {
-        hipLaunchKernelGGL((fwd_kernel<double, 4>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((fwd_kernel<double, 4, 1>), grid, block, 0, st, a);
     } else if (family == 4) {
-        hipLaunchKernelGGL((fwd_kernel<float, 4>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((fwd_kernel<float, 4, 1>), grid, block, 0, st, a);
     } else {
-        hipLaunchKernelGGL((fwd_kernel<float, 16>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((fwd_kernel<float, 16, FAMILY16_WAVES>), grid, block, 0, st, a);
     }
     return hipGetLastError();
 }
