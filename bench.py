@@ -31,12 +31,15 @@ if ROOT not in sys.path:
 
 METRIC = "replica·bead·steps/s and adjoint steps/s vs plain GPU path at 1e-4 rel err"
 
-# Peak VALU issue of one MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
-# Algorithmic VALU lane-slots per replica*bead*step (quarter-rate ops count 4):
-# Philox4x32-10 100, uniform maps 16, Box-Muller 33, FENE bond update 34.
-SLOTS_PER_BEAD_STEP_FENE = 183
-SLOTS_PER_BEAD_STEP_HOOKEAN = 174
+# Peak VALU lane-op rate of one MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 ops per
+# lane per issue (dual issue / packed; the published 157.3 TFLOP/s FP32 vector
+# peak counted as 2 flops per lane-op) x 2.4 GHz = 78.6 T lane-ops/s.
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2 * 2.4e9
+# Algorithmic VALU lane-ops per replica*bead*step, in FMA-issue equivalents
+# (transcendentals count 2, as measured on gfx950): Philox4x32-10 60 (20
+# 32x32->64 products, 40 XORs), uniform maps 8, Box-Muller 19, FENE bond
+# update 32 (Hookean 26).
+OPS_PER_BEAD_STEP_FENE = 119
 
 
 def log(msg):
@@ -139,7 +142,7 @@ def main():
     work_per_step = R * N * T
     value = work_per_step * args.steps / elapsed
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    achieved = SLOTS_PER_BEAD_STEP_FENE * work_per_step / (kernel_ms * 1e-3)
+    achieved = OPS_PER_BEAD_STEP_FENE * work_per_step / (kernel_ms * 1e-3)
     log("fused: %.3f ms/step, kernel %.3f ms, %.3e replica-bead-steps/s" %
         (1e3 * elapsed / args.steps, kernel_ms, value))
     gpu_samples = rep.samples()[0]
@@ -155,10 +158,10 @@ def main():
                                % g["rate"],
                    "global_batch": R, "seq_len": N, "parallelism": "none (1 GPU)",
                    "beads_per_lane": tiles[0][0], "replicas_per_wave": tiles[1][0]},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
-                     "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK_SLOTS,
-                     "traffic": None, "kernel": "fwd_kernel<float,4>", "kernel_ms": kernel_ms,
-                     "slots_per_replica_bead_step": SLOTS_PER_BEAD_STEP_FENE},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+                     "unit": "T VALU lane-ops/s", "frac": achieved / VALU_PEAK_LANE_OPS,
+                     "traffic": None, "kernel": "fwd_kernel<float,4,1>", "kernel_ms": kernel_ms,
+                     "lane_ops_per_replica_bead_step": OPS_PER_BEAD_STEP_FENE},
     }
 
     if not args.no_extras:

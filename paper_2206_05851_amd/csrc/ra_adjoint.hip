@@ -170,13 +170,15 @@ __device__ void run_adjoint(const AdjArgs& a, const GroupDev& G, int item, int k
     const int64_t n_seg = (a.n_end + K - 1) / K;
     int dummy = 0;
     const RoundKeys keys = round_keys(a.key0, a.key1);
+    SlotCoef<float, M> kc;
     for (int64_t sgi = n_seg - 1; sgi >= 0; --sgi) {
         const int64_t s0 = sgi * K;
         const int64_t s1 = min(a.n_end, s0 + K);
         load_lane<float, M>(s, valid, (const float*)a.ckpt + sgi * a.state_total, G, tg);
+        kc = slot_coef<float, M>(G, valid);
         for (int64_t n = s0; n < s1; ++n) {
             seg_store<M>(seg, (int)(n - s0), s, lane);
-            em_step<float, M, FENE>(s, G, valid, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, keys, dummy);
+            em_step<float, M, FENE>(s, G, valid, kc, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, keys, dummy);
         }
         // s = Q^{s1}; sweep n = s1-1 .. s0, injecting at states n+1 that were sampled
         for (int64_t n = s1 - 1; n >= s0; --n) {

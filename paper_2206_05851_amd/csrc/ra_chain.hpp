@@ -93,6 +93,29 @@ __device__ __forceinline__ void slot_force(const Lane<T, M>& s, const GroupDev& 
     fz = g * s.qz[m];
 }
 
+// Per-slot force and noise coefficients (H dt/zeta and sigma), zero on slots
+// that are not a spring of an active replica. Such slots hold Q = 0, so with
+// zero coefficients their increment is exactly 0 and they stay 0 without a
+// per-step select. Used for up to 4 slots per lane; wider lanes keep the
+// coefficients in scalar registers and select instead.
+template <typename T, int M> struct SlotCoef {
+    T cF[M], sg[M];
+};
+
+template <typename T, int M>
+__device__ __forceinline__ SlotCoef<T, M> slot_coef(const GroupDev& G, const bool (&valid)[M]) {
+    const Co<T> c{G};
+    SlotCoef<T, M> k;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        k.cF[m] = valid[m] ? c.cF() : (T)0;
+        k.sg[m] = valid[m] ? c.sigma() : (T)0;
+    }
+    return k;
+}
+
+template <int M> struct MaskedSlots { static constexpr bool value = M <= 4; };
+
 // One Euler-Maruyama step of every slot of the lane. xi(m, x, y, z) yields
 // the normals of bead j0 + m (precomputed or generated on demand — the value
 // is the same). The update of slot m needs G and xi of slots m-1..m+1 only,
@@ -101,7 +124,8 @@ __device__ __forceinline__ void slot_force(const Lane<T, M>& s, const GroupDev& 
 // spring of an active replica.
 template <typename T, int M, bool FENE, typename NoiseFn>
 __device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, const GroupDev& G,
-                                             const bool (&valid)[M], int& clamps) {
+                                                const bool (&valid)[M], const SlotCoef<T, M>& kc,
+                                                int& clamps) {
     const Co<T> c{G};
     T f0x, f0y, f0z, flx, fly, flz;
     slot_force<T, M, FENE>(s, G, 0, f0x, f0y, f0z, clamps);
@@ -115,7 +139,7 @@ __device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, con
     T e0x, e0y, e0z;
     xi(0, e0x, e0y, e0z);
     const T enx = from_next_lane(e0x), eny = from_next_lane(e0y), enz = from_next_lane(e0z);
-    const T kx = c.kx(), ky = c.ky(), kz = c.kz(), kxz = c.kxz(), cF = c.cF(), sg = c.sigma();
+    const T kx = c.kx(), ky = c.ky(), kz = c.kz(), kxz = c.kxz();
     T Px = fpx, Py = fpy, Pz = fpz;   // G of slot m-1
     T Cx = f0x, Cy = f0y, Cz = f0z;   // G of slot m
     T Ex = e0x, Ey = e0y, Ez = e0z;   // xi of bead m
@@ -133,12 +157,21 @@ __device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, con
         const T lx = fmadd((T)-2, Cx, Nx + Px);
         const T ly = fmadd((T)-2, Cy, Ny + Py);
         const T lz = fmadd((T)-2, Cz, Nz + Pz);
+        constexpr bool masked = MaskedSlots<M>::value;
+        const T cF = masked ? kc.cF[m] : c.cF();
+        const T sg = masked ? kc.sg[m] : c.sigma();
         const T ix = fmadd(kx, s.qx[m], fmadd(kxz, s.qz[m], fmadd(cF, lx, sg * (Xx - Ex))));
         const T iy = fmadd(ky, s.qy[m], fmadd(cF, ly, sg * (Xy - Ey)));
         const T iz = fmadd(kz, s.qz[m], fmadd(cF, lz, sg * (Xz - Ez)));
-        s.qx[m] = valid[m] ? s.qx[m] + ix : (T)0;
-        s.qy[m] = valid[m] ? s.qy[m] + iy : (T)0;
-        s.qz[m] = valid[m] ? s.qz[m] + iz : (T)0;
+        if constexpr (masked) {
+            s.qx[m] += ix;
+            s.qy[m] += iy;
+            s.qz[m] += iz;
+        } else {
+            s.qx[m] = valid[m] ? s.qx[m] + ix : (T)0;
+            s.qy[m] = valid[m] ? s.qy[m] + iy : (T)0;
+            s.qz[m] = valid[m] ? s.qz[m] + iz : (T)0;
+        }
         Px = Cx; Py = Cy; Pz = Cz;
         Cx = Nx; Cy = Ny; Cz = Nz;
         Ex = Xx; Ey = Xy; Ez = Xz;
@@ -147,22 +180,22 @@ __device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, con
 
 template <typename T, int M, bool FENE>
 __device__ __forceinline__ void physics_step(Lane<T, M>& s, const Noise<T, M>& e, const GroupDev& G,
-                                             const bool (&valid)[M], int& clamps) {
+                                             const bool (&valid)[M], const SlotCoef<T, M>& kc, int& clamps) {
     physics_step_fn<T, M, FENE>(
-        s, [&](int m, T& x, T& y, T& z) { x = e.x[m]; y = e.y[m]; z = e.z[m]; }, G, valid, clamps);
+        s, [&](int m, T& x, T& y, T& z) { x = e.x[m]; y = e.y[m]; z = e.z[m]; }, G, valid, kc, clamps);
 }
 
 // One full Euler-Maruyama step at global step n (noise + update).
 template <typename T, int M, bool FENE>
 __device__ __forceinline__ void em_step(Lane<T, M>& s, const GroupDev& G, const bool (&valid)[M],
-                                        uint32_t n, uint32_t bead0, uint32_t replica,
-                                        const RoundKeys& keys, int& clamps) {
+                                        const SlotCoef<T, M>& kc, uint32_t n, uint32_t bead0,
+                                        uint32_t replica, const RoundKeys& keys, int& clamps) {
     physics_step_fn<T, M, FENE>(
         s,
         [&](int m, T& x, T& y, T& z) {
             normals3(philox10(n, bead0 + (uint32_t)m, replica, G.stream, keys), x, y, z);
         },
-        G, valid, clamps);
+        G, valid, kc, clamps);
 }
 
 // Tension f_j = H g_j |Q_j| (Eq. 4, zero rest length) of every slot.
@@ -185,13 +218,23 @@ struct TileGeom {
     int j0;            // first bead/spring of the lane
 };
 
+// With UNIFORM_K (one replica per wavefront, P = 1) every lane carries the
+// wave-uniform replica index, so the replica word of the Philox counter stays
+// in a scalar register and part of the first rounds runs on the scalar unit.
+template <bool UNIFORM_K = false>
 __device__ __forceinline__ TileGeom tile_geom(const GroupDev& G, int k_first, int M) {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int seg = lane / G.L;
     TileGeom tg;
-    tg.t = lane - seg * G.L;
-    tg.k = k_first + seg;
-    tg.rep_ok = (seg < G.P) && (tg.k < G.R);
+    if constexpr (UNIFORM_K) {
+        tg.t = lane;
+        tg.k = k_first;
+        tg.rep_ok = (lane < G.L) && (k_first < G.R);
+    } else {
+        const int seg = lane / G.L;
+        tg.t = lane - seg * G.L;
+        tg.k = k_first + seg;
+        tg.rep_ok = (seg < G.P) && (tg.k < G.R);
+    }
     tg.j0 = tg.t * M;
     return tg;
 }

@@ -136,13 +136,18 @@ constexpr float FENE_FP64_BAND = 0.9f;  // FP32 path recomputes s and 1/(1-s) in
 __device__ __forceinline__ float fene_g(float qx, float qy, float qz, float q2, float inv_q0sq,
                                         double inv_q0sq_d, int& clamped) {
     const float s = q2 * inv_q0sq;
-    if (__builtin_expect(s > FENE_FP64_BAND, 0)) {
-        const double dx = qx, dy = qy, dz = qz;
-        double sd = (dx * dx + dy * dy + dz * dz) * inv_q0sq_d;
-        if (sd > 1.0 - FENE_DELTA) { sd = 1.0 - FENE_DELTA; clamped += 1; }
-        return (float)(1.0 / (1.0 - sd));
+    float g = fast_rcp(1.0f - s);
+    // wave vote: the common case (no lane near full extension) costs one
+    // compare and a scalar branch instead of an exec-mask save/restore
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(s > FENE_FP64_BAND) != 0, 0)) {
+        if (s > FENE_FP64_BAND) {
+            const double dx = qx, dy = qy, dz = qz;
+            double sd = (dx * dx + dy * dy + dz * dz) * inv_q0sq_d;
+            if (sd > 1.0 - FENE_DELTA) { sd = 1.0 - FENE_DELTA; clamped += 1; }
+            g = (float)(1.0 / (1.0 - sd));
+        }
     }
-    return fast_rcp(1.0f - s);
+    return g;
 }
 __device__ __forceinline__ double fene_g(double qx, double qy, double qz, double q2, double,
                                          double inv_q0sq_d, int& clamped) {

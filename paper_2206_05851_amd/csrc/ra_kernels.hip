@@ -22,97 +22,159 @@ namespace ra {
 // chains per lane) are generated before the U physics steps consume them.
 template <int M> struct RunAhead { static constexpr int U = M == 1 ? 4 : (M == 2 ? 2 : 1); };
 
-template <typename T, int M, bool FENE>
-__device__ void run_forward(const FwdArgs& a, const GroupDev& G, int k_first, int64_t n0_64) {
+// Fused persistent forward over all n_steps of one work item. The step loop is
+// cut into segments between events (window end, checkpoint), so the inner
+// loop holds nothing but noise generation and the bond update (plus the
+// per-step tension sum when TSF is on).
+template <typename T, int M, bool FENE, bool UNIFORM_K, bool TSF>
+__device__ __forceinline__ void run_forward(const FwdArgs& a, const GroupDev& G, int k_first, int64_t n0_64) {
     constexpr int U = RunAhead<M>::U;
-    const TileGeom tg = tile_geom(G, k_first, M);
+    // Kernel arguments are read once into locals: the step lambdas below must
+    // not take the address of the by-value argument block (that would copy it
+    // to scratch memory).
+    const int S = a.S, K = a.K;
+    const int64_t smp_total = a.smp_total, state_total = a.state_total;
+    T* const state = (T*)a.state;
+    int32_t* const status = a.status;
+    unsigned long long* const clamp_ctr = a.clamps + (&G - a.groups);
+    const int n_steps = (int)a.n_steps;
+    const TileGeom tg = tile_geom<UNIFORM_K>(G, k_first, M);
     const RoundKeys keys = round_keys(a.key0, a.key1);
     Lane<T, M> s;
     bool valid[M];
-    load_lane<T, M>(s, valid, (const T*)a.state, G, tg);
+    load_lane<T, M>(s, valid, state, G, tg);
+    const SlotCoef<T, M> kc = slot_coef<T, M>(G, valid);
     const int nm1 = G.N - 1;
     const uint32_t n0 = (uint32_t)n0_64;       // total steps stay below 2^32
-    const int S = a.S, K = a.K;
-    const bool tsf = a.tsf != nullptr;
+    const uint32_t bead0 = (uint32_t)tg.j0, rep = (uint32_t)tg.k;
     // per-lane output cursors, bumped once per window / checkpoint
     const int64_t lane_off = G.smp_off + (int64_t)tg.k * nm1 + tg.j0;
-    T* smp_w = (T*)a.samples + (int64_t)(n0 / (uint32_t)S) * a.smp_total + lane_off;
-    T* tsf_w = tsf ? (T*)a.tsf + (int64_t)(n0 / (uint32_t)S) * a.smp_total + lane_off : nullptr;
-    T* ck_w = K > 0 ? (T*)a.ckpt + (int64_t)((n0 + (uint32_t)K - 1) / (uint32_t)K) * a.state_total : nullptr;
-    int smp_ctr = (int)(n0 % (uint32_t)S);
-    int ck_ctr = K > 0 ? (int)(n0 % (uint32_t)K) : 1;
-    double tacc[M];
+    T* smp_w = (T*)a.samples + (int64_t)(n0 / (uint32_t)S) * smp_total + lane_off;
+    T* tsf_w = TSF ? (T*)a.tsf + (int64_t)(n0 / (uint32_t)S) * smp_total + lane_off : nullptr;
+    T* ck_w = K > 0 ? (T*)a.ckpt + (int64_t)((n0 + (uint32_t)K - 1) / (uint32_t)K) * state_total : nullptr;
+    double* const tacc_g = TSF ? a.tsf_acc + lane_off : nullptr;
+    int to_smp = S - (int)(n0 % (uint32_t)S);                              // steps to the next window end
+    int to_ck = K > 0 ? (int)((K - (int)(n0 % (uint32_t)K)) % K) : INT32_MAX;  // steps to the next checkpoint
+    // TSF: per-step tensions are summed in registers over at most TSF_FLUSH
+    // steps (relative error below 64 ulp) and folded into the FP64 window sums
+    // kept in global memory, so no FP64 accumulator stays live in the loop
+    constexpr int TSF_FLUSH = 64;
+    T tpart[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) tacc[m] = (tsf && valid[m]) ? a.tsf_acc[lane_off + m] : 0.0;
+    for (int m = 0; m < M; ++m) tpart[m] = (T)0;
+    auto flush_tsf = [&](bool window_end) {
+        if constexpr (TSF) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (valid[m]) {
+                    const double acc = tacc_g[m] + (double)tpart[m];
+                    if (window_end) {
+                        tsf_w[m] = (T)(acc / (double)S);
+                        tacc_g[m] = 0.0;
+                    } else {
+                        tacc_g[m] = acc;
+                    }
+                }
+                tpart[m] = (T)0;
+            }
+        }
+    };
     int clamps = 0;
 
-    auto one_step = [&](auto&& xi) {
-        if (K > 0) {
-            if (ck_ctr == 0) {
-                store_lane<T, M>(s, valid, ck_w, G, tg);
-                ck_w += a.state_total;
-            }
-            if (++ck_ctr == K) ck_ctr = 0;
+    auto accumulate_tsf = [&]() {
+        if constexpr (TSF) {
+            T f[M];
+            tensions<T, M, FENE>(s, G, f);
+#pragma unroll
+            for (int m = 0; m < M; ++m) tpart[m] += f[m];
         }
-        physics_step_fn<T, M, FENE>(s, xi, G, valid, clamps);
-        const bool window_end = (++smp_ctr == S);
-        if (window_end) smp_ctr = 0;
-        if (tsf || window_end) {
+    };
+    auto run_steps = [&](uint32_t n, int len) {   // len steps starting at global step n
+        int i = 0;
+        if constexpr (U > 1) {
+            for (; i + U <= len; i += U) {
+                Noise<T, M> e[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) gen_noise<T, M>(e[u], G, n + (uint32_t)(i + u), bead0, rep, keys);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    physics_step<T, M, FENE>(s, e[u], G, valid, kc, clamps);
+                    accumulate_tsf();
+                }
+            }
+        }
+        for (; i < len; ++i) {
+            em_step<T, M, FENE>(s, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps);
+            accumulate_tsf();
+        }
+    };
+
+    int left = n_steps;
+    int to_flush = TSF_FLUSH;
+    uint32_t n = n0;
+    while (left > 0) {
+        if (to_ck == 0) {                      // checkpoint before step n
+            store_lane<T, M>(s, valid, ck_w, G, tg);
+            ck_w += state_total;
+            to_ck = K;
+        }
+        int len = min(left, min(to_smp, to_ck));
+        if constexpr (TSF) len = min(len, to_flush);
+        run_steps(n, len);
+        n += (uint32_t)len;
+        left -= len;
+        to_ck -= len;
+        to_smp -= len;
+        to_flush -= len;
+        if (to_smp == 0) {                     // window end after step n - 1
             T f[M];
             tensions<T, M, FENE>(s, G, f);
             bool bad = false;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                if (tsf) tacc[m] += (double)f[m];
-                if (window_end && valid[m]) {
+                if (valid[m]) {
                     smp_w[m] = f[m];
                     bad |= !__builtin_isfinite(f[m]);
-                    if (tsf) tsf_w[m] = (T)(tacc[m] / (double)S);
                 }
-                if (window_end) tacc[m] = 0.0;
             }
-            if (window_end) {
-                smp_w += a.smp_total;
-                if (tsf) tsf_w += a.smp_total;
-            }
-            if (bad) atomicOr(a.status, 2);
-        }
-    };
-
-    const int nsteps = (int)a.n_steps;
-    int i = 0;
-    if constexpr (U > 1) {
-        for (; i + U <= nsteps; i += U) {
-            Noise<T, M> e[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                gen_noise<T, M>(e[u], G, n0 + (uint32_t)(i + u), (uint32_t)tg.j0, (uint32_t)tg.k, keys);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const Noise<T, M>& eu = e[u];
-                one_step([&](int m, T& x, T& y, T& z) { x = eu.x[m]; y = eu.y[m]; z = eu.z[m]; });
-            }
+            flush_tsf(true);
+            to_flush = TSF_FLUSH;
+            smp_w += smp_total;
+            if constexpr (TSF) tsf_w += smp_total;
+            if (bad) atomicOr(status, 2);
+            to_smp = S;
+        } else if (TSF && (to_flush == 0 || left == 0)) {
+            flush_tsf(false);
+            to_flush = TSF_FLUSH;
         }
     }
-    for (; i < nsteps; ++i) {
-        const uint32_t n = n0 + (uint32_t)i;
-        one_step([&](int m, T& x, T& y, T& z) {
-            normals3(philox10(n, (uint32_t)(tg.j0 + m), (uint32_t)tg.k, G.stream, keys), x, y, z);
-        });
-    }
-    store_lane<T, M>(s, valid, (T*)a.state, G, tg);
-    if (tsf) {
-#pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (valid[m]) a.tsf_acc[lane_off + m] = tacc[m];
-    }
-    flush_clamps(clamps, a.clamps + (&G - a.groups));
+    store_lane<T, M>(s, valid, state, G, tg);
+    flush_clamps(clamps, clamp_ctr);
 }
 
 template <typename T, int M>
 __device__ __forceinline__ void dispatch_spring(const FwdArgs& a, const GroupDev& G, int k_first, int64_t n0) {
-    if (G.spring == 1) run_forward<T, M, true>(a, G, k_first, n0);
-    else run_forward<T, M, false>(a, G, k_first, n0);
+    const bool tsf = a.tsf != nullptr;
+    if constexpr (sizeof(T) == 8) {           // FP64 correctness path: fewer variants
+        if (G.spring == 1) {
+            if (tsf) run_forward<T, M, true, false, true>(a, G, k_first, n0);
+            else run_forward<T, M, true, false, false>(a, G, k_first, n0);
+        } else {
+            if (tsf) run_forward<T, M, false, false, true>(a, G, k_first, n0);
+            else run_forward<T, M, false, false, false>(a, G, k_first, n0);
+        }
+    } else {
+        const bool uk = G.P == 1;
+#define RA_FWD(FENE_, UK_, TSF_) run_forward<T, M, FENE_, UK_, TSF_>(a, G, k_first, n0)
+        if (G.spring == 1) {
+            if (uk) { if (tsf) RA_FWD(true, true, true); else RA_FWD(true, true, false); }
+            else { if (tsf) RA_FWD(true, false, true); else RA_FWD(true, false, false); }
+        } else {
+            if (uk) { if (tsf) RA_FWD(false, true, true); else RA_FWD(false, true, false); }
+            else { if (tsf) RA_FWD(false, false, true); else RA_FWD(false, false, false); }
+        }
+#undef RA_FWD
+    }
 }
 
 // WAVES_PER_EU = 1 leaves register allocation to the compiler. (Asking the
