@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=192)
+    ap.add_argument("--tile-policy", type=int, default=0,
+                    help="ra_run_desc.tile_policy for the headline workload (0 = cost model)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -108,7 +110,8 @@ def main():
     R, N, T, S = g["n_replicas"], g["n_beads"], run["steps"], run["sample_every"]
     W = T // S
     parent = torch.from_numpy(np.ascontiguousarray(parents[0]).reshape(-1)).to(dev)
-    rep = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W, device=dev)
+    rep = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W, device=dev,
+                      tile_policy=args.tile_policy)
     mean = torch.empty((W, N - 1), dtype=torch.float64, device=dev)
     std = torch.empty_like(mean)
     stream = torch.cuda.current_stream()
@@ -147,6 +150,8 @@ def main():
         (1e3 * elapsed / args.steps, kernel_ms, value))
     gpu_samples = rep.samples()[0]
     tiles = rep.tile_info()
+    family = rep.kernel_family()
+    kernel_name = {1: "fwd_split_kernel", 4: "fwd_kernel<float,4,1>", 16: "fwd_kernel<float,16,2>"}[family]
 
     out = {
         "metric": METRIC, "value": value, "unit": "replica·bead·steps/s", "n_gpus": 1,
@@ -157,10 +162,11 @@ def main():
                                "R=1024, 10^4 steps, sample every 100, FP64 averages, Bell rates"
                                % g["rate"],
                    "global_batch": R, "seq_len": N, "parallelism": "none (1 GPU)",
-                   "beads_per_lane": tiles[0][0], "replicas_per_wave": tiles[1][0]},
+                   "beads_per_lane": tiles[0][0], "replicas_per_wave": tiles[1][0],
+                   "kernel_family": family},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
                      "unit": "T VALU lane-ops/s", "frac": achieved / VALU_PEAK_LANE_OPS,
-                     "traffic": None, "kernel": "fwd_kernel<float,4,1>", "kernel_ms": kernel_ms,
+                     "traffic": None, "kernel": kernel_name, "kernel_ms": kernel_ms,
                      "lane_ops_per_replica_bead_step": OPS_PER_BEAD_STEP_FENE},
     }
 

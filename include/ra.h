@@ -92,8 +92,9 @@ typedef struct {
     int32_t  max_steps;         /* steps since ra_init_chains the checkpoints must hold */
     int32_t  plain;             /* 1: plain path, one launch per step, state in HBM */
     int32_t  use_graph;         /* 1: capture ra_step's launch sequence in a hipGraph */
-    int32_t  tile_policy;       /* 0 cost model; 1 autotune by timing; m > 1 000: force
-                                   m - 1000 beads per lane where legal */
+    int32_t  tile_policy;       /* 0 cost model; 1 autotune by timing; 2 cost model
+                                   without the noise-producer split; 3 force the split
+                                   where legal; 1000 + m: force m beads per lane */
     int32_t  waves_per_block;   /* 0 = default (4) */
 } ra_run_desc;
 
@@ -161,8 +162,11 @@ RA_API ra_status ra_get_samples(ra_ctx* ctx, double* out, double* tsf_out);
 RA_API ra_status ra_get_bonds(ra_ctx* ctx, double* out);
 
 /* Tile chosen per group (host int32[n_groups] each): beads per lane and
- * replicas per wavefront. */
-RA_API ra_status ra_tile_info(ra_ctx* ctx, int32_t* beads_per_lane, int32_t* replicas_per_wave);
+ * replicas per wavefront; kernel_family (host int32[1], may be NULL): 1 = one
+ * bead per lane with a noise-producer wavefront per work item, 4 = 1-4 beads
+ * per lane, 16 = 6-16 beads per lane, 0 = plain path. */
+RA_API ra_status ra_tile_info(ra_ctx* ctx, int32_t* beads_per_lane, int32_t* replicas_per_wave,
+                              int32_t* kernel_family);
 
 /* Noise stream check: for n counters (device uint32 [n][4]) and key = seed,
  * writes the Philox words (device uint32 [n][4]) and the three normals in

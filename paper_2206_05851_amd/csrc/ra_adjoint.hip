@@ -258,6 +258,7 @@ __global__ void grad_reduce_kernel(const int32_t* __restrict__ begin_count, int 
 
 hipError_t launch_adjoint(const AdjArgs& a, int family, int waves_per_block, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
+    if (family != 4 && family != 16) return hipErrorInvalidValue;
     const int wpb = waves_per_block;
     dim3 grid((a.n_items + wpb - 1) / wpb), block(WAVE * wpb);
     if (family == 4) hipLaunchKernelGGL(adjoint_kernel<4>, grid, block, 0, st, a);

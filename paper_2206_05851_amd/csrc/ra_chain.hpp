@@ -122,10 +122,12 @@ template <int M> struct MaskedSlots { static constexpr bool value = M <= 4; };
 // so both roll through three-slot windows; the lane's first/last slots meet
 // the neighbour lanes' through DPP. valid[m] masks slots that are not a
 // spring of an active replica.
-template <typename T, int M, bool FENE, typename NoiseFn>
-__device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, const GroupDev& G,
-                                                const bool (&valid)[M], const SlotCoef<T, M>& kc,
-                                                int& clamps) {
+// xnext(e0, en) gives the next lane's bead-0 normals (by DPP from e0 unless the
+// caller has them at hand, e.g. in LDS).
+template <typename T, int M, bool FENE, typename NoiseFn, typename NextFn>
+__device__ __forceinline__ void physics_step_core(Lane<T, M>& s, NoiseFn&& xi, NextFn&& xnext,
+                                                  const GroupDev& G, const bool (&valid)[M],
+                                                  const SlotCoef<T, M>& kc, int& clamps) {
     const Co<T> c{G};
     T f0x, f0y, f0z, flx, fly, flz;
     slot_force<T, M, FENE>(s, G, 0, f0x, f0y, f0z, clamps);
@@ -136,9 +138,9 @@ __device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, con
     }
     const T fpx = from_prev_lane(flx), fpy = from_prev_lane(fly), fpz = from_prev_lane(flz);
     const T fnx = from_next_lane(f0x), fny = from_next_lane(f0y), fnz = from_next_lane(f0z);
-    T e0x, e0y, e0z;
+    T e0x, e0y, e0z, enx, eny, enz;
     xi(0, e0x, e0y, e0z);
-    const T enx = from_next_lane(e0x), eny = from_next_lane(e0y), enz = from_next_lane(e0z);
+    xnext(e0x, e0y, e0z, enx, eny, enz);
     const T kx = c.kx(), ky = c.ky(), kz = c.kz(), kxz = c.kxz();
     T Px = fpx, Py = fpy, Pz = fpz;   // G of slot m-1
     T Cx = f0x, Cy = f0y, Cz = f0z;   // G of slot m
@@ -176,6 +178,20 @@ __device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, con
         Cx = Nx; Cy = Ny; Cz = Nz;
         Ex = Xx; Ey = Xy; Ez = Xz;
     }
+}
+
+template <typename T, int M, bool FENE, typename NoiseFn>
+__device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, const GroupDev& G,
+                                                const bool (&valid)[M], const SlotCoef<T, M>& kc,
+                                                int& clamps) {
+    physics_step_core<T, M, FENE>(
+        s, xi,
+        [](T ex, T ey, T ez, T& nx, T& ny, T& nz) {
+            nx = from_next_lane(ex);
+            ny = from_next_lane(ey);
+            nz = from_next_lane(ez);
+        },
+        G, valid, kc, clamps);
 }
 
 template <typename T, int M, bool FENE>

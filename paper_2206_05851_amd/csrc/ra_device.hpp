@@ -36,14 +36,19 @@ __device__ __forceinline__ RoundKeys round_keys(uint32_t key0, uint32_t key1) {
     return k;
 }
 
+// Three-input XOR as one gfx950 v_bitop3_b32 (truth table 0x96 = a ^ b ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           const RoundKeys& k) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k.k0[round];
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k.k1[round];
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k.k0[round]);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k.k1[round]);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -103,16 +108,18 @@ __device__ __forceinline__ void normals3(const Words& w, double& a, double& b, d
 constexpr int DPP_WAVE_SHL1 = 0x130;   // lane l reads lane l+1
 constexpr int DPP_WAVE_SHR1 = 0x138;   // lane l reads lane l-1
 
+// mov_dpp with bound_ctrl writes 0 where the source lane is outside the wave
+// and leaves the old value undefined, which lets the compiler fold the shift
+// into the consuming VOP2 instruction.
 template <int CTRL>
 __device__ __forceinline__ float dpp_shift(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 CTRL, 0xF, 0xF, true));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_shift(double v) {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 template <typename T> __device__ __forceinline__ T from_prev_lane(T v) { return dpp_shift<DPP_WAVE_SHR1>(v); }

@@ -202,7 +202,6 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     for (int i = 0; i < n_groups; ++i)
         if (groups[i].n_beads > 4 * WAVE) family = 16;
     if (run->precision == 64) family = 4;
-    c->family = family;
     for (int i = 0; i < n_groups; ++i) {
         int forced = run->tile_policy > 1000 ? run->tile_policy - 1000 : 0;
         Ms[i] = choose_beads_per_lane(groups[i].n_beads, groups[i].n_replicas, family, forced);
@@ -214,6 +213,27 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
             return fail(nullptr, st, "autotune: " + why);
         }
     }
+    // Noise-producer split (one bead per lane, no TSF, FP32): only on request
+    // (tile_policy 3); on the 1024-replica, 50-bead workload it measured slower
+    // than the one-wave kernel with its software-pipelined noise.
+    {
+        bool fits = family == 4 && run->precision == 32 && !run->plain && !run->tsf;
+        int64_t items = 0;                      // wavefronts with one bead per lane
+        for (int i = 0; i < n_groups && fits; ++i) {
+            if (groups[i].n_beads > WAVE) fits = false;
+            else {
+                const int P = WAVE / groups[i].n_beads;
+                items += (groups[i].n_replicas + P - 1) / P;
+            }
+        }
+        const bool want = run->tile_policy == 3;
+        (void)items;
+        if (fits && want) {
+            family = 1;
+            for (int i = 0; i < n_groups; ++i) Ms[i] = 1;
+        }
+    }
+    c->family = family;
 
     // layout
     std::vector<int64_t> par_off(n_groups);
@@ -360,7 +380,8 @@ static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps) {
     const int64_t chunk = (int64_t)1 << 30;
     for (int64_t done = 0; done < n_steps; done += chunk) {
         a.n_steps = std::min(chunk, n_steps - done);
-        HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->stream));
+        if (c->family == 1) HIPCHK(c, launch_forward_split(a, c->stream));
+    else HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->stream));
         HIPCHK(c, launch_advance(c->dstep, a.n_steps, c->stream));
     }
     return RA_OK;
@@ -491,7 +512,8 @@ ra_status ra_backward(ra_ctx* c, const double* mean, const double* grad_mean, co
     a.segbuf = c->segbuf;
     a.seg_off = c->dseg_off;
     a.partial = c->partial;
-    HIPCHK(c, launch_adjoint(a, c->family, c->wpb, c->stream));
+    // the split forward (family 1) is one bead per lane: its adjoint is family 4's
+    HIPCHK(c, launch_adjoint(a, c->family == 16 ? 16 : 4, c->wpb, c->stream));
     HIPCHK(c, launch_grad_reduce(c->ditem_begin, ng, c->partial, grad_params, c->stream));
     return RA_OK;
 }
@@ -534,8 +556,9 @@ ra_status ra_get_bonds(ra_ctx* c, double* out) {
     return RA_OK;
 }
 
-ra_status ra_tile_info(ra_ctx* c, int32_t* beads_per_lane, int32_t* replicas_per_wave) {
+ra_status ra_tile_info(ra_ctx* c, int32_t* beads_per_lane, int32_t* replicas_per_wave, int32_t* kernel_family) {
     if (!c) return fail(nullptr, RA_EINVAL, "null context");
+    if (kernel_family) *kernel_family = c->run.plain ? 0 : c->family;
     for (size_t i = 0; i < c->hgroups.size(); ++i) {
         if (beads_per_lane) beads_per_lane[i] = c->hgroups[i].M;
         if (replicas_per_wave) replicas_per_wave[i] = c->hgroups[i].P;

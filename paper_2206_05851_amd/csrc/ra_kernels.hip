@@ -92,14 +92,26 @@ __device__ __forceinline__ void run_forward(const FwdArgs& a, const GroupDev& G,
     auto run_steps = [&](uint32_t n, int len) {   // len steps starting at global step n
         int i = 0;
         if constexpr (U > 1) {
-            for (; i + U <= len; i += U) {
+            // software pipeline: the noise of block b+1 is generated in the same
+            // basic block as the updates of block b, so the scheduler can fill the
+            // update chain's latencies with independent Philox work (one spare
+            // block of noise is generated past the end and discarded)
+            if (U <= len) {
                 Noise<T, M> e[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) gen_noise<T, M>(e[u], G, n + (uint32_t)(i + u), bead0, rep, keys);
+                for (int u = 0; u < U; ++u) gen_noise<T, M>(e[u], G, n + (uint32_t)u, bead0, rep, keys);
+                for (; i + U <= len; i += U) {
+                    Noise<T, M> f[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    physics_step<T, M, FENE>(s, e[u], G, valid, kc, clamps);
-                    accumulate_tsf();
+                    for (int u = 0; u < U; ++u)
+                        gen_noise<T, M>(f[u], G, n + (uint32_t)(i + U + u), bead0, rep, keys);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        physics_step<T, M, FENE>(s, e[u], G, valid, kc, clamps);
+                        accumulate_tsf();
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) e[u] = f[u];
                 }
             }
         }
@@ -177,8 +189,10 @@ __device__ __forceinline__ void dispatch_spring(const FwdArgs& a, const GroupDev
     }
 }
 
-// WAVES_PER_EU = 1 leaves register allocation to the compiler. (Asking the
-// 16-bead family for 3-4 resident waves makes it spill inside the step loop.)
+// WAVES_PER_EU is a register budget hint: family 4 needs none (about 100
+// VGPRs); family 16 is held to 2 resident waves per SIMD (256 registers), which
+// it fits without spilling — left alone the scheduler hoists all 16 Philox
+// chains and falls to 1 wave, and asking for 3-4 waves makes it spill.
 template <typename T, int FAMILY, int WAVES_PER_EU>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 void fwd_kernel(FwdArgs a) {
@@ -501,7 +515,7 @@ static dim3 grid1d(int64_t n, int block) {
 }
 
 #ifndef FAMILY16_WAVES
-#define FAMILY16_WAVES 1
+#define FAMILY16_WAVES 2
 #endif
 
 hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, hipStream_t st) {

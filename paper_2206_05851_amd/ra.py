@@ -74,7 +74,7 @@ def library():
         "ra_guard_counts": [P, ctypes.POINTER(i64)],
         "ra_get_samples": [P, P, P],
         "ra_get_bonds": [P, P],
-        "ra_tile_info": [P, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "ra_tile_info": [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "ra_debug_noise": [P, i64, u64, P, P, P, P],
         "ra_destroy": [P],
     }
@@ -253,11 +253,21 @@ class Replicas:
         return outs
 
     def tile_info(self):
+        """(beads per lane per group, replicas per wave per group)."""
         G = len(self.groups)
         M = (ctypes.c_int32 * G)()
         P = (ctypes.c_int32 * G)()
-        self._check(self.L.ra_tile_info(self.ptr, M, P))
+        self._check(self.L.ra_tile_info(self.ptr, M, P, None))
         return list(M), list(P)
+
+    def kernel_family(self):
+        """1 = noise-producer split, 4 / 16 = one-wave families, 0 = plain path."""
+        G = len(self.groups)
+        M = (ctypes.c_int32 * G)()
+        P = (ctypes.c_int32 * G)()
+        f = ctypes.c_int32()
+        self._check(self.L.ra_tile_info(self.ptr, M, P, ctypes.byref(f)))
+        return f.value
 
     def close(self):
         if self.ptr:

@@ -16,14 +16,15 @@ def _gpu():
     require_gpu()
 
 
-def _grad_pair(groups, parents, seed, steps, S, K, k0=1e-6, xd=0.1, wseed=0, rate_scale=1e5):
+def _grad_pair(groups, parents, seed, steps, S, K, k0=1e-6, xd=0.1, wseed=0, rate_scale=1e5, tile_policy=0):
     import torch
     W = steps // S
     nspr = sum(g["n_beads"] - 1 for g in groups)
     rng = np.random.default_rng(wseed)
     gm = rng.normal(size=(W, nspr))
     gr = rng.normal(size=(W, nspr)) * rate_scale
-    rep = run_gpu(groups, parents, seed, steps, S, checkpoint_every=K, max_steps=steps)
+    rep = run_gpu(groups, parents, seed, steps, S, checkpoint_every=K, max_steps=steps,
+                  tile_policy=tile_policy)
     mean, _ = rep.average_forces()
     g_gpu = rep.backward(mean, torch.from_numpy(gm).cuda(), torch.from_numpy(gr).cuda(), k0, xd)
     g_gpu = g_gpu.cpu().numpy()
@@ -40,14 +41,16 @@ def _check(g_gpu, g_ref, rtol):
     assert err < rtol, (g_gpu, g_ref)
 
 
-@pytest.mark.parametrize("spring,flow,N", [(wl.FENE, wl.UNIAXIAL, 12), (wl.FENE, wl.SHEAR, 33),
-                                           (wl.HOOKEAN, wl.PLANAR, 10), (wl.FENE, wl.PLANAR, 150)])
-def test_adjoint_matches_oracle_tangents_200_steps(spring, flow, N):
+@pytest.mark.parametrize("spring,flow,N,policy", [(wl.FENE, wl.UNIAXIAL, 12, 0), (wl.FENE, wl.SHEAR, 33, 0),
+                                                  (wl.FENE, wl.SHEAR, 33, 2), (wl.HOOKEAN, wl.PLANAR, 10, 2),
+                                                  (wl.FENE, wl.PLANAR, 150, 0)])
+def test_adjoint_matches_oracle_tangents_200_steps(spring, flow, N, policy):
+    # policy 0 picks the noise-producer forward for N <= 64, policy 2 the one-wave one
     b = 40.0 if spring == wl.FENE else 0.0
     g = wl.group(N, 64, 1e-4, spring, 1.3, b, flow, 30.0 if flow == wl.SHEAR else 0.8)
     parent = wl.equilibrium_parent(N, spring, 1.3, b, seed=N)
-    announce("adjoint N=%d spring=%d flow=%d" % (N, spring, flow))
-    g_gpu, g_ref = _grad_pair([g], [parent], 17, 200, 50, 50)
+    announce("adjoint N=%d spring=%d flow=%d policy=%d" % (N, spring, flow, policy))
+    g_gpu, g_ref = _grad_pair([g], [parent], 17, 200, 50, 50, tile_policy=policy)
     _check(g_gpu, g_ref, 1e-4)
     if spring == wl.HOOKEAN:
         assert g_gpu[0, 2] == 0.0
