@@ -21,7 +21,11 @@ struct Words {
 };
 
 // Round keys of one seed: key + r * (Weyl increments), r = 0..9. Built once
-// per kernel so the step loop does not redo the key schedule.
+// per kernel so the step loop does not redo the key schedule. They are pinned
+// to VGPRs (the empty asm only constrains the register class): with a scalar
+// key the compiler splits each three-way XOR back into two v_xor_b32, with
+// vector keys it selects one v_bitop3_b32, and the per-step scalar work of
+// the first rounds disappears from the single instruction stream.
 struct RoundKeys {
     uint32_t k0[10], k1[10];
 };
@@ -32,6 +36,8 @@ __device__ __forceinline__ RoundKeys round_keys(uint32_t key0, uint32_t key1) {
     for (int r = 0; r < 10; ++r) {
         k.k0[r] = key0 + (uint32_t)r * 0x9E3779B9u;
         k.k1[r] = key1 + (uint32_t)r * 0xBB67AE85u;
+        asm volatile("" : "+v"(k.k0[r]));
+        asm volatile("" : "+v"(k.k1[r]));
     }
     return k;
 }
