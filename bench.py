@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="plain,adjoint,batched,large1000",
+                    help="comma-separated extra workloads to measure once")
     ap.add_argument("--cpu-replicas", type=int, default=192)
     ap.add_argument("--tile-policy", type=int, default=0,
                     help="ra_run_desc.tile_policy for the headline workload (0 = cost model)")
@@ -170,7 +172,8 @@ def main():
                      "lane_ops_per_replica_bead_step": OPS_PER_BEAD_STEP_FENE},
     }
 
-    if not args.no_extras:
+    extras = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
+    if "plain" in extras:
         # plain unbatched path, same workload and counters
         plain = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W,
                             plain=True, device=dev)
@@ -194,7 +197,7 @@ def main():
         plain.close()
         log("plain: %.3f ms/step" % (1e3 * tp))
 
-        # adjoint workload
+    if "adjoint" in extras:
         ag, ap_, arun = wl.adjoint100()
         ga = ag[0]
         apar = torch.from_numpy(np.ascontiguousarray(ap_[0]).reshape(-1)).to(dev)
@@ -225,6 +228,7 @@ def main():
         adj.close()
         log("adjoint: fwd %.2f ms bwd %.2f ms" % (1e3 * tf, 1e3 * tb))
 
+    if "batched" in extras:
         # batched uneven chains, one graph-captured persistent launch per call
         bg, bp, brun = wl.batched512()
         bpar = torch.from_numpy(np.concatenate([np.ascontiguousarray(p).reshape(-1) for p in bp])).to(dev)
@@ -247,6 +251,7 @@ def main():
         bat.close()
         log("batched: %.2f ms" % (1e3 * tbat))
 
+    if "large1000" in extras:
         # 1000-bead transient with TSF
         lg, lp, lrun = wl.large1000()
         lpar = torch.from_numpy(np.ascontiguousarray(lp[0]).reshape(-1)).to(dev)

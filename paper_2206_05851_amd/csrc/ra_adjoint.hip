@@ -97,8 +97,8 @@ __device__ __forceinline__ void inject(const Lane<float, M>& q, const bool (&val
 // Reverse step through Phi at the state q = Q^n; lambda holds lambda^{n+1}.
 template <int M, bool FENE>
 __device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const bool (&valid)[M], const GroupDev& G,
-                                             float (&lx)[M], float (&ly)[M], float (&lz)[M], double& gr,
-                                             double& gH, double& gb) {
+                                             float (&lx)[M], float (&ly)[M], float (&lz)[M], float& gr,
+                                             float& gH, float& gb) {
     const float kx = G.kx, ky = G.ky, kz = G.kz, kxz = G.kxz, cF = G.cF;
     // d(dt kappa)/d rate, per flow
     float px = 0.f, py = 0.f, pz = 0.f, pxz = 0.f;
@@ -129,12 +129,12 @@ __device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const bool
         factor_gs<FENE>(q.qx[m], q.qy[m], q.qz[m], G, g, s, smooth);
         const float Qx = q.qx[m], Qy = q.qy[m], Qz = q.qz[m];
         // theta terms with lambda^{n+1}
-        gr += (double)fmadd(lx[m], fmadd(px, Qx, pxz * Qz), fmadd(ly[m], py * Qy, lz[m] * pz * Qz));
+        gr += fmadd(lx[m], fmadd(px, Qx, pxz * Qz), fmadd(ly[m], py * Qy, lz[m] * pz * Qz));
         const float muQ = fmadd(ux[m], Qx, fmadd(uy[m], Qy, uz[m] * Qz));
         const float wH = (FENE && smooth) ? dtz * g * fmadd(g, s, 1.0f) : dtz * g;
         const float wb = (FENE && smooth) ? -cF * g * g * (s / (float)G.b) : 0.0f;
-        gH += (double)(wH * muQ);
-        gb += (double)(wb * muQ);
+        gH = fmadd(wH, muQ, gH);
+        gb = fmadd(wb, muQ, gb);
         // lambda^n = lambda + (dt kappa)^T lambda + cF J mu
         const float ex = (FENE && smooth) ? 2.0f * g * g * G.inv_q0sq * muQ : 0.0f;
         const float jx = fmadd(g, ux[m], ex * Qx);
@@ -157,77 +157,88 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 template <int M, bool FENE>
 __device__ void run_adjoint(const AdjArgs& a, const GroupDev& G, int item, int k_first) {
+    // kernel arguments into locals (the loops must not address the argument block)
+    const int S = a.S, K = a.K;
+    const int64_t n_end = a.n_end, state_total = a.state_total, spr_total = a.spr_total;
+    const float* const ckpt = (const float*)a.ckpt;
+    const double* const lam_mu = a.lam_mu;
+    float* const seg = a.segbuf + a.seg_off[item];
+    double* const partial = a.partial + 3 * item;
     const TileGeom tg = tile_geom(G, k_first, M);
     const int lane = threadIdx.x & (WAVE - 1);
-    Lane<float, M> s, q;
+    Lane<float, M> s, q, qn;
     bool valid[M];
     float lx[M], ly[M], lz[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) lx[m] = ly[m] = lz[m] = 0.0f;
-    double gr = 0.0, gH = 0.0, gb = 0.0;
-    float* seg = a.segbuf + a.seg_off[item];
-    const int K = a.K;
-    const int64_t n_seg = (a.n_end + K - 1) / K;
+    double gr = 0.0, gH = 0.0, gb = 0.0;      // FP64 totals
     int dummy = 0;
-    const RoundKeys keys = round_keys(a.key0, a.key1);
+    const RoundKeys keys = round_keys<false>(a.key0, a.key1);
     SlotCoef<float, M> kc;
-    for (int64_t sgi = n_seg - 1; sgi >= 0; --sgi) {
-        const int64_t s0 = sgi * K;
-        const int64_t s1 = min(a.n_end, s0 + K);
-        load_lane<float, M>(s, valid, (const float*)a.ckpt + sgi * a.state_total, G, tg);
+    constexpr int STRIDE = M * 3 * WAVE;      // floats per stored state
+    const AdjArgs* ap = &a;                   // for inject(); not touched in the step loops
+    const int n_seg = (int)((n_end + K - 1) / K);
+    for (int sgi = n_seg - 1; sgi >= 0; --sgi) {
+        const int s0 = sgi * K;
+        const int s1 = (int)min(n_end, (int64_t)s0 + K);
+        load_lane<float, M>(s, valid, ckpt + (int64_t)sgi * state_total, G, tg);
         kc = slot_coef<float, M>(G, valid);
-        for (int64_t n = s0; n < s1; ++n) {
-            seg_store<M>(seg, (int)(n - s0), s, lane);
+        float* wp = seg;
+        for (int n = s0; n < s1; ++n) {
+            seg_store<M>(wp, 0, s, lane);
+            wp += STRIDE;
             em_step<float, M, FENE>(s, G, valid, kc, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, keys, dummy);
         }
-        // s = Q^{s1}; sweep n = s1-1 .. s0, injecting at states n+1 that were sampled
-        for (int64_t n = s1 - 1; n >= s0; --n) {
-            if ((n + 1) % a.S == 0) inject<M, FENE>(s, valid, G, a, tg, (n + 1) / a.S - 1, lx, ly, lz, gH, gb);
-            seg_load<M>(seg, (int)(n - s0), q, lane);
-            reverse_step<M, FENE>(q, valid, G, lx, ly, lz, gr, gH, gb);
+        // s = Q^{s1}; sweep n = s1-1 .. s0, injecting at states n+1 that were sampled.
+        // rr = (n + 1) mod S, w = window of state n + 1 when rr == 0
+        int rr = s1 % S;
+        int w = s1 / S - 1;
+        float pr = 0.0f, pH = 0.0f, pb = 0.0f;   // FP32 partials of this segment
+        const float* rp = seg + (int64_t)(s1 - 1 - s0) * STRIDE;
+        seg_load<M>(rp, 0, qn, lane);           // Q^{s1-1}, loaded one step ahead
+        for (int n = s1 - 1; n >= s0; --n) {
+            q = qn;
+            if (n > s0) seg_load<M>(rp - STRIDE, 0, qn, lane);
+            rp -= STRIDE;
+            if (rr == 0) {
+                double dH = 0.0, db = 0.0;
+                inject<M, FENE>(s, valid, G, *ap, tg, w, lx, ly, lz, dH, db);
+                gH += dH;
+                gb += db;
+                --w;
+            }
+            reverse_step<M, FENE>(q, valid, G, lx, ly, lz, pr, pH, pb);
             s = q;
+            rr = rr == 0 ? S - 1 : rr - 1;
         }
+        gr += (double)pr;
+        gH += (double)pH;
+        gb += (double)pb;
     }
+    (void)spr_total;
+    (void)lam_mu;
     gr = wave_sum(gr);
     gH = wave_sum(gH);
     gb = wave_sum(gb);
     if (lane == 0) {
-        a.partial[3 * item] = gr;
-        a.partial[3 * item + 1] = gH;
-        a.partial[3 * item + 2] = gb;
+        partial[0] = gr;
+        partial[1] = gH;
+        partial[2] = gb;
     }
 }
 
+// One kernel per beads-per-lane M, launched over the contiguous range of the
+// (M-sorted) work list that uses it, so each M gets its own register budget.
 template <int M>
-__device__ __forceinline__ void adj_dispatch(const AdjArgs& a, const GroupDev& G, int item, int k0) {
-    if (G.spring == 1) run_adjoint<M, true>(a, G, item, k0);
-    else run_adjoint<M, false>(a, G, item, k0);
-}
-
-template <int FAMILY>
-__global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M <= 2 ? 4 : 1)))
+void adjoint_kernel(AdjArgs a, int item_begin, int item_end) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int item = (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
-    if (item >= a.n_items) return;
+    const int item = item_begin + (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
+    if (item >= item_end) return;
     const Item it = a.items[item];
     const GroupDev& G = a.groups[it.g];
-    if constexpr (FAMILY == 4) {
-        switch (G.M) {
-        case 1: adj_dispatch<1>(a, G, item, it.k0); break;
-        case 2: adj_dispatch<2>(a, G, item, it.k0); break;
-        case 3: adj_dispatch<3>(a, G, item, it.k0); break;
-        case 4: adj_dispatch<4>(a, G, item, it.k0); break;
-        default: break;
-        }
-    } else {
-        switch (G.M) {
-        case 6: adj_dispatch<6>(a, G, item, it.k0); break;
-        case 8: adj_dispatch<8>(a, G, item, it.k0); break;
-        case 12: adj_dispatch<12>(a, G, item, it.k0); break;
-        case 16: adj_dispatch<16>(a, G, item, it.k0); break;
-        default: break;
-        }
-    }
+    if (G.spring == 1) run_adjoint<M, true>(a, G, item, it.k0);
+    else run_adjoint<M, false>(a, G, item, it.k0);
 }
 
 // lam_mu[w][s] = grad_mean + grad_rates * dk/dmean, dk/dmean = k * x_dagger / kT.
@@ -256,13 +267,24 @@ __global__ void grad_reduce_kernel(const int32_t* __restrict__ begin_count, int 
     grad[e] = acc;
 }
 
-hipError_t launch_adjoint(const AdjArgs& a, int family, int waves_per_block, hipStream_t st) {
+hipError_t launch_adjoint(const AdjArgs& a, int M, int item_begin, int item_end, int waves_per_block,
+                          hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
-    if (family != 4 && family != 16) return hipErrorInvalidValue;
+    const int n = item_end - item_begin;
+    if (n <= 0) return hipSuccess;
     const int wpb = waves_per_block;
-    dim3 grid((a.n_items + wpb - 1) / wpb), block(WAVE * wpb);
-    if (family == 4) hipLaunchKernelGGL(adjoint_kernel<4>, grid, block, 0, st, a);
-    else hipLaunchKernelGGL(adjoint_kernel<16>, grid, block, 0, st, a);
+    dim3 grid((n + wpb - 1) / wpb), block(WAVE * wpb);
+    switch (M) {
+    case 1: hipLaunchKernelGGL(adjoint_kernel<1>, grid, block, 0, st, a, item_begin, item_end); break;
+    case 2: hipLaunchKernelGGL(adjoint_kernel<2>, grid, block, 0, st, a, item_begin, item_end); break;
+    case 3: hipLaunchKernelGGL(adjoint_kernel<3>, grid, block, 0, st, a, item_begin, item_end); break;
+    case 4: hipLaunchKernelGGL(adjoint_kernel<4>, grid, block, 0, st, a, item_begin, item_end); break;
+    case 6: hipLaunchKernelGGL(adjoint_kernel<6>, grid, block, 0, st, a, item_begin, item_end); break;
+    case 8: hipLaunchKernelGGL(adjoint_kernel<8>, grid, block, 0, st, a, item_begin, item_end); break;
+    case 12: hipLaunchKernelGGL(adjoint_kernel<12>, grid, block, 0, st, a, item_begin, item_end); break;
+    case 16: hipLaunchKernelGGL(adjoint_kernel<16>, grid, block, 0, st, a, item_begin, item_end); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -30,14 +30,19 @@ struct RoundKeys {
     uint32_t k0[10], k1[10];
 };
 
+// PIN_VGPR = false keeps the keys in scalar registers (20 fewer VGPRs, two
+// v_xor_b32 per three-way XOR): for kernels where occupancy matters more.
+template <bool PIN_VGPR = true>
 __device__ __forceinline__ RoundKeys round_keys(uint32_t key0, uint32_t key1) {
     RoundKeys k;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         k.k0[r] = key0 + (uint32_t)r * 0x9E3779B9u;
         k.k1[r] = key1 + (uint32_t)r * 0xBB67AE85u;
-        asm volatile("" : "+v"(k.k0[r]));
-        asm volatile("" : "+v"(k.k1[r]));
+        if constexpr (PIN_VGPR) {
+            asm volatile("" : "+v"(k.k0[r]));
+            asm volatile("" : "+v"(k.k1[r]));
+        }
     }
     return k;
 }

@@ -512,8 +512,14 @@ ra_status ra_backward(ra_ctx* c, const double* mean, const double* grad_mean, co
     a.segbuf = c->segbuf;
     a.seg_off = c->dseg_off;
     a.partial = c->partial;
-    // the split forward (family 1) is one bead per lane: its adjoint is family 4's
-    HIPCHK(c, launch_adjoint(a, c->family == 16 ? 16 : 4, c->wpb, c->stream));
+    // one launch per beads-per-lane value over its contiguous range of the work list
+    for (size_t b = 0; b < c->hitems.size();) {
+        const int M = c->hgroups[c->hitems[b].g].M;
+        size_t e = b;
+        while (e < c->hitems.size() && c->hgroups[c->hitems[e].g].M == M) ++e;
+        HIPCHK(c, launch_adjoint(a, M, (int)b, (int)e, c->wpb, c->stream));
+        b = e;
+    }
     HIPCHK(c, launch_grad_reduce(c->ditem_begin, ng, c->partial, grad_params, c->stream));
     return RA_OK;
 }

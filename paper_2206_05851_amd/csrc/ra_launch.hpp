@@ -67,7 +67,8 @@ hipError_t launch_pos_to_bonds(const GroupDev* groups, int n_groups, int64_t max
                                double* out, int precision, hipStream_t st);
 hipError_t launch_debug_noise(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
                               float* n32, double* n64, hipStream_t st);
-hipError_t launch_adjoint(const AdjArgs& a, int family, int waves_per_block, hipStream_t st);
+hipError_t launch_adjoint(const AdjArgs& a, int M, int item_begin, int item_end, int waves_per_block,
+                          hipStream_t st);
 hipError_t launch_lam_mu(const GroupDev* groups, int n_groups, int64_t n_windows, const double* mean,
                          const double* grad_mean, const double* grad_rates, double k0, double xd,
                          int64_t spr_total, double* lam_mu, hipStream_t st);
