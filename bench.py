@@ -31,15 +31,38 @@ if ROOT not in sys.path:
 
 METRIC = "replica·bead·steps/s and adjoint steps/s vs plain GPU path at 1e-4 rel err"
 
-# Peak VALU lane-op rate of one MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 ops per
-# lane per issue (dual issue / packed; the published 157.3 TFLOP/s FP32 vector
-# peak counted as 2 flops per lane-op) x 2.4 GHz = 78.6 T lane-ops/s.
-VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2 * 2.4e9
-# Algorithmic VALU lane-ops per replica*bead*step, in FMA-issue equivalents
-# (transcendentals count 2, as measured on gfx950): Philox4x32-10 60 (20
-# 32x32->64 products, 40 XORs), uniform maps 8, Box-Muller 19, FENE bond
-# update 32 (Hookean 26).
-OPS_PER_BEAD_STEP_FENE = 119
+# Peak VALU issue rate of one MI355X in lane-slots: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz = 39.3 T lane-slots/s. One lane-slot is one lane of one full-rate
+# VALU instruction (a wave64 instruction occupies a SIMD for 4 cycles); it is
+# the published 157.3 TFLOP/s FP32 vector peak divided by 2 flops per FMA and
+# by 2 for the packed FP32 forms, which integer work cannot use.
+VALU_PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
+# Algorithmic lane-slots per replica*bead*step of the FENE forward step, at the
+# issue cost of the gfx950 instruction that each operation needs (a
+# transcendental occupies 2 slots, everything else 1):
+#   Philox4x32-10: 10 rounds x (2 products 32x32->64 + 2 three-input XORs) = 40
+#   uniform maps: 4 words x (exponent splice + subtract)                      =  8
+#   Box-Muller: 2 log + 2 sqrt + 3 sin/cos (2 slots each) + 5 scalings        = 19
+#   FENE bond update (spring law, flow, neighbour exchange, EM combine)      = 32
+VALU_SLOTS_PER_BEAD_STEP_FENE = 40 + 8 + 19 + 32
+# HBM bytes per launch of the forward kernel on the headline workload, read with
+# rocprofv3 counters (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, both factors from
+# a 1 GiB device copy). Valid only for the kernel sources they were taken on:
+# the digest of those sources is recorded with the figure, and bench.py reports
+# null when the sources have changed since.
+FWD_TRAFFIC = {"sha256": "48c60750371bc639310fd4f2a4c1b963a22087866d206a6db97b3e721d299e45",
+               "bytes": (447.296875 * 2.0 + 20592.0) * 1024}
+FWD_SOURCES = ("ra_kernels.hip", "ra_chain.hpp", "ra_device.hpp", "ra_types.hpp", "ra_launch.hpp",
+               "ra_host.cpp", "ra_tune.cpp", "ra_tune.hpp")
+
+
+def fwd_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FWD_SOURCES:
+        with open(os.path.join(ROOT, "paper_2206_05851_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -147,12 +170,14 @@ def main():
     work_per_step = R * N * T
     value = work_per_step * args.steps / elapsed
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    achieved = OPS_PER_BEAD_STEP_FENE * work_per_step / (kernel_ms * 1e-3)
+    achieved = VALU_SLOTS_PER_BEAD_STEP_FENE * work_per_step / (kernel_ms * 1e-3)
     log("fused: %.3f ms/step, kernel %.3f ms, %.3e replica-bead-steps/s" %
         (1e3 * elapsed / args.steps, kernel_ms, value))
     gpu_samples = rep.samples()[0]
     tiles = rep.tile_info()
     family = rep.kernel_family()
+    traffic = (FWD_TRAFFIC["bytes"] if family == 4 and args.tile_policy == 0
+               and fwd_sources_digest() == FWD_TRAFFIC["sha256"] else None)
     kernel_name = {1: "fwd_split_kernel", 4: "fwd_kernel<float,4,1>", 16: "fwd_kernel<float,16,2>"}[family]
 
     out = {
@@ -166,10 +191,10 @@ def main():
                    "global_batch": R, "seq_len": N, "parallelism": "none (1 GPU)",
                    "beads_per_lane": tiles[0][0], "replicas_per_wave": tiles[1][0],
                    "kernel_family": family},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
-                     "unit": "T VALU lane-ops/s", "frac": achieved / VALU_PEAK_LANE_OPS,
-                     "traffic": None, "kernel": kernel_name, "kernel_ms": kernel_ms,
-                     "lane_ops_per_replica_bead_step": OPS_PER_BEAD_STEP_FENE},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_SLOTS / 1e12,
+                     "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK_LANE_SLOTS,
+                     "traffic": traffic, "kernel": kernel_name, "kernel_ms": kernel_ms,
+                     "lane_slots_per_replica_bead_step": VALU_SLOTS_PER_BEAD_STEP_FENE},
     }
 
     extras = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
