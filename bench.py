@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="plain,adjoint,batched,large1000",
                     help="comma-separated extra workloads to measure once")
-    ap.add_argument("--cpu-replicas", type=int, default=192)
+    ap.add_argument("--cpu-replicas", type=int, default=384)
     ap.add_argument("--tile-policy", type=int, default=0,
                     help="ra_run_desc.tile_policy for the headline workload (0 = cost model)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -255,16 +255,38 @@ __global__ __launch_bounds__(64) void lam_mu_kernel(const GroupDev* __restrict__
     }
 }
 
-// grad[g][p] = sum over the group's work items, in work-list order.
-__global__ void grad_reduce_kernel(const int32_t* __restrict__ begin_count, int n_groups,
-                                   const double* __restrict__ partial, double* __restrict__ grad) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 3 * n_groups) return;
-    const int g = e / 3, p = e - 3 * g;
+// grad[g][p] = sum over the group's work items, one block per group in a
+// fixed order: thread t sums items t, t + GR_THREADS, ... in order, then the
+// threads' sums combine by a fixed-shape tree.
+constexpr int GR_THREADS = 256;
+
+__global__ __launch_bounds__(GR_THREADS) void grad_reduce_kernel(const int32_t* __restrict__ begin_count,
+                                                                const double* __restrict__ partial,
+                                                                double* __restrict__ grad) {
+    __shared__ double sh[3][GR_THREADS];
+    const int g = blockIdx.x;
+    const int t = threadIdx.x;
     const int b = begin_count[2 * g], n = begin_count[2 * g + 1];
-    double acc = 0.0;
-    for (int i = 0; i < n; ++i) acc += partial[3 * (b + i) + p];
-    grad[e] = acc;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int i = t; i < n; i += GR_THREADS) {
+        const double* q = partial + 3 * (int64_t)(b + i);
+        a0 += q[0];
+        a1 += q[1];
+        a2 += q[2];
+    }
+    sh[0][t] = a0;
+    sh[1][t] = a1;
+    sh[2][t] = a2;
+    __syncthreads();
+    for (int h = GR_THREADS / 2; h >= 1; h >>= 1) {
+        if (t < h) {
+            sh[0][t] += sh[0][t + h];
+            sh[1][t] += sh[1][t + h];
+            sh[2][t] += sh[2][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 3) grad[3 * g + t] = sh[t][0];
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, int M, int item_begin, int item_end, int waves_per_block,
@@ -301,8 +323,9 @@ hipError_t launch_lam_mu(const GroupDev* groups, int n_groups, int64_t n_windows
 hipError_t launch_grad_reduce(const int32_t* item_begin, int n_groups, const double* partial,
                               double* grad_params, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
-    hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((3 * n_groups + 63) / 64)), dim3(64), 0, st,
-                       item_begin, n_groups, partial, grad_params);
+    if (n_groups == 0) return hipSuccess;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)n_groups), dim3(GR_THREADS), 0, st, item_begin,
+                       partial, grad_params);
     return hipGetLastError();
 }
 

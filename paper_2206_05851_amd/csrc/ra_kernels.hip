@@ -378,15 +378,20 @@ __global__ __launch_bounds__(256) void plain_sample_kernel(const GroupDev* __res
 // ---------------------------------------------------------------------------
 // Replica reduction (RSF estimate, Sec. II): per (window, spring) the replica
 // mean and the R-1 standard deviation, FP64, two passes, fixed order:
-// wave v sums replicas [v*R/W, (v+1)*R/W) in order, waves combine in order.
+// wave v of RED_WAVES sums replicas [v*c, (v+1)*c) (c = ceil(R/RED_WAVES)) in
+// order, the waves' sums combine in wave order. Loads are unrolled so each
+// lane keeps several rows in flight; the second pass re-reads the block's
+// rows, which are still in L2.
 // ---------------------------------------------------------------------------
+constexpr int RED_WAVES = 16;
+
 template <typename T>
-__global__ __launch_bounds__(256) void reduce_kernel(const GroupDev* __restrict__ groups,
-                                                     const ColTile* __restrict__ tiles,
-                                                     const T* __restrict__ smp, int64_t smp_total,
-                                                     int64_t spr_total, double* __restrict__ mean,
-                                                     double* __restrict__ stdv) {
-    __shared__ double part[4][WAVE];
+__global__ __launch_bounds__(WAVE * RED_WAVES) void reduce_kernel(const GroupDev* __restrict__ groups,
+                                                               const ColTile* __restrict__ tiles,
+                                                               const T* __restrict__ smp, int64_t smp_total,
+                                                               int64_t spr_total, double* __restrict__ mean,
+                                                               double* __restrict__ stdv) {
+    __shared__ double part[RED_WAVES][WAVE];
     const ColTile tile = tiles[blockIdx.x];
     const int64_t w = blockIdx.y;
     const GroupDev& G = groups[tile.g];
@@ -395,30 +400,39 @@ __global__ __launch_bounds__(256) void reduce_kernel(const GroupDev* __restrict_
     const int nm1 = G.N - 1;
     const int j = tile.j0 + lane;
     const bool ok = j < nm1;
-    const int chunk = (G.R + 3) / 4;
-    const int kb = wv * chunk;
+    const int chunk = (G.R + RED_WAVES - 1) / RED_WAVES;
+    const int kb = min(G.R, wv * chunk);
     const int ke = min(G.R, kb + chunk);
     const T* base = smp + w * smp_total + G.smp_off + (ok ? j : 0);
     double acc = 0.0;
-    if (ok)
+    if (ok) {
+#pragma unroll 8
         for (int k = kb; k < ke; ++k) acc += (double)base[(int64_t)k * nm1];
+    }
     part[wv][lane] = acc;
     __syncthreads();
-    const double mu = (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) / (double)G.R;
+    double tot = 0.0;
+#pragma unroll
+    for (int v = 0; v < RED_WAVES; ++v) tot += part[v][lane];
+    const double mu = tot / (double)G.R;
     __syncthreads();
     double ss = 0.0;
-    if (ok)
+    if (ok) {
+#pragma unroll 8
         for (int k = kb; k < ke; ++k) {
             const double d = (double)base[(int64_t)k * nm1] - mu;
             ss = fmadd(d, d, ss);
         }
+    }
     part[wv][lane] = ss;
     __syncthreads();
     if (wv == 0 && ok) {
-        const double tot = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        double sst = 0.0;
+#pragma unroll
+        for (int v = 0; v < RED_WAVES; ++v) sst += part[v][lane];
         const int64_t o = w * spr_total + G.spr_off + j;
         if (mean) mean[o] = mu;
-        if (stdv) stdv[o] = G.R > 1 ? sqrt(tot / (double)(G.R - 1)) : 0.0;
+        if (stdv) stdv[o] = G.R > 1 ? sqrt(sst / (double)(G.R - 1)) : 0.0;
     }
 }
 
@@ -608,7 +622,7 @@ hipError_t launch_reduce(const GroupDev* groups, const ColTile* tiles, int n_til
                          int precision, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     if (n_tiles == 0 || n_windows == 0) return hipSuccess;
-    dim3 grid((unsigned)n_tiles, (unsigned)n_windows), block(256);
+    dim3 grid((unsigned)n_tiles, (unsigned)n_windows), block(WAVE * RED_WAVES);
     if (precision == 64)
         hipLaunchKernelGGL(reduce_kernel<double>, grid, block, 0, st, groups, tiles, (const double*)smp,
                            smp_total, spr_total, mean, stdv);
