@@ -76,6 +76,12 @@ def lib():
         L.ra_oracle_backward.argtypes = [P, dp, dp, ctypes.c_double, ctypes.c_double, dp]
         L.ra_oracle_get_samples.argtypes = [P, dp, dp]
         L.ra_oracle_get_positions.argtypes = [P, dp]
+        L.ra_oracle_set_tag.argtypes = [P, ctypes.c_uint32]
+        L.ra_oracle_reclone.argtypes = [P, dp, ctypes.c_int64]
+        L.ra_oracle_rsf_cycle.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
+        L.ra_oracle_block_sigma.argtypes = [P, ctypes.c_int32, dp]
+        L.ra_oracle_mftu.argtypes = [P, dp, ctypes.c_int64, dp]
+        L.ra_oracle_conformation.argtypes = [P, dp, dp, dp, dp]
         L.ra_oracle_clamps.argtypes = [P, ctypes.c_int32]
         L.ra_oracle_clamps.restype = ctypes.c_int64
         L.ra_oracle_last_error.argtypes = [P]
@@ -262,6 +268,42 @@ class Oracle:
 
     def clamps(self, g):
         return self.L.ra_oracle_clamps(self.ptr, g)
+
+    def set_tag(self, tag):
+        self._check(self.L.ra_oracle_set_tag(self.ptr, int(tag)), "set_tag")
+
+    def reclone(self, parent_xyz, step0):
+        p = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64).ravel()
+                                                 for x in parent_xyz]))
+        self._check(self.L.ra_oracle_reclone(self.ptr, _dp(p), int(step0)), "reclone")
+
+    def rsf_cycle(self, parent, n_windows, parent_steps):
+        """RSF cycle; parent is an Oracle with one replica per group."""
+        self._check(self.L.ra_oracle_rsf_cycle(self.ptr, parent.ptr, int(n_windows),
+                                               int(parent_steps)), "rsf_cycle")
+
+    def block_sigma(self, block):
+        sig = np.zeros((self.n_windows, self.total_springs))
+        self._check(self.L.ra_oracle_block_sigma(self.ptr, int(block), _dp(sig)), "block_sigma")
+        return sig
+
+    def mftu(self, rate_sum):
+        rs = np.ascontiguousarray(rate_sum, dtype=np.float64)
+        out = np.zeros(len(self.descs))
+        self._check(self.L.ra_oracle_mftu(self.ptr, _dp(rs), rs.shape[0], _dp(out)), "mftu")
+        return out
+
+    def conformation(self, per_bead=False):
+        """(dbar [Rsim][3], rg2 [Rsim][3], src_rg2 [G][3][, d_bead [Rsim][N][3] per group])."""
+        nr = sum(e - b for b, e in self.ranges)
+        nb = sum((e - b) * d["n_beads"] for d, (b, e) in zip(self.descs, self.ranges))
+        dbar = np.zeros((nr, 3))
+        rg2 = np.zeros((nr, 3))
+        src = np.zeros((len(self.descs), 3))
+        db = np.zeros((nb, 3)) if per_bead else None
+        self._check(self.L.ra_oracle_conformation(self.ptr, _dp(dbar), _dp(db), _dp(rg2), _dp(src)),
+                    "conformation")
+        return (dbar, rg2, src, db) if per_bead else (dbar, rg2, src)
 
     def close(self):
         if self.ptr:

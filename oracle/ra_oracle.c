@@ -143,6 +143,8 @@ struct rao_ctx {
     double*  tsf_acc;      /* [smp] running window sums */
     double*  dmu;          /* [w][spr][3] sum over replicas of df/dtheta */
     int64_t* clamps;       /* per group */
+    double*  src;          /* [g][i][3] conformation the replicas were last cloned from */
+    uint32_t tag;          /* noise tag of this context's trajectories */
     int64_t  step;         /* steps taken since init */
     int64_t  n_windows;
     int      initialised;
@@ -163,7 +165,7 @@ void ra_oracle_destroy(rao_ctx* c)
     free(c->groups); free(c->k_begin); free(c->k_end);
     free(c->pos_off); free(c->smp_off); free(c->spr_off);
     free(c->pos); free(c->tan); free(c->samples); free(c->tsf_samples);
-    free(c->tsf_acc); free(c->dmu); free(c->clamps);
+    free(c->tsf_acc); free(c->dmu); free(c->clamps); free(c->src);
     free(c);
 }
 
@@ -218,12 +220,16 @@ int ra_oracle_create(rao_ctx** out, const rao_group* groups, int32_t n_groups,
     c->smp_off = malloc(sizeof(int64_t) * (size_t)n_groups);
     c->spr_off = malloc(sizeof(int64_t) * (size_t)n_groups);
     c->clamps = calloc((size_t)n_groups, sizeof(int64_t));
+    int64_t n_src = 0;
+    for (int g = 0; g < n_groups; ++g) n_src += 3 * (int64_t)groups[g].n_beads;
+    c->src = calloc((size_t)n_src, sizeof(double));
     if (!c->groups || !c->k_begin || !c->k_end || !c->pos_off || !c->smp_off ||
-        !c->spr_off || !c->clamps) { ra_oracle_destroy(c); return RAO_ENOMEM; }
+        !c->spr_off || !c->clamps || !c->src) { ra_oracle_destroy(c); return RAO_ENOMEM; }
     memcpy(c->groups, groups, sizeof(rao_group) * (size_t)n_groups);
     for (int g = 0; g < n_groups; ++g) { c->k_begin[g] = 0; c->k_end[g] = groups[g].n_replicas; }
     c->seed = seed; c->sample_every = sample_every; c->max_windows = max_windows;
     c->tsf = tsf ? 1 : 0; c->tangents = tangents ? 1 : 0;
+    c->tag = RAO_TAG_REPLICA;
     int rc = layout(c);
     if (rc != RAO_OK) { ra_oracle_destroy(c); return rc; }
     *out = c;
@@ -246,10 +252,11 @@ int64_t ra_oracle_clamps(const rao_ctx* c, int32_t g)
     return (c && g >= 0 && g < c->n_groups) ? c->clamps[g] : -1;
 }
 
-/* RSF clone (Sec. II): every replica starts from the parent conformation. */
-int ra_oracle_init_chains(rao_ctx* c, const double* parent_xyz)
+/* Copy the parent conformation into every simulated replica and remember it
+ * as the clone source; rejects a FENE bond at or past full extension and
+ * non-finite coordinates. */
+static int clone_from(rao_ctx* c, const double* parent_xyz)
 {
-    if (!c || !parent_xyz) return fail(c, RAO_EINVAL, "null argument");
     int64_t par = 0;
     for (int g = 0; g < c->n_groups; ++g) {
         const rao_group* d = &c->groups[g];
@@ -266,16 +273,86 @@ int ra_oracle_init_chains(rao_ctx* c, const double* parent_xyz)
         }
         for (int i = 0; i < 3 * n; ++i)
             if (!isfinite(p[i])) return fail(c, RAO_EINVAL, "non-finite parent coordinate");
+        par += 3 * n;
+    }
+    par = 0;
+    for (int g = 0; g < c->n_groups; ++g) {
+        int n = c->groups[g].n_beads;
+        const double* p = parent_xyz + par;
         int rs = c->k_end[g] - c->k_begin[g];
         for (int k = 0; k < rs; ++k)
             memcpy(c->pos + c->pos_off[g] + (int64_t)k * n * 3, p, sizeof(double) * 3 * (size_t)n);
+        memcpy(c->src + par, p, sizeof(double) * 3 * (size_t)n);
         par += 3 * n;
-        c->clamps[g] = 0;
     }
     if (c->tan) memset(c->tan, 0, sizeof(double) * (size_t)(3 * c->n_pos));
     if (c->tsf_acc) memset(c->tsf_acc, 0, sizeof(double) * (size_t)c->n_smp);
+    return RAO_OK;
+}
+
+/* RSF clone (Sec. II): every replica starts from the parent conformation. */
+int ra_oracle_init_chains(rao_ctx* c, const double* parent_xyz)
+{
+    if (!c || !parent_xyz) return fail(c, RAO_EINVAL, "null argument");
+    int rc = clone_from(c, parent_xyz);
+    if (rc != RAO_OK) return rc;
+    for (int g = 0; g < c->n_groups; ++g) c->clamps[g] = 0;
     c->step = 0; c->n_windows = 0; c->initialised = 1;
     return RAO_OK;
+}
+
+int ra_oracle_set_tag(rao_ctx* c, uint32_t tag)
+{
+    if (!c || (tag != RAO_TAG_REPLICA && tag != RAO_TAG_PARENT))
+        return fail(c, RAO_EINVAL, "tag must be REPLICA or PARENT");
+    c->tag = tag;
+    return RAO_OK;
+}
+
+/* RSF re-clone (Sec. II): at a force-sampling time the parent is halted and
+ * every replica restarts from its current conformation. The replicas' step
+ * counter becomes step0, so the replicas of each window draw their own
+ * counters (w*S + s); samples of earlier windows are kept. */
+int ra_oracle_reclone(rao_ctx* c, const double* parent_xyz, int64_t step0)
+{
+    if (!c || !parent_xyz) return fail(c, RAO_EINVAL, "null argument");
+    if (step0 < 0 || step0 % c->sample_every != 0 || step0 / c->sample_every < c->n_windows)
+        return fail(c, RAO_EINVAL, "step0 must be a multiple of S at or after the last sampled window");
+    if (c->tangents) return fail(c, RAO_ESTATE, "re-clone is not differentiated");
+    int rc = clone_from(c, parent_xyz);
+    if (rc != RAO_OK) return rc;
+    c->step = step0;
+    c->initialised = 1;
+    return RAO_OK;
+}
+
+/* The RSF sampling cycle (Sec. II). Window w: the parent chain (context par,
+ * one replica per group, parent noise tag) continues its own trajectory for
+ * parent_steps steps, which par samples as one window (ISF at the end, TSF
+ * over the steps when par keeps TSF); the parent is halted, the replicas are
+ * re-cloned from its conformation and evolve for S steps, and each replica's
+ * spring tensions are sampled once at the end (RSF window w). */
+int ra_oracle_rsf_cycle(rao_ctx* rep, rao_ctx* par, int64_t n_windows, int64_t parent_steps)
+{
+    if (!rep || !par || n_windows < 0 || parent_steps < 1) return fail(rep, RAO_EINVAL, "bad argument");
+    if (par->n_groups != rep->n_groups || par->sample_every != parent_steps || !par->initialised)
+        return fail(rep, RAO_EINVAL, "parent context must match groups, sample every parent_steps, be initialised");
+    for (int g = 0; g < rep->n_groups; ++g)
+        if (par->groups[g].n_beads != rep->groups[g].n_beads || par->k_end[g] - par->k_begin[g] != 1)
+            return fail(rep, RAO_EINVAL, "parent context needs one chain of the same length per group");
+    double* xyz = malloc(sizeof(double) * (size_t)(par->n_pos + 1));
+    if (!xyz) return fail(rep, RAO_ENOMEM, "out of host memory");
+    int rc = RAO_OK;
+    const int64_t w0 = rep->n_windows;
+    for (int64_t w = w0; w < w0 + n_windows && rc == RAO_OK; ++w) {
+        rc = ra_oracle_step(par, parent_steps);
+        if (rc != RAO_OK) { fail(rep, rc, ra_oracle_last_error(par)); break; }
+        memcpy(xyz, par->pos, sizeof(double) * (size_t)par->n_pos);
+        rc = ra_oracle_reclone(rep, xyz, w * rep->sample_every);
+        if (rc == RAO_OK) rc = ra_oracle_step(rep, rep->sample_every);
+    }
+    free(xyz);
+    return rc;
 }
 
 /* Pathwise derivatives of the spring force for the forward-mode tangents.
@@ -357,7 +434,7 @@ static void em_step_replica(rao_ctx* c, int g, int kk, uint32_t n,
     /* position update */
     for (int i = 0; i < N; ++i) {
         double xi[3], v[3];
-        rao_noise(c->seed, n, (uint32_t)i, (uint32_t)k, RAO_TAG_REPLICA, d->stream_id, xi);
+        rao_noise(c->seed, n, (uint32_t)i, (uint32_t)k, c->tag, d->stream_id, xi);
         rao_flow_velocity(d->flow, d->rate, r + 3 * i, v);
         if (c->tangents) {
             for (int p = 0; p < 3; ++p) {
@@ -540,6 +617,115 @@ int ra_oracle_backward(rao_ctx* c, const double* grad_mean, const double* grad_r
         for (int p = 0; p < 3; ++p) grad_params[3 * g + p] = acc[p];
     }
     free(mean);
+    return RAO_OK;
+}
+
+/* Spread of the RSF estimator for N_R = block replicas (Figs. 2 and 5):
+ * the R replicas of a group are split into B = floor(R/block) consecutive
+ * blocks, each block's mean tension is one RSF estimate, and sigma is their
+ * standard deviation (denominator B-1) per window and spring. */
+int ra_oracle_block_sigma(const rao_ctx* c, int32_t block, double* sigma)
+{
+    if (!c || !sigma || block < 1) return RAO_EINVAL;
+    for (int64_t w = 0; w < c->n_windows; ++w)
+        for (int g = 0; g < c->n_groups; ++g) {
+            int N = c->groups[g].n_beads;
+            int rs = c->k_end[g] - c->k_begin[g];
+            int B = rs / block;
+            for (int j = 0; j + 1 < N; ++j) {
+                double sum = 0.0;
+                for (int b = 0; b < B; ++b) {
+                    double m = 0.0;
+                    for (int q = 0; q < block; ++q)
+                        m += c->samples[w * c->n_smp + c->smp_off[g] + (int64_t)(b * block + q) * (N - 1) + j];
+                    sum += m / block;
+                }
+                double mu = B > 0 ? sum / B : 0.0;
+                double ss = 0.0;
+                for (int b = 0; b < B; ++b) {
+                    double m = 0.0;
+                    for (int q = 0; q < block; ++q)
+                        m += c->samples[w * c->n_smp + c->smp_off[g] + (int64_t)(b * block + q) * (N - 1) + j];
+                    double e = m / block - mu;
+                    ss += e * e;
+                }
+                sigma[w * c->n_spr + c->spr_off[g] + j] = B > 1 ? sqrt(ss / (B - 1)) : 0.0;
+            }
+        }
+    return RAO_OK;
+}
+
+/* Mean first-passage time to any event on a chain (MFTU, Sec. III): with
+ * the per-chain total rate K_w = sum_j k_j held over each window, and K
+ * stationary over the run, the first event time is exponential with mean
+ * 1 / <K>, <K> the average of K_w over the windows. */
+int ra_oracle_mftu(const rao_ctx* c, const double* rate_sum, int64_t n_windows, double* mftu)
+{
+    if (!c || !rate_sum || !mftu || n_windows < 1) return RAO_EINVAL;
+    for (int g = 0; g < c->n_groups; ++g) {
+        double sum = 0.0;
+        for (int64_t w = 0; w < n_windows; ++w) sum += rate_sum[w * c->n_groups + g];
+        mftu[g] = 1.0 / (sum / (double)n_windows);
+    }
+    return RAO_OK;
+}
+
+/* Centre-of-mass-frame coordinates of one chain: out[i][a] = r[i][a] - r_cm[a]. */
+static void com_frame(const double* r, int N, double* out)
+{
+    double cm[3] = { 0.0, 0.0, 0.0 };
+    for (int i = 0; i < N; ++i)
+        for (int a = 0; a < 3; ++a) cm[a] += r[3 * i + a];
+    for (int a = 0; a < 3; ++a) cm[a] /= N;
+    for (int i = 0; i < N; ++i)
+        for (int a = 0; a < 3; ++a) out[3 * i + a] = r[3 * i + a] - cm[a];
+}
+
+/* Replica fidelity (Sec. IV, Eq. 5): for replica k and component a,
+ * dbar[k][a] = (1/N) sum_i |rhat_a^i(k) - rhat_a^i(source)|, rhat the
+ * centre-of-mass-frame coordinates and source the conformation the replicas
+ * were last cloned from; d_bead[k][i][a] the same without the bead average.
+ * rg2[k][a] = (1/N) sum_i (rhat_a^i)^2, the component contributions to the
+ * squared radius of gyration (R_Gz^2 is a = z); src_rg2[g][a] likewise for
+ * the source. Replicas are the simulated ones, groups concatenated. Any
+ * output may be NULL. */
+int ra_oracle_conformation(const rao_ctx* c, double* dbar, double* d_bead, double* rg2, double* src_rg2)
+{
+    if (!c || !c->initialised) return RAO_EINVAL;
+    int nmax = 2;
+    for (int g = 0; g < c->n_groups; ++g) if (c->groups[g].n_beads > nmax) nmax = c->groups[g].n_beads;
+    double* hs = malloc(sizeof(double) * 3 * (size_t)nmax);
+    double* hr = malloc(sizeof(double) * 3 * (size_t)nmax);
+    if (!hs || !hr) { free(hs); free(hr); return RAO_ENOMEM; }
+    int64_t src_off = 0, kglob = 0, bglob = 0;
+    for (int g = 0; g < c->n_groups; ++g) {
+        int N = c->groups[g].n_beads;
+        int rs = c->k_end[g] - c->k_begin[g];
+        com_frame(c->src + src_off, N, hs);
+        if (src_rg2)
+            for (int a = 0; a < 3; ++a) {
+                double v = 0.0;
+                for (int i = 0; i < N; ++i) v += hs[3 * i + a] * hs[3 * i + a];
+                src_rg2[3 * g + a] = v / N;
+            }
+        for (int k = 0; k < rs; ++k, ++kglob) {
+            com_frame(c->pos + c->pos_off[g] + (int64_t)k * N * 3, N, hr);
+            for (int a = 0; a < 3; ++a) {
+                double dsum = 0.0, rsum = 0.0;
+                for (int i = 0; i < N; ++i) {
+                    double d = fabs(hr[3 * i + a] - hs[3 * i + a]);
+                    if (d_bead) d_bead[(bglob + (int64_t)k * N + i) * 3 + a] = d;
+                    dsum += d;
+                    rsum += hr[3 * i + a] * hr[3 * i + a];
+                }
+                if (dbar) dbar[kglob * 3 + a] = dsum / N;
+                if (rg2) rg2[kglob * 3 + a] = rsum / N;
+            }
+        }
+        bglob += (int64_t)rs * N;
+        src_off += 3 * N;
+    }
+    free(hs); free(hr);
     return RAO_OK;
 }
 

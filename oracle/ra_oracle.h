@@ -89,6 +89,24 @@ int  ra_oracle_bell_rates(rao_ctx* c, const double* mean, int64_t n_windows,
  * (rate, H, b) per group; needs tangents=1 at create; grad_rates may be NULL */
 int  ra_oracle_backward(rao_ctx* c, const double* grad_mean, const double* grad_rates,
                         double k0, double x_dagger, double* grad_params);
+/* noise tag of the context's trajectories: RAO_TAG_REPLICA (default) or RAO_TAG_PARENT */
+int  ra_oracle_set_tag(rao_ctx* c, uint32_t tag);
+/* RSF re-clone (Sec. II): every replica restarts from parent_xyz; the step
+ * counter becomes step0 (a multiple of S, not before the last sampled window);
+ * earlier windows are kept */
+int  ra_oracle_reclone(rao_ctx* c, const double* parent_xyz, int64_t step0);
+/* RSF cycle (Sec. II): per window the parent context (one chain per group,
+ * sample_every = parent_steps) advances parent_steps steps, the replicas are
+ * re-cloned from it at step0 = w*S and advance S steps */
+int  ra_oracle_rsf_cycle(rao_ctx* rep, rao_ctx* par, int64_t n_windows, int64_t parent_steps);
+/* sigma[W][sum_g (N_g-1)]: std over floor(R/block) consecutive replica blocks of the block mean */
+int  ra_oracle_block_sigma(const rao_ctx* c, int32_t block, double* sigma);
+/* mftu[g] = 1 / (mean over windows of rate_sum[w][g]) */
+int  ra_oracle_mftu(const rao_ctx* c, const double* rate_sum, int64_t n_windows, double* mftu);
+/* Eq. 5 fidelity dbar[k][3], per-bead d_bead[k][i][3], squared radius of
+ * gyration components rg2[k][3] and src_rg2[g][3] of the clone source */
+int  ra_oracle_conformation(const rao_ctx* c, double* dbar, double* d_bead, double* rg2,
+                            double* src_rg2);
 /* per-replica tension samples [W][sum_g Rsub_g*(N_g-1)] and TSF values */
 int  ra_oracle_get_samples(const rao_ctx* c, double* out, double* tsf_out);
 /* bead positions [sum_g Rsub_g*N_g*3] */
