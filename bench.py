@@ -13,8 +13,10 @@ value = replica*bead*steps per second (1024 * 50 * 10^4 per step / time).
 Also reported, each measured once after warm-up: the plain unbatched GPU path
 on the same workload (one launch per EM step, state in HBM; speedup), the
 adjoint (N = 100, 4096 replicas, 2000 steps, checkpoints every 100), the
-batched run (512 uneven FENE chains, one graph-captured persistent launch)
-and the 1000-bead transient (8192 replicas, 2e4 steps, RSF + TSF).
+batched run (512 uneven FENE chains, one graph-captured persistent launch),
+the 1000-bead transient (8192 replicas, 2e4 steps, RSF + TSF) and the RSF
+sampling cycle (a parent trajectory re-cloned into 1000 replicas every 750
+steps, 20 windows, with ISF/TSF/RSF, sigma(N_R) and MFTU).
 The roofline object is for the fused forward kernel; its time is taken with
 HIP events on the stream the kernel runs on. cpu_baseline is the FP64 oracle
 on a bounded sample of the same workload, on the host's cores.
@@ -109,7 +111,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="plain,adjoint,batched,large1000",
+    ap.add_argument("--extras", default="plain,adjoint,batched,large1000,rsf50",
                     help="comma-separated extra workloads to measure once")
     ap.add_argument("--cpu-replicas", type=int, default=384)
     ap.add_argument("--tile-policy", type=int, default=0,
@@ -298,6 +300,44 @@ def main():
                             "value": lwork / tbig, "ms_per_step": 1e3 * tbig}
         big.close()
         log("large1000: %.1f ms" % (1e3 * tbig))
+
+    if "rsf50" in extras:
+        # RSF sampling cycle: parent trajectory on its own stream, re-clone per window
+        rg, rp, rrun = wl.rsf50()
+        rS, rP, rW = rrun["sample_every"], rrun["parent_steps"], rrun["n_windows"]
+        pstream = torch.cuda.Stream()
+        rpar = ra.Replicas([dict(x, n_replicas=1) for x in rg], rrun["seed"], sample_every=rP, max_windows=rW,
+                           tsf=True, noise_tag=1, stream=pstream, use_graph=True, device=dev)
+        rrep = ra.Replicas(rg, rrun["seed"], sample_every=rS, max_windows=rW, use_graph=True, device=dev)
+        mftu = {}
+        rpd = torch.from_numpy(np.concatenate([np.ravel(x) for x in rp])).to(dev)
+
+        def rsf_cycle():
+            rpar.init_chains(rpd)
+            rrep.init_chains(rpd)
+            rrep.rsf_cycle(rpar, rW, rP)
+            isf, _, tsf, _ = rpar.average_forces(tsf=True)
+            rsf, _ = rrep.average_forces()
+            for b in rrun["blocks"]:
+                rrep.block_sigma(b)
+            for name, prof in (("isf", isf), ("tsf", tsf), ("rsf", rsf)):
+                _, rs = rpar.bell_rates(prof, rrun["k0"], rrun["x_dagger"])
+                mftu[name] = rpar.mftu(rs)
+
+        rsf_cycle()
+        trsf = min(time_once(rsf_cycle) for _ in range(2))
+        rpar.sync_status()
+        rrep.sync_status()
+        rwork = rg[0]["n_replicas"] * rg[0]["n_beads"] * rS * rW
+        out["rsf50"] = {"workload": "rsf50: RSF cycle, FENE N=50 b=100, shear Wi=50, parent + 1000 replicas "
+                                    "re-cloned every 750 steps, S=750, 20 windows, ISF/TSF/RSF, "
+                                    "sigma(N_R=10,20,40,50), Bell rates and MFTU",
+                        "value": rwork / trsf, "unit": "replica·bead·steps/s (whole cycle incl. parent)",
+                        "ms_per_cycle": 1e3 * trsf, "us_per_window": 1e6 * trsf / rW,
+                        "mftu": {k: float(v[0]) for k, v in mftu.items()}}
+        rpar.close()
+        rrep.close()
+        log("rsf50: %.2f ms per cycle (%.1f us per window)" % (1e3 * trsf, 1e6 * trsf / rW))
 
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB

@@ -31,7 +31,8 @@
  *   - Spring j of a chain joins beads j and j+1 (0-based), N-1 springs.
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key =
  *     (seed low, seed high) and counter = (step, bead, replica,
- *     tag<<24 | stream_id); tag 0 drives replica noise, tag 2 Bell events.
+ *     tag<<24 | stream_id); tag 0 drives replica noise, tag 1 a parent
+ *     trajectory (noise_tag = 1), tag 2 Bell events.
  *     A group's results depend only on its descriptor, its parent, the seed
  *     and the step count: never on which other groups share the context.
  */
@@ -81,7 +82,7 @@ typedef struct {
     uint32_t pad_;
 } ra_chain_desc;
 
-/* Run options (host struct, 48 bytes). */
+/* Run options (host struct, 56 bytes). */
 typedef struct {
     uint64_t seed;              /* Philox key */
     int32_t  precision;         /* 32: FP32 state, FP64 averages; 64: all FP64 */
@@ -96,6 +97,8 @@ typedef struct {
                                    without the noise-producer split; 3 force the split
                                    where legal; 1000 + m: force m beads per lane */
     int32_t  waves_per_block;   /* 0 = default (4) */
+    int32_t  noise_tag;         /* 0: replica noise; 1: parent trajectory (RSF cycle, Sec. II) */
+    int32_t  reserved_;         /* must be 0 */
 } ra_run_desc;
 
 /* Create a context: validates every descriptor (RA_EINVAL with nothing
@@ -145,6 +148,58 @@ RA_API ra_status ra_bell_rates(ra_ctx* ctx, const double* mean, int64_t n_window
 RA_API ra_status ra_backward(ra_ctx* ctx, const double* mean, const double* grad_mean,
                              const double* grad_rates, double k0, double x_dagger,
                              double* grad_params);
+
+/* RSF re-clone (Sec. II): at a force-sampling time the parent chain is halted
+ * and every replica of group g restarts from the current state of group g's
+ * first chain in `parent` (a context with the same groups and chain lengths,
+ * normally one chain per group and noise_tag = 1, same precision, fused path).
+ * The context's step count must be a multiple of S and is kept: the replicas
+ * of window w continue with counters (w*S + s, bead, replica, group),
+ * distinct from every other window's, and earlier windows stay available to
+ * ra_average_forces. The context must have been created but need not have
+ * been initialised. Stream-ordered after the parent's queued work when both
+ * contexts use the same stream; otherwise the caller orders the two streams
+ * (ra_rsf_cycle does). The re-cloned conformation becomes the reference of
+ * ra_conformation. After a re-clone ra_backward returns RA_ESTATE until the
+ * next ra_init_chains. */
+RA_API ra_status ra_reclone(ra_ctx* ctx, const ra_ctx* parent);
+
+/* The RSF sampling cycle (Sec. II) for n_windows windows, continuing from the
+ * windows already sampled: per window the parent context advances
+ * parent_steps steps (its sample_every must equal parent_steps, so each
+ * window also records the parent's instantaneous tensions (ISF) and, with
+ * tsf = 1, their time average over the window (TSF)); the replicas are
+ * re-cloned from it and evolve S steps; their tensions are sampled once at the
+ * end (RSF). When the two contexts have different streams, the parent's next
+ * window overlaps the replicas' current one (ordered by HIP events). Capacity
+ * of both contexts is checked before anything is enqueued. */
+RA_API ra_status ra_rsf_cycle(ra_ctx* ctx, ra_ctx* parent, int64_t n_windows, int64_t parent_steps);
+
+/* Spread of the RSF estimate for N_R = block replicas (Figs. 2 and 5): per
+ * window and spring, the R replicas of a group are split into
+ * B = floor(R/block) consecutive blocks, each block mean is one RSF estimate,
+ * and sigma = their standard deviation (denominator B-1; 0 when B < 2).
+ * sigma: device FP64 [W][sum_g(N_g-1)]; block >= 1. */
+RA_API ra_status ra_block_sigma(ra_ctx* ctx, int32_t block, double* sigma);
+
+/* Mean first-passage time to any event on a chain (MFTU, Sec. III, Table 1):
+ * mftu[g] = 1 / (mean over the n_windows windows of rate_sum[w][g]), the mean
+ * of an exponential first-event time with the run-averaged total rate.
+ * rate_sum: device FP64 [n_windows][n_groups] from ra_bell_rates; mftu: device
+ * FP64 [n_groups]; n_windows >= 1. */
+RA_API ra_status ra_mftu(ra_ctx* ctx, const double* rate_sum, int64_t n_windows, double* mftu);
+
+/* Replica fidelity (Sec. IV, Eq. 5) and radius of gyration, from the current
+ * state of every replica, in the centre-of-mass frame:
+ *   dbar[q][a]   = (1/N) sum_i |rhat_a^i(q) - rhat_a^i(source)|,
+ *   d_bead[b][a] = the same term for one bead, b = (replica, bead) flattened,
+ *   rg2[q][a]    = (1/N) sum_i rhat_a^i(q)^2 (a = z gives R_Gz^2),
+ *   src_rg2[g][a] likewise for group g's source conformation,
+ * where source is the conformation of the last ra_init_chains or ra_reclone
+ * and q runs over all replicas, groups concatenated. Device FP64 outputs
+ * [sum_g R_g][3], [sum_g R_g N_g][3], [sum_g R_g][3], [n_groups][3]; any may
+ * be NULL. Fused path only. */
+RA_API ra_status ra_conformation(ra_ctx* ctx, double* dbar, double* d_bead, double* rg2, double* src_rg2);
 
 /* Synchronise the context's stream and report device-side errors:
  * RA_EINVAL (invalid parent), RA_EUNSTABLE (non-finite tension) or RA_OK. */

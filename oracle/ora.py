@@ -77,7 +77,7 @@ def lib():
         L.ra_oracle_get_samples.argtypes = [P, dp, dp]
         L.ra_oracle_get_positions.argtypes = [P, dp]
         L.ra_oracle_set_tag.argtypes = [P, ctypes.c_uint32]
-        L.ra_oracle_reclone.argtypes = [P, dp, ctypes.c_int64]
+        L.ra_oracle_reclone.argtypes = [P, dp]
         L.ra_oracle_rsf_cycle.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
         L.ra_oracle_block_sigma.argtypes = [P, ctypes.c_int32, dp]
         L.ra_oracle_mftu.argtypes = [P, dp, ctypes.c_int64, dp]
@@ -272,10 +272,10 @@ class Oracle:
     def set_tag(self, tag):
         self._check(self.L.ra_oracle_set_tag(self.ptr, int(tag)), "set_tag")
 
-    def reclone(self, parent_xyz, step0):
+    def reclone(self, parent_xyz):
         p = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64).ravel()
                                                  for x in parent_xyz]))
-        self._check(self.L.ra_oracle_reclone(self.ptr, _dp(p), int(step0)), "reclone")
+        self._check(self.L.ra_oracle_reclone(self.ptr, _dp(p)), "reclone")
 
     def rsf_cycle(self, parent, n_windows, parent_steps):
         """RSF cycle; parent is an Oracle with one replica per group."""

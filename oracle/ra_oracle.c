@@ -310,18 +310,17 @@ int ra_oracle_set_tag(rao_ctx* c, uint32_t tag)
 }
 
 /* RSF re-clone (Sec. II): at a force-sampling time the parent is halted and
- * every replica restarts from its current conformation. The replicas' step
- * counter becomes step0, so the replicas of each window draw their own
- * counters (w*S + s); samples of earlier windows are kept. */
-int ra_oracle_reclone(rao_ctx* c, const double* parent_xyz, int64_t step0)
+ * every replica restarts from its current conformation. The replicas keep
+ * their step count, a multiple of S, so the replicas of each window draw their
+ * own counters (w*S + s); samples of earlier windows are kept. */
+int ra_oracle_reclone(rao_ctx* c, const double* parent_xyz)
 {
     if (!c || !parent_xyz) return fail(c, RAO_EINVAL, "null argument");
-    if (step0 < 0 || step0 % c->sample_every != 0 || step0 / c->sample_every < c->n_windows)
-        return fail(c, RAO_EINVAL, "step0 must be a multiple of S at or after the last sampled window");
+    if (c->step % c->sample_every != 0)
+        return fail(c, RAO_EINVAL, "re-clone only at a window boundary (step count a multiple of S)");
     if (c->tangents) return fail(c, RAO_ESTATE, "re-clone is not differentiated");
     int rc = clone_from(c, parent_xyz);
     if (rc != RAO_OK) return rc;
-    c->step = step0;
     c->initialised = 1;
     return RAO_OK;
 }
@@ -331,7 +330,8 @@ int ra_oracle_reclone(rao_ctx* c, const double* parent_xyz, int64_t step0)
  * parent_steps steps, which par samples as one window (ISF at the end, TSF
  * over the steps when par keeps TSF); the parent is halted, the replicas are
  * re-cloned from its conformation and evolve for S steps, and each replica's
- * spring tensions are sampled once at the end (RSF window w). */
+ * spring tensions are sampled once at the end (RSF window w). The replicas'
+ * windows continue from those already sampled. */
 int ra_oracle_rsf_cycle(rao_ctx* rep, rao_ctx* par, int64_t n_windows, int64_t parent_steps)
 {
     if (!rep || !par || n_windows < 0 || parent_steps < 1) return fail(rep, RAO_EINVAL, "bad argument");
@@ -343,12 +343,11 @@ int ra_oracle_rsf_cycle(rao_ctx* rep, rao_ctx* par, int64_t n_windows, int64_t p
     double* xyz = malloc(sizeof(double) * (size_t)(par->n_pos + 1));
     if (!xyz) return fail(rep, RAO_ENOMEM, "out of host memory");
     int rc = RAO_OK;
-    const int64_t w0 = rep->n_windows;
-    for (int64_t w = w0; w < w0 + n_windows && rc == RAO_OK; ++w) {
+    for (int64_t w = 0; w < n_windows && rc == RAO_OK; ++w) {
         rc = ra_oracle_step(par, parent_steps);
         if (rc != RAO_OK) { fail(rep, rc, ra_oracle_last_error(par)); break; }
         memcpy(xyz, par->pos, sizeof(double) * (size_t)par->n_pos);
-        rc = ra_oracle_reclone(rep, xyz, w * rep->sample_every);
+        rc = ra_oracle_reclone(rep, xyz);
         if (rc == RAO_OK) rc = ra_oracle_step(rep, rep->sample_every);
     }
     free(xyz);

@@ -92,12 +92,11 @@ int  ra_oracle_backward(rao_ctx* c, const double* grad_mean, const double* grad_
 /* noise tag of the context's trajectories: RAO_TAG_REPLICA (default) or RAO_TAG_PARENT */
 int  ra_oracle_set_tag(rao_ctx* c, uint32_t tag);
 /* RSF re-clone (Sec. II): every replica restarts from parent_xyz; the step
- * counter becomes step0 (a multiple of S, not before the last sampled window);
- * earlier windows are kept */
-int  ra_oracle_reclone(rao_ctx* c, const double* parent_xyz, int64_t step0);
+ * count (a multiple of S) is kept, and so are earlier windows */
+int  ra_oracle_reclone(rao_ctx* c, const double* parent_xyz);
 /* RSF cycle (Sec. II): per window the parent context (one chain per group,
  * sample_every = parent_steps) advances parent_steps steps, the replicas are
- * re-cloned from it at step0 = w*S and advance S steps */
+ * re-cloned from it and advance S steps */
 int  ra_oracle_rsf_cycle(rao_ctx* rep, rao_ctx* par, int64_t n_windows, int64_t parent_steps);
 /* sigma[W][sum_g (N_g-1)]: std over floor(R/block) consecutive replica blocks of the block mean */
 int  ra_oracle_block_sigma(const rao_ctx* c, int32_t block, double* sigma);

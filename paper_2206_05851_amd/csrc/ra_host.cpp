@@ -53,8 +53,13 @@ struct ra_ctx {
     int32_t* status = nullptr;
     unsigned long long* clamps = nullptr;
     int64_t* dstep = nullptr;
+    double* src = nullptr;          // [sum_g N_g][3] centre-of-mass frame of the clone source
+    int64_t* drep_off = nullptr;    // [n_groups + 1] first replica of each group
+    int64_t n_reps = 0;
+    hipEvent_t ev_parent = nullptr, ev_reclone = nullptr;   // RSF cycle across two streams
     int64_t step = 0;
     bool initialised = false;
+    bool recloned = false;          // a re-clone since the last init (no adjoint)
     std::map<int64_t, hipGraphExec_t> graphs;
     std::string err;
 };
@@ -92,6 +97,8 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
         why = "the adjoint (checkpoint_every > 0) needs precision 32 and the fused path";
         return RA_EINVAL;
     }
+    if (r->noise_tag != 0 && r->noise_tag != 1) { why = "noise_tag must be 0 or 1"; return RA_EINVAL; }
+    if (r->reserved_ != 0) { why = "reserved_ must be 0"; return RA_EINVAL; }
     const int wpb = r->waves_per_block ? r->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4) { why = "waves_per_block must be 0, 1, 2 or 4"; return RA_EINVAL; }
     for (int i = 0; i < n; ++i) {
@@ -117,7 +124,7 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
     return RA_OK;
 }
 
-GroupDev make_group(const ra_chain_desc& d, int M) {
+GroupDev make_group(const ra_chain_desc& d, int M, int tag) {
     GroupDev G{};
     G.N = d.n_beads;
     G.R = d.n_replicas;
@@ -125,7 +132,7 @@ GroupDev make_group(const ra_chain_desc& d, int M) {
     G.L = (d.n_beads + M - 1) / M;
     G.P = WAVE / G.L;
     G.spring = d.spring;
-    G.stream = d.stream_id & 0xFFFFFFu;   // tag 0: replica noise
+    G.stream = ((uint32_t)tag << 24) | (d.stream_id & 0xFFFFFFu);   // tag 0 replicas, 1 parent
     G.flow = d.flow;
     double kx = 0, ky = 0, kz = 0, kxz = 0;
     switch (d.flow) {
@@ -170,9 +177,11 @@ void ra_destroy(ra_ctx* c) {
     // pos[1] points into the pos[0] allocation and is not freed on its own
     void* ptrs[] = {c->dgroups, c->ditems, c->dtiles, c->dpar_off, c->ditem_begin, c->state, c->pos[0],
                     c->samples, c->tsf, c->tsf_acc, c->ckpt, c->segbuf, c->dseg_off,
-                    c->partial, c->lam_mu, c->status, c->clamps, c->dstep};
+                    c->partial, c->lam_mu, c->status, c->clamps, c->dstep, c->src, c->drep_off};
     for (void* p : ptrs)
         if (p) hipFree(p);
+    if (c->ev_parent) hipEventDestroy(c->ev_parent);
+    if (c->ev_reclone) hipEventDestroy(c->ev_reclone);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -239,7 +248,7 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     std::vector<int64_t> par_off(n_groups);
     int64_t par = 0;
     for (int i = 0; i < n_groups; ++i) {
-        GroupDev G = make_group(groups[i], Ms[i]);
+        GroupDev G = make_group(groups[i], Ms[i], run->noise_tag);
         const int64_t nm1 = G.N - 1;
         G.state_off = c->state_total;
         G.smp_off = c->smp_total;
@@ -291,6 +300,8 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     ALLOC(c->status, 1);
     ALLOC(c->clamps, n_groups);
     ALLOC(c->dstep, 1);
+    ALLOC(c->src, par);
+    ALLOC(c->drep_off, n_groups + 1);
     if (run->plain) {
         ALLOC(p8, 2 * c->pos_total * esz);
         c->pos[0] = p8;
@@ -332,6 +343,13 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     HIPCHK(c, hipMemcpy(c->ditems, c->hitems.data(), c->hitems.size() * sizeof(Item), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->dtiles, c->htiles.data(), c->htiles.size() * sizeof(ColTile), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->dpar_off, par_off.data(), n_groups * sizeof(int64_t), hipMemcpyHostToDevice));
+    {
+        std::vector<int64_t> ro(n_groups + 1, 0);
+        for (int i = 0; i < n_groups; ++i) ro[i + 1] = ro[i] + groups[i].n_replicas;
+        c->n_reps = ro[n_groups];
+        HIPCHK(c, hipMemcpy(c->drep_off, ro.data(), ro.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    HIPCHK(c, hipMemset(c->src, 0, par * sizeof(double)));
     HIPCHK(c, hipMemset(c->status, 0, sizeof(int32_t)));
     HIPCHK(c, hipMemset(c->clamps, 0, n_groups * sizeof(unsigned long long)));
     HIPCHK(c, hipMemset(c->dstep, 0, sizeof(int64_t)));
@@ -352,8 +370,10 @@ ra_status ra_init_chains(ra_ctx* c, const double* parent_xyz) {
     HIPCHK(c, launch_clone(c->dgroups, ng, c->max_group_elems, parent_xyz, c->dpar_off,
                            plain ? c->pos[0] : c->state, c->tsf_acc, c->status, c->run.precision, plain,
                            c->stream));
+    HIPCHK(c, launch_src_from_xyz(c->dgroups, ng, parent_xyz, c->dpar_off, c->src, c->stream));
     c->step = 0;
     c->initialised = true;
+    c->recloned = false;
     return RA_OK;
 }
 
@@ -490,6 +510,7 @@ ra_status ra_backward(ra_ctx* c, const double* mean, const double* grad_mean, co
     if (!c) return fail(nullptr, RA_EINVAL, "null context");
     if (c->run.checkpoint_every <= 0) return fail(c, RA_ESTATE, "ra_backward needs checkpoint_every > 0");
     if (!c->initialised) return fail(c, RA_ESTATE, "ra_backward before ra_init_chains");
+    if (c->recloned) return fail(c, RA_ESTATE, "ra_backward does not differentiate through a re-clone");
     if (!grad_params) return fail(c, RA_EINVAL, "grad_params is null");
     if (grad_rates && !mean) return fail(c, RA_EINVAL, "grad_rates needs mean");
     const int ng = (int)c->hgroups.size();
@@ -521,6 +542,112 @@ ra_status ra_backward(ra_ctx* c, const double* mean, const double* grad_mean, co
         b = e;
     }
     HIPCHK(c, launch_grad_reduce(c->ditem_begin, ng, c->partial, grad_params, c->stream));
+    return RA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// RSF cycle (Sec. II): re-clone from a parent context, the cycle driver, and
+// the estimators built on the sampled windows.
+// ---------------------------------------------------------------------------
+static ra_status check_parent(ra_ctx* c, const ra_ctx* p) {
+    if (!p) return fail(c, RA_EINVAL, "parent is null");
+    if (p == c) return fail(c, RA_EINVAL, "parent must be another context");
+    if (c->run.plain || p->run.plain) return fail(c, RA_EINVAL, "re-clone needs the fused path in both contexts");
+    if (p->run.precision != c->run.precision) return fail(c, RA_EINVAL, "parent precision differs");
+    if (p->descs.size() != c->descs.size()) return fail(c, RA_EINVAL, "parent has a different number of groups");
+    for (size_t g = 0; g < c->descs.size(); ++g)
+        if (p->descs[g].n_beads != c->descs[g].n_beads)
+            return fail(c, RA_EINVAL, "parent group " + std::to_string(g) + " has a different chain length");
+    if (!p->initialised) return fail(c, RA_ESTATE, "parent context not initialised");
+    return RA_OK;
+}
+
+// The capacity checks of ra_step for n_steps more steps, without enqueuing.
+static bool step_fits(const ra_ctx* c, int64_t n_steps, std::string& why) {
+    const int64_t end = c->step + n_steps;
+    if (end > (int64_t)0xFFFFFFFF) { why = "total steps would exceed 2^32"; return false; }
+    if (end / c->run.sample_every > c->run.max_windows) { why = "window capacity exceeded"; return false; }
+    if (c->run.checkpoint_every > 0 && end > c->run.max_steps) { why = "checkpoint capacity exceeded"; return false; }
+    return true;
+}
+
+ra_status ra_reclone(ra_ctx* c, const ra_ctx* parent) {
+    if (!c) return fail(nullptr, RA_EINVAL, "null context");
+    ra_status st = check_parent(c, parent);
+    if (st != RA_OK) return st;
+    if (c->step % c->run.sample_every != 0)
+        return fail(c, RA_EINVAL, "re-clone only at a window boundary (step count a multiple of S)");
+    const int ng = (int)c->hgroups.size();
+    HIPCHK(c, launch_reclone(c->dgroups, parent->dgroups, ng, c->max_group_elems, parent->state, c->state, c->tsf_acc,
+                             c->status, c->run.precision, c->stream));
+    HIPCHK(c, launch_src_from_bonds(c->dgroups, parent->dgroups, ng, parent->state, c->dpar_off, c->src,
+                                    c->run.precision, c->stream));
+    HIPCHK(c, launch_set_step(c->dstep, c->step, c->stream));
+    c->initialised = true;
+    c->recloned = true;
+    return RA_OK;
+}
+
+ra_status ra_rsf_cycle(ra_ctx* c, ra_ctx* parent, int64_t n_windows, int64_t parent_steps) {
+    if (!c) return fail(nullptr, RA_EINVAL, "null context");
+    ra_status st = check_parent(c, parent);
+    if (st != RA_OK) return st;
+    if (n_windows < 0 || parent_steps < 1) return fail(c, RA_EINVAL, "n_windows < 0 or parent_steps < 1");
+    if (parent->run.sample_every != parent_steps)
+        return fail(c, RA_EINVAL, "the parent context must sample every parent_steps steps");
+    const int S = c->run.sample_every;
+    if (c->step % S != 0) return fail(c, RA_EINVAL, "the replicas are not at a window boundary");
+    std::string why;
+    if (!step_fits(parent, n_windows * parent_steps, why)) return fail(c, RA_EINVAL, "parent: " + why);
+    if (!step_fits(c, n_windows * (int64_t)S, why)) return fail(c, RA_EINVAL, why);
+    const bool two = parent->stream != c->stream;
+    if (two && !c->ev_parent) {
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_parent, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_reclone, hipEventDisableTiming));
+    }
+    for (int64_t w = 0; w < n_windows; ++w) {
+        // the parent's next window may start once the last re-clone has read its state
+        if (two && w > 0) HIPCHK(c, hipStreamWaitEvent(parent->stream, c->ev_reclone, 0));
+        st = ra_step(parent, parent_steps);
+        if (st != RA_OK) return fail(c, st, "parent: " + parent->err);
+        if (two) {
+            HIPCHK(c, hipEventRecord(c->ev_parent, parent->stream));
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_parent, 0));
+        }
+        st = ra_reclone(c, parent);
+        if (st != RA_OK) return st;
+        if (two) HIPCHK(c, hipEventRecord(c->ev_reclone, c->stream));
+        st = ra_step(c, S);
+        if (st != RA_OK) return st;
+    }
+    // later work on the parent's stream must not overwrite the state before the last re-clone read it
+    if (two && n_windows > 0) HIPCHK(c, hipStreamWaitEvent(parent->stream, c->ev_reclone, 0));
+    return RA_OK;
+}
+
+ra_status ra_block_sigma(ra_ctx* c, int32_t block, double* sigma) {
+    if (!c) return fail(nullptr, RA_EINVAL, "null context");
+    if (!sigma || block < 1) return fail(c, RA_EINVAL, "sigma is null or block < 1");
+    if (!c->initialised) return fail(c, RA_ESTATE, "ra_block_sigma before ra_init_chains");
+    const int64_t W = c->step / c->run.sample_every;
+    HIPCHK(c, launch_block_sigma(c->dgroups, c->dtiles, (int)c->htiles.size(), W, c->samples, c->smp_total,
+                                 c->spr_total, block, sigma, c->run.precision, c->stream));
+    return RA_OK;
+}
+
+ra_status ra_mftu(ra_ctx* c, const double* rate_sum, int64_t n_windows, double* mftu) {
+    if (!c) return fail(nullptr, RA_EINVAL, "null context");
+    if (!rate_sum || !mftu || n_windows < 1) return fail(c, RA_EINVAL, "null argument or n_windows < 1");
+    HIPCHK(c, launch_mftu(rate_sum, n_windows, (int)c->hgroups.size(), mftu, c->stream));
+    return RA_OK;
+}
+
+ra_status ra_conformation(ra_ctx* c, double* dbar, double* d_bead, double* rg2, double* src_rg2) {
+    if (!c) return fail(nullptr, RA_EINVAL, "null context");
+    if (c->run.plain) return fail(c, RA_EINVAL, "ra_conformation needs the fused path");
+    if (!c->initialised) return fail(c, RA_ESTATE, "ra_conformation before ra_init_chains");
+    HIPCHK(c, launch_conformation(c->dgroups, (int)c->hgroups.size(), c->drep_off, c->n_reps, c->state, c->dpar_off,
+                                  c->src, dbar, d_bead, rg2, src_rg2, c->run.precision, c->stream));
     return RA_OK;
 }
 

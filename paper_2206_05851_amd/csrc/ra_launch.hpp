@@ -75,4 +75,21 @@ hipError_t launch_lam_mu(const GroupDev* groups, int n_groups, int64_t n_windows
 hipError_t launch_grad_reduce(const int32_t* item_begin, int n_groups, const double* partial,
                               double* grad_params, hipStream_t st);
 
+// RSF cycle and estimators (ra_rsf.hip)
+hipError_t launch_reclone(const GroupDev* groups, const GroupDev* pgroups, int n_groups, int64_t max_elems,
+                          const void* pstate, void* state, double* tsf_acc, int32_t* status, int precision,
+                          hipStream_t st);
+hipError_t launch_set_step(int64_t* step, int64_t value, hipStream_t st);
+hipError_t launch_src_from_xyz(const GroupDev* groups, int n_groups, const double* parent, const int64_t* par_off,
+                               double* src, hipStream_t st);
+hipError_t launch_src_from_bonds(const GroupDev* groups, const GroupDev* pgroups, int n_groups, const void* pstate,
+                                 const int64_t* par_off, double* src, int precision, hipStream_t st);
+hipError_t launch_conformation(const GroupDev* groups, int n_groups, const int64_t* rep_off, int64_t n_reps,
+                               const void* state, const int64_t* par_off, const double* src, double* dbar,
+                               double* d_bead, double* rg2, double* src_rg2, int precision, hipStream_t st);
+hipError_t launch_block_sigma(const GroupDev* groups, const ColTile* tiles, int n_tiles, int64_t n_windows,
+                              const void* smp, int64_t smp_total, int64_t spr_total, int block, double* sigma,
+                              int precision, hipStream_t st);
+hipError_t launch_mftu(const double* rate_sum, int64_t n_windows, int n_groups, double* mftu, hipStream_t st);
+
 }  // namespace ra

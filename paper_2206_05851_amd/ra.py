@@ -20,7 +20,8 @@ _NAMES = {RA_EINVAL: "RA_EINVAL", RA_ENOMEM: "RA_ENOMEM", RA_EDEVICE: "RA_EDEVIC
 
 # Every symbol include/ra.h declares.
 EXPORTS = ["ra_create", "ra_init_chains", "ra_step", "ra_average_forces", "ra_bell_rates",
-           "ra_backward", "ra_sync_status", "ra_guard_counts", "ra_get_samples", "ra_get_bonds",
+           "ra_backward", "ra_reclone", "ra_rsf_cycle", "ra_block_sigma", "ra_mftu", "ra_conformation",
+           "ra_sync_status", "ra_guard_counts", "ra_get_samples", "ra_get_bonds",
            "ra_tile_info", "ra_debug_noise", "ra_last_error", "ra_destroy"]
 
 
@@ -45,10 +46,11 @@ class RunDesc(ctypes.Structure):
                 ("tsf", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
                 ("max_steps", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("tile_policy", ctypes.c_int32),
-                ("waves_per_block", ctypes.c_int32)]
+                ("waves_per_block", ctypes.c_int32), ("noise_tag", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32)]
 
 
-assert ctypes.sizeof(ChainDesc) == 80 and ctypes.sizeof(RunDesc) == 48
+assert ctypes.sizeof(ChainDesc) == 80 and ctypes.sizeof(RunDesc) == 56
 
 _lib = None
 
@@ -70,6 +72,11 @@ def library():
         "ra_average_forces": [P, P, P, P, P, ctypes.POINTER(i64)],
         "ra_bell_rates": [P, P, i64, dbl, dbl, P, P, P],
         "ra_backward": [P, P, P, P, dbl, dbl, P],
+        "ra_reclone": [P, P],
+        "ra_rsf_cycle": [P, P, i64, i64],
+        "ra_block_sigma": [P, i32, P],
+        "ra_mftu": [P, P, i64, P],
+        "ra_conformation": [P, P, P, P, P],
         "ra_sync_status": [P],
         "ra_guard_counts": [P, ctypes.POINTER(i64)],
         "ra_get_samples": [P, P, P],
@@ -140,7 +147,7 @@ class Replicas:
 
     def __init__(self, groups, seed, precision=32, sample_every=100, max_windows=100, tsf=False,
                  checkpoint_every=0, max_steps=0, plain=False, use_graph=False, tile_policy=0,
-                 waves_per_block=0, device=None, stream=None):
+                 waves_per_block=0, noise_tag=0, device=None, stream=None):
         self.L = library()
         self.groups = [dict(g) for g in groups]
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -152,7 +159,7 @@ class Replicas:
         run = RunDesc(seed=int(seed), precision=precision, sample_every=sample_every,
                       max_windows=max_windows, tsf=int(bool(tsf)), checkpoint_every=checkpoint_every,
                       max_steps=max_steps, plain=int(bool(plain)), use_graph=int(bool(use_graph)),
-                      tile_policy=tile_policy, waves_per_block=waves_per_block)
+                      tile_policy=tile_policy, waves_per_block=waves_per_block, noise_tag=noise_tag)
         self._descs = arr
         self.ptr = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -170,6 +177,17 @@ class Replicas:
         if rc != RA_OK:
             raise RAError(rc, self.L.ra_last_error(self.ptr).decode())
 
+    # A context may run on its own stream; tensors are made and read on the
+    # caller's current stream. Order the two around every call that takes or
+    # returns tensors.
+    def _enter(self):
+        if self.stream is not None:
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        if self.stream is not None:
+            torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     def _dev(self, shape, dtype=torch.float64):
         return torch.empty(shape, dtype=dtype, device=self.device)
 
@@ -180,6 +198,7 @@ class Replicas:
             flat = torch.cat([torch.as_tensor(p, dtype=torch.float64).reshape(-1) for p in parents])
             parents = flat.to(self.device)
         self._parents = parents.contiguous()
+        self._enter()
         self._check(self.L.ra_init_chains(self.ptr, _ptr(self._parents)))
         self.n_windows = 0
 
@@ -197,7 +216,9 @@ class Replicas:
             mean, std = out
         tm = self._dev((W.value, self.n_springs)) if tsf else None
         ts = self._dev((W.value, self.n_springs)) if tsf else None
+        self._enter()
         self._check(self.L.ra_average_forces(self.ptr, _ptr(mean), _ptr(std), _ptr(tm), _ptr(ts), None))
+        self._leave()
         return (mean, std, tm, ts) if tsf else (mean, std)
 
     def bell_rates(self, mean, k0, x_dagger, events=False):
@@ -205,17 +226,61 @@ class Replicas:
         rates = self._dev((W, self.n_springs))
         rsum = self._dev((W, len(self.groups)))
         ev = self._dev((W, self.n_springs), torch.uint8) if events else None
+        self._enter()
         self._check(self.L.ra_bell_rates(self.ptr, _ptr(mean), W, float(k0), float(x_dagger),
                                          _ptr(rates), _ptr(rsum), _ptr(ev)))
+        self._leave()
         return (rates, rsum, ev) if events else (rates, rsum)
 
     def backward(self, mean, grad_mean, grad_rates=None, k0=0.0, x_dagger=0.0):
         out = self._dev((len(self.groups), 3))
         gm = grad_mean.contiguous() if grad_mean is not None else None
         gr = grad_rates.contiguous() if grad_rates is not None else None
+        self._enter()
         self._check(self.L.ra_backward(self.ptr, _ptr(mean), _ptr(gm), _ptr(gr), float(k0),
                                        float(x_dagger), _ptr(out)))
+        self._leave()
         return out
+
+    def reclone(self, parent):
+        """RSF re-clone (Sec. II) from another context's current chains."""
+        self._check(self.L.ra_reclone(self.ptr, parent.ptr))
+
+    def rsf_cycle(self, parent, n_windows, parent_steps):
+        """RSF sampling cycle (Sec. II) driven by a parent context."""
+        self._check(self.L.ra_rsf_cycle(self.ptr, parent.ptr, int(n_windows), int(parent_steps)))
+
+    def block_sigma(self, block):
+        """Spread of the RSF estimate over blocks of `block` replicas, [W, springs]."""
+        W = ctypes.c_int64()
+        self._check(self.L.ra_average_forces(self.ptr, None, None, None, None, ctypes.byref(W)))
+        out = self._dev((W.value, self.n_springs))
+        self._enter()
+        self._check(self.L.ra_block_sigma(self.ptr, int(block), _ptr(out)))
+        self._leave()
+        return out
+
+    def mftu(self, rate_sum):
+        """1 / (window mean of the per-chain total rate), one value per group."""
+        out = self._dev((len(self.groups),))
+        rs = rate_sum.contiguous()
+        self._enter()
+        self._check(self.L.ra_mftu(self.ptr, _ptr(rs), rs.shape[0], _ptr(out)))
+        self._leave()
+        return out
+
+    def conformation(self, per_bead=False):
+        """(dbar [sum R][3], rg2 [sum R][3], src_rg2 [G][3][, d_bead [sum R N][3]]) (Eq. 5)."""
+        nr = sum(g["n_replicas"] for g in self.groups)
+        nb = sum(g["n_replicas"] * g["n_beads"] for g in self.groups)
+        dbar = self._dev((nr, 3))
+        rg2 = self._dev((nr, 3))
+        src = self._dev((len(self.groups), 3))
+        db = self._dev((nb, 3)) if per_bead else None
+        self._enter()
+        self._check(self.L.ra_conformation(self.ptr, _ptr(dbar), _ptr(db), _ptr(rg2), _ptr(src)))
+        self._leave()
+        return (dbar, rg2, src, db) if per_bead else (dbar, rg2, src)
 
     def sync_status(self):
         self._check(self.L.ra_sync_status(self.ptr))
@@ -231,7 +296,9 @@ class Replicas:
         self._check(self.L.ra_average_forces(self.ptr, None, None, None, None, ctypes.byref(W)))
         flat = self._dev((W.value, self.n_samples))
         tflat = self._dev((W.value, self.n_samples)) if tsf else None
+        self._enter()
         self._check(self.L.ra_get_samples(self.ptr, _ptr(flat), _ptr(tflat)))
+        self._leave()
         outs, touts, off = [], [], 0
         for g in self.groups:
             m = g["n_replicas"] * (g["n_beads"] - 1)
@@ -244,7 +311,9 @@ class Replicas:
     def bonds(self):
         """Current bond vectors, one tensor [R_g, N_g-1, 3] per group (FP64)."""
         flat = self._dev((self.n_bond_values,))
+        self._enter()
         self._check(self.L.ra_get_bonds(self.ptr, _ptr(flat)))
+        self._leave()
         outs, off = [], 0
         for g in self.groups:
             m = g["n_replicas"] * (g["n_beads"] - 1) * 3

@@ -137,3 +137,17 @@ def large1000(n_replicas=8192, steps=20000):
     parent = equilibrium_parent(N, FENE, 1.0, 400.0, seed=103)
     return [g], [parent], dict(seed=4, steps=steps, sample_every=500, precision=32,
                                k0=1e-6, x_dagger=0.1, tsf=True)
+
+
+def rsf50(n_replicas=1000, n_windows=20):
+    """RSF sampling cycle (Sec. II) on a FENE chain N=50, b=100, in simple
+    shear at Wi=50: one parent trajectory (parent noise tag) halted every 750
+    steps, 1000 replicas re-cloned from it and evolved for S=750 steps
+    (dt=1e-4), 20 windows; ISF and TSF from the parent, RSF from the
+    replicas, sigma(N_R) over blocks of 10, 20, 40 and 50 replicas, Bell rates
+    and MFTU with k0=1e-6, x=0.1."""
+    N = 50
+    g = group(N, n_replicas, 1e-4, FENE, 1.0, 100.0, SHEAR, wi_to_rate(50.0, N))
+    parent = equilibrium_parent(N, FENE, 1.0, 100.0, seed=104)
+    return [g], [parent], dict(seed=5, sample_every=750, parent_steps=750, n_windows=n_windows,
+                               precision=32, k0=1e-6, x_dagger=0.1, blocks=(10, 20, 40, 50))

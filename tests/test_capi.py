@@ -44,9 +44,9 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_sizes_match_header():
     from paper_2206_05851_amd import ra
     text = open(os.path.join(ROOT, "include", "ra.h")).read()
-    assert "80 bytes" in text and "48 bytes" in text
+    assert "80 bytes" in text and "56 bytes" in text
     assert ctypes.sizeof(ra.ChainDesc) == 80
-    assert ctypes.sizeof(ra.RunDesc) == 48
+    assert ctypes.sizeof(ra.RunDesc) == 56
 
 
 def _create(lib, desc_kw, run_kw):
@@ -76,6 +76,8 @@ def _create(lib, desc_kw, run_kw):
     ({}, dict(checkpoint_every=10, precision=64), "adjoint"),
     ({}, dict(checkpoint_every=10, plain=1), "adjoint"),
     ({}, dict(waves_per_block=3), "waves_per_block"),
+    ({}, dict(noise_tag=2), "noise_tag"),
+    ({}, dict(reserved_=1), "reserved_"),
 ])
 def test_invalid_descriptors_rejected_on_host(lib, desc_kw, run_kw, frag):
     rc, msg = _create(lib, desc_kw, run_kw)
@@ -87,4 +89,9 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.ra_step(None, 10) == -1
     assert lib.ra_init_chains(None, None) == -1
     assert lib.ra_backward(None, None, None, None, 0.0, 0.0, None) == -1
+    assert lib.ra_reclone(None, None) == -1
+    assert lib.ra_rsf_cycle(None, None, 1, 1) == -1
+    assert lib.ra_block_sigma(None, 1, None) == -1
+    assert lib.ra_mftu(None, None, 1, None) == -1
+    assert lib.ra_conformation(None, None, None, None, None) == -1
     lib.ra_destroy(None)

@@ -1,0 +1,170 @@
+"""GPU RSF sampling cycle (Sec. II re-clone from a parent trajectory), block
+spread sigma(N_R), MFTU and the Eq. 5 fidelity / radius-of-gyration
+diagnostics, against the oracle on the same seeds and counters."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_err, require_gpu
+from paper_2206_05851_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _gpu_pair(groups, parents, seed, S, P, W, precision=32, two_streams=False, use_graph=False):
+    import torch
+    from paper_2206_05851_amd import ra
+    pstream = torch.cuda.Stream() if two_streams else None
+    par = ra.Replicas([dict(g, n_replicas=1) for g in groups], seed, precision=precision, sample_every=P,
+                      max_windows=W, tsf=True, noise_tag=1, stream=pstream, use_graph=use_graph)
+    par.init_chains(parents)
+    rep = ra.Replicas(groups, seed, precision=precision, sample_every=S, max_windows=W, use_graph=use_graph)
+    return par, rep
+
+
+def _oracle_pair(groups, parents, seed, S, P, W, ranges=None):
+    from oracle import ora
+    par = ora.Oracle([dict(g, n_replicas=1) for g in groups], seed, P, W, tsf=True)
+    par.set_tag(ora.TAG_PARENT)
+    par.init_chains(parents)
+    rep = ora.Oracle(groups, seed, S, W)
+    for g, r in (ranges or {}).items():
+        rep.set_replicas(g, *r)
+    return par, rep
+
+
+def _run_both(groups, parents, seed, S, P, W, **kw):
+    import torch
+    gp, gr = _gpu_pair(groups, parents, seed, S, P, W, **kw)
+    gr.rsf_cycle(gp, W, P)
+    isf, _, tsf, _ = gp.average_forces(tsf=True)
+    rsf, rstd = gr.average_forces()
+    torch.cuda.synchronize()
+    gp.sync_status()
+    gr.sync_status()
+    op, orr = _oracle_pair(groups, parents, seed, S, P, W)
+    orr.rsf_cycle(op, W, P)
+    oisf, _, otsf, _ = op.average_forces(tsf=True)
+    orsf, orstd = orr.average_forces()
+    return (gp, gr, isf.cpu().numpy(), tsf.cpu().numpy(), rsf.cpu().numpy(), rstd.cpu().numpy()), \
+           (op, orr, oisf, otsf, orsf, orstd)
+
+
+@pytest.mark.parametrize("two_streams", [False, True])
+def test_rsf_cycle_matches_oracle(two_streams):
+    gs = [wl.group(24, 48, 1e-4, wl.FENE, 1.0, 60.0, wl.SHEAR, wl.wi_to_rate(40.0, 24), stream_id=3),
+          wl.group(10, 20, 1e-3, wl.HOOKEAN, 1.0, 0.0, wl.UNIAXIAL, wl.wi_to_rate(0.4, 10), stream_id=9)]
+    ps = [wl.equilibrium_parent(24, wl.FENE, 1.0, 60.0, seed=5), wl.equilibrium_parent(10, seed=6)]
+    S, P, W = 40, 30, 5
+    announce("rsf cycle two_streams=%s" % two_streams)
+    (gp, gr, isf, tsf, rsf, rstd), (op, orr, oisf, otsf, orsf, orstd) = _run_both(gs, ps, 11, S, P, W,
+                                                                                   two_streams=two_streams)
+    e = [rel_err(isf, oisf, 1e-3), rel_err(tsf, otsf, 1e-3), rel_err(rsf, orsf, 1e-3), rel_err(rstd, orstd, 1e-3)]
+    announce("isf %.2e tsf %.2e rsf %.2e std %.2e" % tuple(e))
+    assert max(e) < 1e-4
+    # MFTU of each estimate through the parent context (window = parent_steps)
+    import torch
+    for prof, oprof in ((isf, oisf), (tsf, otsf), (rsf, orsf)):
+        _, rs = gp.bell_rates(torch.from_numpy(prof).cuda(), 1e-3, 0.1)
+        m = gp.mftu(rs).cpu().numpy()
+        _, ors = op.bell_rates(oprof, 1e-3, 0.1)
+        assert rel_err(m, op.mftu(ors)) < 1e-5
+
+
+def test_rsf_cycle_fp64_matches_oracle_tightly():
+    gs = [wl.group(10, 32, 1e-3, wl.HOOKEAN, 1.0, 0.0, wl.PLANAR, 0.2)]
+    ps = [wl.equilibrium_parent(10, seed=1)]
+    announce("rsf cycle fp64")
+    (_, _, isf, tsf, rsf, rstd), (_, _, oisf, otsf, orsf, orstd) = _run_both(gs, ps, 3, 50, 20, 4, precision=64)
+    assert max(rel_err(isf, oisf), rel_err(tsf, otsf), rel_err(rsf, orsf), rel_err(rstd, orstd)) < 1e-10
+
+
+def test_rsf_cycle_graph_replay_is_bitwise_eager():
+    gs = [wl.group(30, 40, 1e-4, wl.FENE, 1.0, 80.0, wl.PLANAR, 0.5)]
+    ps = [wl.equilibrium_parent(30, wl.FENE, 1.0, 80.0, seed=2)]
+    out = []
+    for graph in (False, True):
+        gp, gr = _gpu_pair(gs, ps, 4, 25, 25, 6, use_graph=graph, two_streams=graph)
+        gr.rsf_cycle(gp, 3, 25)
+        gr.rsf_cycle(gp, 3, 25)
+        out.append((gp.average_forces(tsf=True)[2].cpu().numpy(), gr.average_forces()[0].cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_block_sigma_definition_and_oracle():
+    import torch
+    gs = [wl.group(12, 200, 1e-3, wl.FENE, 1.0, 50.0, wl.UNIAXIAL, 0.1)]
+    ps = [wl.equilibrium_parent(12, wl.FENE, 1.0, 50.0, seed=8)]
+    (gp, gr, *_), (op, orr, *_) = _run_both(gs, ps, 21, 30, 30, 3)
+    smp = gr.samples()[0].cpu().numpy()          # [W][R][N-1]
+    for nr in (10, 20, 40, 64, 200, 300):
+        sig = gr.block_sigma(nr).cpu().numpy()
+        torch.cuda.synchronize()
+        B = 200 // nr
+        if B >= 2:
+            bm = smp[:, :B * nr].reshape(3, B, nr, 11).mean(axis=2)
+            assert rel_err(sig, bm.std(axis=1, ddof=1), 1e-12) < 1e-12
+        else:
+            assert np.all(sig == 0.0)
+        assert rel_err(sig, orr.block_sigma(nr), 1e-3) < 1e-4
+
+
+def test_conformation_after_cycle_matches_oracle():
+    gs = [wl.group(40, 16, 1e-4, wl.FENE, 1.0, 100.0, wl.SHEAR, wl.wi_to_rate(50.0, 40), stream_id=1),
+          wl.group(7, 9, 1e-3, wl.HOOKEAN, 1.0, 0.0, wl.QUIESCENT, 0.0, stream_id=2)]
+    ps = [wl.equilibrium_parent(40, wl.FENE, 1.0, 100.0, seed=3), wl.equilibrium_parent(7, seed=4)]
+    (gp, gr, *_), (op, orr, *_) = _run_both(gs, ps, 6, 60, 40, 3)
+    dbar, rg2, srg2, db = [t.cpu().numpy() for t in gr.conformation(per_bead=True)]
+    odbar, org2, osrg2, odb = orr.conformation(per_bead=True)
+    e = [rel_err(dbar, odbar, 1e-2), rel_err(rg2, org2, 1e-2), rel_err(srg2, osrg2, 1e-2),
+         np.max(np.abs(db - odb))]
+    announce("conformation dbar %.2e rg2 %.2e src %.2e d_bead abs %.2e" % tuple(e))
+    assert max(e[:3]) < 1e-4 and e[3] < 1e-4
+    assert np.all(dbar > 0)
+    # right after a fresh clone every replica is its source (FP32 rounding only)
+    from paper_2206_05851_amd import ra
+    fresh = ra.Replicas(gs, 6, sample_every=10, max_windows=1)
+    fresh.init_chains(ps)
+    d0, r0, s0 = [t.cpu().numpy() for t in fresh.conformation()]
+    assert np.max(d0) < 1e-5
+    assert rel_err(r0, np.repeat(s0, [16, 9], axis=0)) < 1e-5
+
+
+def test_reclone_and_cycle_errors():
+    from paper_2206_05851_amd import ra
+    g = wl.group(10, 8, 1e-3)
+    p = wl.equilibrium_parent(10, seed=0)
+    rep = ra.Replicas([g], 0, sample_every=10, max_windows=4, checkpoint_every=10, max_steps=40)
+    par = ra.Replicas([dict(g, n_replicas=1)], 0, sample_every=10, max_windows=4, noise_tag=1)
+    with pytest.raises(ra.RAError, match="RA_ESTATE"):
+        rep.reclone(par)                          # parent not initialised
+    par.init_chains([p])
+    other = ra.Replicas([wl.group(11, 1, 1e-3)], 0, sample_every=10, max_windows=4)
+    other.init_chains([wl.equilibrium_parent(11, seed=0)])
+    with pytest.raises(ra.RAError, match="RA_EINVAL"):
+        rep.reclone(other)                        # chain length differs
+    f64 = ra.Replicas([dict(g, n_replicas=1)], 0, precision=64, sample_every=10, max_windows=4)
+    f64.init_chains([p])
+    with pytest.raises(ra.RAError, match="RA_EINVAL"):
+        rep.reclone(f64)                          # precision differs
+    with pytest.raises(ra.RAError, match="RA_EINVAL"):
+        rep.rsf_cycle(par, 2, 7)                  # parent samples every 10, not 7
+    with pytest.raises(ra.RAError, match="RA_EINVAL"):
+        rep.rsf_cycle(par, 5, 10)                 # window capacity of 4
+    rep.rsf_cycle(par, 2, 10)
+    rep.step(5)
+    with pytest.raises(ra.RAError, match="RA_EINVAL"):
+        rep.reclone(par)                          # mid-window
+    rep.step(5)
+    mean, _ = rep.average_forces()
+    import torch
+    with pytest.raises(ra.RAError, match="RA_ESTATE"):
+        rep.backward(mean, torch.zeros_like(mean))   # no adjoint through a re-clone
+    rep.init_chains([p])
+    rep.step(10)
+    rep.backward(mean[:1].contiguous(), torch.zeros_like(mean[:1]))
+    rep.sync_status()

@@ -128,17 +128,16 @@ def test_parent_step_uses_parent_tag():
     assert np.max(np.abs(rep.positions()[0][0] - got)) > 1e-3
 
 
-def test_reclone_rejects_steps_before_sampled_windows():
+def test_reclone_only_at_window_boundaries():
     desc = wl.group(3, 2, 1e-3)
     o = ora.Oracle([desc], 0, 10, 5)
     p = wl.equilibrium_parent(3, seed=0)
     o.init_chains([p])
-    o.step(20)
+    o.step(15)
     with pytest.raises(ora.OracleError):
-        o.reclone([p], 10)
-    with pytest.raises(ora.OracleError):
-        o.reclone([p], 25)
-    o.reclone([p], 20)
+        o.reclone([p])
+    o.step(5)
+    o.reclone([p])
     o.step(10)
     assert o.n_windows == 3
 
