@@ -16,7 +16,8 @@ adjoint (N = 100, 4096 replicas, 2000 steps, checkpoints every 100), the
 batched run (512 uneven FENE chains, one graph-captured persistent launch),
 the 1000-bead transient (8192 replicas, 2e4 steps, RSF + TSF) and the RSF
 sampling cycle (a parent trajectory re-cloned into 1000 replicas every 750
-steps, 20 windows, with ISF/TSF/RSF, sigma(N_R) and MFTU).
+steps, 20 windows, with ISF/TSF/RSF, sigma(N_R) and MFTU) on the FENE chain
+and on the paper's collapsed polymer (rest-length springs + LJ, no HI).
 The roofline object is for the fused forward kernel; its time is taken with
 HIP events on the stream the kernel runs on. cpu_baseline is the FP64 oracle
 on a bounded sample of the same workload, on the host's cores.
@@ -104,6 +105,48 @@ def time_once(fn):
     return time.perf_counter() - t0
 
 
+def rsf_cycle_bench(workload, desc, dev, name):
+    """One RSF cycle (parent context on its own stream, re-clone per window)
+    with the estimators built on it, timed after a warm-up cycle."""
+    import numpy as np
+    import torch
+    from paper_2206_05851_amd import ra
+    rg, rp, rrun = workload
+    rS, rP, rW = rrun["sample_every"], rrun["parent_steps"], rrun["n_windows"]
+    pstream = torch.cuda.Stream()
+    rpar = ra.Replicas([dict(x, n_replicas=1) for x in rg], rrun["seed"], sample_every=rP, max_windows=rW,
+                       tsf=True, noise_tag=1, stream=pstream, use_graph=True, device=dev)
+    rrep = ra.Replicas(rg, rrun["seed"], sample_every=rS, max_windows=rW, use_graph=True, device=dev)
+    mftu = {}
+    rpd = torch.from_numpy(np.concatenate([np.ravel(x) for x in rp])).to(dev)
+
+    def cycle():
+        rpar.init_chains(rpd)
+        rrep.init_chains(rpd)
+        rrep.rsf_cycle(rpar, rW, rP)
+        isf, _, tsf, _ = rpar.average_forces(tsf=True)
+        rsf, _ = rrep.average_forces()
+        for b in rrun["blocks"]:
+            rrep.block_sigma(b)
+        rrep.conformation()
+        for key, prof in (("isf", isf), ("tsf", tsf), ("rsf", rsf)):
+            _, rs = rpar.bell_rates(prof, rrun["k0"], rrun["x_dagger"])
+            mftu[key] = rpar.mftu(rs)
+
+    cycle()
+    t = min(time_once(cycle) for _ in range(2))
+    rpar.sync_status()
+    rrep.sync_status()
+    work = rg[0]["n_replicas"] * rg[0]["n_beads"] * rS * rW
+    res = {"workload": name + ": " + desc, "value": work / t,
+           "unit": "replica·bead·steps/s (whole cycle incl. parent)", "ms_per_cycle": 1e3 * t,
+           "us_per_window": 1e6 * t / rW, "mftu": {k: float(v[0]) for k, v in mftu.items()}}
+    rpar.close()
+    rrep.close()
+    log("%s: %.2f ms per cycle (%.1f us per window)" % (name, 1e3 * t, 1e6 * t / rW))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,7 +154,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="plain,adjoint,batched,large1000,rsf50",
+    ap.add_argument("--extras", default="plain,adjoint,batched,large1000,rsf50,collapsed50",
                     help="comma-separated extra workloads to measure once")
     ap.add_argument("--cpu-replicas", type=int, default=384)
     ap.add_argument("--tile-policy", type=int, default=0,
@@ -301,43 +344,15 @@ def main():
         big.close()
         log("large1000: %.1f ms" % (1e3 * tbig))
 
-    if "rsf50" in extras:
-        # RSF sampling cycle: parent trajectory on its own stream, re-clone per window
-        rg, rp, rrun = wl.rsf50()
-        rS, rP, rW = rrun["sample_every"], rrun["parent_steps"], rrun["n_windows"]
-        pstream = torch.cuda.Stream()
-        rpar = ra.Replicas([dict(x, n_replicas=1) for x in rg], rrun["seed"], sample_every=rP, max_windows=rW,
-                           tsf=True, noise_tag=1, stream=pstream, use_graph=True, device=dev)
-        rrep = ra.Replicas(rg, rrun["seed"], sample_every=rS, max_windows=rW, use_graph=True, device=dev)
-        mftu = {}
-        rpd = torch.from_numpy(np.concatenate([np.ravel(x) for x in rp])).to(dev)
-
-        def rsf_cycle():
-            rpar.init_chains(rpd)
-            rrep.init_chains(rpd)
-            rrep.rsf_cycle(rpar, rW, rP)
-            isf, _, tsf, _ = rpar.average_forces(tsf=True)
-            rsf, _ = rrep.average_forces()
-            for b in rrun["blocks"]:
-                rrep.block_sigma(b)
-            for name, prof in (("isf", isf), ("tsf", tsf), ("rsf", rsf)):
-                _, rs = rpar.bell_rates(prof, rrun["k0"], rrun["x_dagger"])
-                mftu[name] = rpar.mftu(rs)
-
-        rsf_cycle()
-        trsf = min(time_once(rsf_cycle) for _ in range(2))
-        rpar.sync_status()
-        rrep.sync_status()
-        rwork = rg[0]["n_replicas"] * rg[0]["n_beads"] * rS * rW
-        out["rsf50"] = {"workload": "rsf50: RSF cycle, FENE N=50 b=100, shear Wi=50, parent + 1000 replicas "
-                                    "re-cloned every 750 steps, S=750, 20 windows, ISF/TSF/RSF, "
-                                    "sigma(N_R=10,20,40,50), Bell rates and MFTU",
-                        "value": rwork / trsf, "unit": "replica·bead·steps/s (whole cycle incl. parent)",
-                        "ms_per_cycle": 1e3 * trsf, "us_per_window": 1e6 * trsf / rW,
-                        "mftu": {k: float(v[0]) for k, v in mftu.items()}}
-        rpar.close()
-        rrep.close()
-        log("rsf50: %.2f ms per cycle (%.1f us per window)" % (1e3 * trsf, 1e6 * trsf / rW))
+    for rname, rdesc in (("rsf50", "RSF cycle, FENE N=50 b=100, shear Wi=50, parent + 1000 replicas "
+                                   "re-cloned every 750 steps, S=750, 20 windows, ISF/TSF/RSF, "
+                                   "sigma(N_R=10,20,40,50), Bell rates and MFTU"),
+                         ("collapsed50", "RSF cycle on the collapsed polymer without HI: N=50, harmonic "
+                                         "backbone kappa=400 rest length 2, LJ u=1 between non-adjacent "
+                                         "beads, shear 30, dt=1e-5, parent + 1000 replicas re-cloned every "
+                                         "750 steps (S=0.0075), 20 windows, ISF/TSF/RSF, sigma(N_R), MFTU")):
+        if rname in extras:
+            out[rname] = rsf_cycle_bench(getattr(wl, rname)(), rdesc, dev, rname)
 
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB

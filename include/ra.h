@@ -8,8 +8,9 @@
  *   - every replica is advanced by the Brownian-dynamics update of Eq. (1),
  *     here with only the self term of the diffusion tensor, Eq. (2)
  *     (free-draining), under a homogeneous flow v = kappa . r;
- *   - after an evolution time S the tension of each spring (Eq. (4) with a
- *     zero-rest-length Hookean or FENE spring) is sampled once per replica
+ *   - after an evolution time S the tension of each spring (Eq. (4): signed
+ *     for the rest-length spring, the magnitude for zero-rest-length Hookean
+ *     and FENE springs) is sampled once per replica
  *     and averaged over replicas (RSF); optionally it is also averaged over
  *     the steps of the window (TSF, Sec. II);
  *   - the averaged tension feeds a Bell-type rate k = k0 exp(x_dagger f/kT)
@@ -58,26 +59,37 @@ typedef enum {
     RA_ESTATE = -5      /* call out of order (e.g. ra_step before ra_init_chains) */
 } ra_status;
 
-typedef enum { RA_HOOKEAN = 0, RA_FENE = 1 } ra_spring;
+typedef enum { RA_HOOKEAN = 0, RA_FENE = 1, RA_HARMONIC = 2 } ra_spring;
 typedef enum { RA_QUIESCENT = 0, RA_UNIAXIAL = 1, RA_PLANAR = 2, RA_SHEAR = 3 } ra_flow;
 
-/* One group = one parent chain and its replicas (host struct, 80 bytes).
- * Spring force on bead j from spring j: F = H g Q, Q = r_{j+1} - r_j,
- * g = 1 (Hookean) or 1/(1 - min(|Q|^2/Q0^2, 1 - 1e-3)) (FENE, Q0^2 = b kT/H).
+/* One group = one parent chain and its replicas (host struct, 104 bytes).
+ * Spring force on bead j from spring j: F = H g Q, Q = r_{j+1} - r_j, with
+ *   Hookean  g = 1, tension f = H |Q|;
+ *   FENE     g = 1/(1 - min(|Q|^2/Q0^2, 1 - 1e-3)), Q0^2 = b kT/H, f = H g |Q|;
+ *   HARMONIC g = 1 - r0/|Q| (rest length r0, the Sec. II backbone spring
+ *            kappa/2 (r - 2a)^2 with kappa = H), signed tension f = H (|Q| - r0)
+ *            (Eq. 4).
+ * Optional Lennard-Jones self-association between non-adjacent beads
+ * (|i - j| >= 2, Sec. II): U = lj_eps [(lj_rmin/r)^12 - 2 (lj_rmin/r)^6].
+ * Groups with a HARMONIC spring or lj_eps > 0 run the pair-interaction kernel
+ * (N <= 64, no adjoint); a context holds either only such groups or none.
  * Flow: uniaxial kappa = rate*diag(1,-1/2,-1/2); planar rate*diag(1,-1,0);
  * shear v_x = rate * z (the paper's convention, Sec. II). */
 typedef struct {
-    int32_t  n_beads;      /* N, 2 <= N <= 1024 (FP64: N <= 256) */
+    int32_t  n_beads;      /* N, 2 <= N <= 1024 (FP64: N <= 256; pair kernel: N <= 64) */
     int32_t  n_replicas;   /* R >= 1 */
     int32_t  spring;       /* ra_spring */
     int32_t  flow;         /* ra_flow */
     double   H;            /* spring constant > 0 */
-    double   b;            /* FENE extensibility > 0 (ignored for Hookean) */
+    double   b;            /* FENE extensibility > 0 (FENE only) */
     double   rate;         /* strain rate or shear rate (not a Weissenberg number) */
     double   kT;           /* thermal energy > 0 */
     double   zeta;         /* bead friction > 0 */
     double   dt;           /* time step > 0 */
     double   noise_scale;  /* 1 = physical noise; 0 = deterministic */
+    double   rest_length;  /* HARMONIC rest length r0 >= 0 (ignored otherwise) */
+    double   lj_eps;       /* LJ well depth >= 0 (0 = no LJ) */
+    double   lj_rmin;      /* LJ minimum position > 0 when lj_eps > 0 */
     uint32_t stream_id;    /* group id in the random counter, < 2^24 */
     uint32_t pad_;
 } ra_chain_desc;
@@ -218,8 +230,9 @@ RA_API ra_status ra_get_bonds(ra_ctx* ctx, double* out);
 
 /* Tile chosen per group (host int32[n_groups] each): beads per lane and
  * replicas per wavefront; kernel_family (host int32[1], may be NULL): 1 = one
- * bead per lane with a noise-producer wavefront per work item, 4 = 1-4 beads
- * per lane, 16 = 6-16 beads per lane, 0 = plain path. */
+ * bead per lane with a noise-producer wavefront per work item, 2 = the
+ * pair-interaction kernel (one bead per lane; LJ and rest-length springs),
+ * 4 = 1-4 beads per lane, 16 = 6-16 beads per lane, 0 = plain path. */
 RA_API ra_status ra_tile_info(ra_ctx* ctx, int32_t* beads_per_lane, int32_t* replicas_per_wave,
                               int32_t* kernel_family);
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ra_oracle.c")
 LIB = os.path.join(HERE, "libra_oracle.so")
 
-HOOKEAN, FENE = 0, 1
+HOOKEAN, FENE, HARMONIC = 0, 1, 2
 QUIESCENT, UNIAXIAL, PLANAR, SHEAR = 0, 1, 2, 3
 TAG_REPLICA, TAG_PARENT, TAG_EVENT = 0, 1, 2
 
@@ -35,8 +35,9 @@ class Group(ctypes.Structure):
                 ("spring", ctypes.c_int32), ("flow", ctypes.c_int32),
                 ("H", ctypes.c_double), ("b", ctypes.c_double), ("rate", ctypes.c_double),
                 ("kT", ctypes.c_double), ("zeta", ctypes.c_double), ("dt", ctypes.c_double),
-                ("noise_scale", ctypes.c_double), ("stream_id", ctypes.c_uint32),
-                ("pad_", ctypes.c_uint32)]
+                ("noise_scale", ctypes.c_double), ("rest_length", ctypes.c_double),
+                ("lj_eps", ctypes.c_double), ("lj_rmin", ctypes.c_double),
+                ("stream_id", ctypes.c_uint32), ("pad_", ctypes.c_uint32)]
 
 
 _lib = None
@@ -60,6 +61,8 @@ def lib():
                                  ctypes.c_double, dp, dp, dp, dp]
         L.rao_spring.restype = ctypes.c_int
         L.rao_flow_velocity.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        L.rao_lj.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+        L.rao_lj.restype = ctypes.c_double
         L.ra_oracle_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(Group), ctypes.c_int32,
                                        ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_int32]
@@ -134,6 +137,14 @@ def spring(kind, H, b, kT, Q):
     return F, g.value, f.value, bool(clamped)
 
 
+def lj(u, rmin, d):
+    """(U, F) of one Lennard-Jones pair, d = r_i - r_j, F the force on i."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    F = np.zeros(3)
+    U = lib().rao_lj(u, rmin, _dp(d), _dp(F))
+    return U, F
+
+
 def flow_velocity(flow, rate, r):
     r = np.ascontiguousarray(r, dtype=np.float64)
     v = np.zeros(3)
@@ -161,6 +172,9 @@ def make_groups(descs):
         g.zeta = d.get("zeta", 1.0)
         g.dt = d["dt"]
         g.noise_scale = d.get("noise_scale", 1.0)
+        g.rest_length = d.get("rest_length", 0.0)
+        g.lj_eps = d.get("lj_eps", 0.0)
+        g.lj_rmin = d.get("lj_rmin", 0.0)
         g.stream_id = d.get("stream_id", i)
     return arr
 

@@ -86,11 +86,18 @@ static double dot3(const double a[3], const double b[3])
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-static int spring_factor(int spring, double H, double b, double kT, const double Q[3],
+static int spring_factor(int spring, double H, double p2, double kT, const double Q[3],
                          double* g, double* s_out)
 {
     if (spring == RAO_HOOKEAN) { *g = 1.0; *s_out = 0.0; return 0; }
-    double q0sq = b * kT / H;
+    if (spring == RAO_HARMONIC) {
+        /* rest length r0 = p2: F = H (|Q| - r0) Q/|Q| = H g Q, g = 1 - r0/|Q| */
+        double q = sqrt(dot3(Q, Q));
+        *g = q > 0.0 ? 1.0 - p2 / q : 0.0;
+        *s_out = 0.0;
+        return 0;
+    }
+    double q0sq = p2 * kT / H;
     double s = dot3(Q, Q) / q0sq;
     int clamped = 0;
     if (s > 1.0 - RAO_FENE_DELTA) { s = 1.0 - RAO_FENE_DELTA; clamped = 1; }
@@ -99,14 +106,31 @@ static int spring_factor(int spring, double H, double b, double kT, const double
     return clamped;
 }
 
-int rao_spring(int spring, double H, double b, double kT, const double Q[3],
+int rao_spring(int spring, double H, double p2, double kT, const double Q[3],
                double F[3], double* g, double* f)
 {
     double s;
-    int clamped = spring_factor(spring, H, b, kT, Q, g, &s);
+    int clamped = spring_factor(spring, H, p2, kT, Q, g, &s);
     for (int a = 0; a < 3; ++a) F[a] = H * (*g) * Q[a];
-    *f = H * (*g) * sqrt(dot3(Q, Q));
+    if (spring == RAO_HARMONIC) *f = H * (sqrt(dot3(Q, Q)) - p2);   /* signed, Eq. 4 */
+    else *f = H * (*g) * sqrt(dot3(Q, Q));
     return clamped;
+}
+
+/* Lennard-Jones pair (Sec. II collapsed-polymer model). */
+double rao_lj(double u, double rmin, const double d[3], double F[3])
+{
+    double r2 = dot3(d, d);
+    double x6 = pow(rmin * rmin / r2, 3.0);          /* (rmin/r)^6 */
+    double c = 12.0 * u / r2 * (x6 * x6 - x6);
+    for (int a = 0; a < 3; ++a) F[a] = c * d[a];
+    return u * (x6 * x6 - 2.0 * x6);
+}
+
+/* Second spring parameter: b (FENE) or the rest length (harmonic). */
+static double spring_p2(const rao_group* d)
+{
+    return d->spring == RAO_HARMONIC ? d->rest_length : d->b;
 }
 
 /* Homogeneous flow v = kappa . r. Shear follows the paper's convention
@@ -205,10 +229,14 @@ int ra_oracle_create(rao_ctx** out, const rao_group* groups, int32_t n_groups,
     for (int g = 0; g < n_groups; ++g) {
         const rao_group* d = &groups[g];
         if (d->n_beads < 2 || d->n_replicas < 1 || !(d->dt > 0) || !(d->kT > 0) ||
-            !(d->zeta > 0) || !(d->H > 0) || d->spring < 0 || d->spring > 1 ||
+            !(d->zeta > 0) || !(d->H > 0) || d->spring < 0 || d->spring > 2 ||
             d->flow < 0 || d->flow > 3 || d->stream_id > 0xFFFFFFu ||
-            (d->spring == RAO_FENE && !(d->b > 0)))
+            (d->spring == RAO_FENE && !(d->b > 0)) ||
+            (d->spring == RAO_HARMONIC && !(d->rest_length >= 0)) ||
+            !(d->lj_eps >= 0) || (d->lj_eps > 0 && !(d->lj_rmin > 0)))
             return RAO_EINVAL;
+        if (tangents && (d->spring == RAO_HARMONIC || d->lj_eps > 0))
+            return RAO_EINVAL;   /* gradients cover the Hookean and FENE laws only */
     }
     rao_ctx* c = calloc(1, sizeof *c);
     if (!c) return RAO_ENOMEM;
@@ -401,8 +429,8 @@ static void em_step_replica(rao_ctx* c, int g, int kk, uint32_t n,
     for (int j = 0; j + 1 < N; ++j) {
         double Q[3], F[3], gj, f, s;
         for (int a = 0; a < 3; ++a) Q[a] = r[3 * (j + 1) + a] - r[3 * j + a];
-        int clamped = rao_spring(d->spring, d->H, d->b, d->kT, Q, F, &gj, &f);
-        spring_factor(d->spring, d->H, d->b, d->kT, Q, &gj, &s);
+        int clamped = rao_spring(d->spring, d->H, spring_p2(d), d->kT, Q, F, &gj, &f);
+        spring_factor(d->spring, d->H, spring_p2(d), d->kT, Q, &gj, &s);
         c->clamps[g] += clamped;
         for (int a = 0; a < 3; ++a) Fbuf[3 * j + a] = F[a];
         if (c->tangents) {
@@ -430,6 +458,18 @@ static void em_step_replica(rao_ctx* c, int g, int kk, uint32_t n,
                     dFnet[(int64_t)p * 3 * N + 3 * i + a] = w;
                 }
         }
+    /* Lennard-Jones self-association between non-adjacent beads (|i - j| >= 2) */
+    if (d->lj_eps > 0)
+        for (int i = 0; i < N; ++i)
+            for (int j = i + 2; j < N; ++j) {
+                double dv[3], F[3];
+                for (int a = 0; a < 3; ++a) dv[a] = r[3 * i + a] - r[3 * j + a];
+                rao_lj(d->lj_eps, d->lj_rmin, dv, F);
+                for (int a = 0; a < 3; ++a) {
+                    Fnet[3 * i + a] += F[a];
+                    Fnet[3 * j + a] -= F[a];
+                }
+            }
     /* position update */
     for (int i = 0; i < N; ++i) {
         double xi[3], v[3];
@@ -466,8 +506,8 @@ static void sample_replica(rao_ctx* c, int g, int kk, int window_end, int64_t w)
     for (int j = 0; j + 1 < N; ++j) {
         double Q[3], F[3], gj, f, s;
         for (int a = 0; a < 3; ++a) Q[a] = r[3 * (j + 1) + a] - r[3 * j + a];
-        int clamped = rao_spring(d->spring, d->H, d->b, d->kT, Q, F, &gj, &f);
-        spring_factor(d->spring, d->H, d->b, d->kT, Q, &gj, &s);
+        int clamped = rao_spring(d->spring, d->H, spring_p2(d), d->kT, Q, F, &gj, &f);
+        spring_factor(d->spring, d->H, spring_p2(d), d->kT, Q, &gj, &s);
         int64_t idx = c->smp_off[g] + (int64_t)kk * (N - 1) + j;
         if (c->tsf) c->tsf_acc[idx] += f;
         if (!window_end) continue;

@@ -14,9 +14,12 @@
  *   - random displacement with zero mean and covariance 2*D*dt (Eq. 1 text),
  *     Gaussian, generated from a counter-based Philox4x32-10 stream;
  *   - homogeneous flow v = kappa . r (Sec. II; shear v = gdot * z * x-hat);
- *   - spring tension sampled per spring (Eq. 4, generalised to zero-rest-
- *     length Hookean and FENE springs), averaged over replicas (RSF, Sec. II)
- *     and over time within a window (TSF, Sec. II);
+ *   - spring tension sampled per spring (Eq. 4: signed kappa (r - r0) for
+ *     rest-length harmonic springs, H g |Q| for zero-rest-length Hookean and
+ *     FENE springs), averaged over replicas (RSF, Sec. II) and over time
+ *     within a window (TSF, Sec. II);
+ *   - optional Lennard-Jones self-association between non-adjacent beads
+ *     (Sec. II, collapsed-polymer model);
  *   - Bell-type rate k = k0 * exp(x_dagger * f / kT) (Sec. III, vWF rate law).
  *
  * All arithmetic is IEEE double; the only library calls are libm's
@@ -30,7 +33,7 @@
 extern "C" {
 #endif
 
-enum { RAO_HOOKEAN = 0, RAO_FENE = 1 };
+enum { RAO_HOOKEAN = 0, RAO_FENE = 1, RAO_HARMONIC = 2 };
 enum { RAO_QUIESCENT = 0, RAO_UNIAXIAL = 1, RAO_PLANAR = 2, RAO_SHEAR = 3 };
 enum { RAO_OK = 0, RAO_EINVAL = -1, RAO_ENOMEM = -2, RAO_ESTATE = -5 };
 
@@ -47,6 +50,9 @@ typedef struct {
     double   rate;         /* strain rate (elongation) or shear rate */
     double   kT, zeta, dt;
     double   noise_scale;  /* 1 = physical noise, 0 = deterministic */
+    double   rest_length;  /* RAO_HARMONIC: zero-force bond length (2a in Sec. II) */
+    double   lj_eps;       /* Lennard-Jones well depth u between non-adjacent beads (0 = off) */
+    double   lj_rmin;      /* position of the LJ minimum (2a in Sec. II) */
     uint32_t stream_id;    /* group id in the Philox counter, < 2^24 */
     uint32_t pad_;
 } rao_group;
@@ -60,9 +66,13 @@ double rao_uniform(uint32_t x);
 void   rao_normals(const uint32_t x[4], double xi[3]);
 void   rao_noise(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
                  uint32_t tag, uint32_t group, double xi[3]);
-/* spring force F (on bead j, toward bead j+1), factor g, tension f; returns 1 if clamped */
-int    rao_spring(int spring, double H, double b, double kT, const double Q[3],
+/* spring force F (on bead j, toward bead j+1), factor g (F = H g Q), tension f;
+ * p2 is b for FENE and the rest length for RAO_HARMONIC; returns 1 if clamped */
+int    rao_spring(int spring, double H, double p2, double kT, const double Q[3],
                   double F[3], double* g, double* f);
+/* Lennard-Jones force on bead i from bead j (Sec. II): U = u [(rmin/r)^12 - 2 (rmin/r)^6],
+ * d = r_i - r_j; F = (12 u / r^2) [(rmin/r)^12 - (rmin/r)^6] d; returns U */
+double rao_lj(double u, double rmin, const double d[3], double F[3]);
 void   rao_flow_velocity(int flow, double rate, const double r[3], double v[3]);
 
 /* ---- context API mirroring the library's calls ------------------------ */

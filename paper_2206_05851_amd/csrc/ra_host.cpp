@@ -84,6 +84,9 @@ ra_status fail(ra_ctx* c, ra_status code, const std::string& msg) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Groups of the collapsed-polymer force field run the pair-interaction kernel.
+bool is_pair_group(const ra_chain_desc& d) { return d.spring == RA_HARMONIC || d.lj_eps > 0.0; }
+
 ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std::string& why) {
     char buf[256];
     if (!g || n < 1 || !r) { why = "null descriptor or n_groups < 1"; return RA_EINVAL; }
@@ -101,13 +104,28 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
     if (r->reserved_ != 0) { why = "reserved_ must be 0"; return RA_EINVAL; }
     const int wpb = r->waves_per_block ? r->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4) { why = "waves_per_block must be 0, 1, 2 or 4"; return RA_EINVAL; }
+    int n_pair = 0;
+    for (int i = 0; i < n; ++i) n_pair += is_pair_group(g[i]) ? 1 : 0;
+    if (n_pair > 0 && n_pair < n) {
+        why = "a context holds either only pair-interaction groups (HARMONIC spring or LJ) or none";
+        return RA_EINVAL;
+    }
+    if (n_pair > 0 && r->checkpoint_every > 0) {
+        why = "the adjoint covers the Hookean and FENE chain model only";
+        return RA_EINVAL;
+    }
+    if (n_pair > 0 && r->plain) { why = "the pair-interaction model has no plain path"; return RA_EINVAL; }
     for (int i = 0; i < n; ++i) {
         const ra_chain_desc& d = g[i];
-        const int nmax = r->precision == 64 ? 256 : 1024;
+        const int nmax = n_pair ? WAVE : r->precision == 64 ? 256 : 1024;
         const char* bad = nullptr;
         if (d.n_beads < 2 || d.n_beads > nmax) bad = "n_beads out of range";
         else if (d.n_replicas < 1) bad = "n_replicas < 1";
-        else if (d.spring != RA_HOOKEAN && d.spring != RA_FENE) bad = "unknown spring";
+        else if (d.spring != RA_HOOKEAN && d.spring != RA_FENE && d.spring != RA_HARMONIC) bad = "unknown spring";
+        else if (d.spring == RA_HARMONIC && !(std::isfinite(d.rest_length) && d.rest_length >= 0))
+            bad = "HARMONIC needs a finite rest_length >= 0";
+        else if (!(std::isfinite(d.lj_eps) && d.lj_eps >= 0)) bad = "lj_eps must be finite and >= 0";
+        else if (d.lj_eps > 0 && !finite_pos(d.lj_rmin)) bad = "LJ needs finite lj_rmin > 0";
         else if (d.flow < RA_QUIESCENT || d.flow > RA_SHEAR) bad = "unknown flow";
         else if (!finite_pos(d.H) || !finite_pos(d.kT) || !finite_pos(d.zeta) || !finite_pos(d.dt))
             bad = "H, kT, zeta and dt must be finite and > 0";
@@ -149,6 +167,11 @@ GroupDev make_group(const ra_chain_desc& d, int M, int tag) {
     G.kx = (float)G.kx_d; G.ky = (float)G.ky_d; G.kz = (float)G.kz_d; G.kxz = (float)G.kxz_d;
     G.cF = (float)G.cF_d; G.sigma = (float)G.sigma_d; G.H = (float)G.H_d; G.inv_q0sq = (float)G.inv_q0sq_d;
     G.kT = d.kT; G.zeta = d.zeta; G.dt = d.dt; G.b = d.b; G.rate = d.rate;
+    G.dtz_d = d.dt / d.zeta;
+    G.r0_d = d.spring == RA_HARMONIC ? d.rest_length : 0.0;
+    G.lj12u_d = 12.0 * d.lj_eps;
+    G.ljr2_d = d.lj_eps > 0.0 ? d.lj_rmin * d.lj_rmin : 0.0;
+    G.dtz = (float)G.dtz_d; G.r0 = (float)G.r0_d; G.lj12u = (float)G.lj12u_d; G.ljr2 = (float)G.ljr2_d;
     return G;
 }
 
@@ -211,11 +234,13 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     for (int i = 0; i < n_groups; ++i)
         if (groups[i].n_beads > 4 * WAVE) family = 16;
     if (run->precision == 64) family = 4;
+    const bool pair = is_pair_group(groups[0]);   // validated: all groups or none
+    if (pair) family = 2;
     for (int i = 0; i < n_groups; ++i) {
         int forced = run->tile_policy > 1000 ? run->tile_policy - 1000 : 0;
-        Ms[i] = choose_beads_per_lane(groups[i].n_beads, groups[i].n_replicas, family, forced);
+        Ms[i] = pair ? 1 : choose_beads_per_lane(groups[i].n_beads, groups[i].n_replicas, family, forced);
     }
-    if (run->tile_policy == 1 && !run->plain) {
+    if (run->tile_policy == 1 && !run->plain && !pair) {
         ra_status st = autotune_tiles(c->descs, *run, family, c->wpb, c->stream, Ms, why);
         if (st != RA_OK) {
             ra_destroy(c);
@@ -401,7 +426,8 @@ static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps) {
     for (int64_t done = 0; done < n_steps; done += chunk) {
         a.n_steps = std::min(chunk, n_steps - done);
         if (c->family == 1) HIPCHK(c, launch_forward_split(a, c->stream));
-    else HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->stream));
+        else if (c->family == 2) HIPCHK(c, launch_forward_pair(a, c->run.precision, c->wpb, c->stream));
+        else HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->stream));
         HIPCHK(c, launch_advance(c->dstep, a.n_steps, c->stream));
     }
     return RA_OK;

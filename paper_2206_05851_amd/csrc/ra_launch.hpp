@@ -75,6 +75,9 @@ hipError_t launch_lam_mu(const GroupDev* groups, int n_groups, int64_t n_windows
 hipError_t launch_grad_reduce(const int32_t* item_begin, int n_groups, const double* partial,
                               double* grad_params, hipStream_t st);
 
+// pair-interaction (collapsed-polymer) forward kernel (ra_pair.hip)
+hipError_t launch_forward_pair(const FwdArgs& a, int precision, int waves_per_block, hipStream_t st);
+
 // RSF cycle and estimators (ra_rsf.hip)
 hipError_t launch_reclone(const GroupDev* groups, const GroupDev* pgroups, int n_groups, int64_t max_elems,
                           const void* pstate, void* state, double* tsf_acc, int32_t* status, int precision,

@@ -1,0 +1,238 @@
+// ra_pair.hip — forward kernel of the collapsed-polymer force field (Sec. II):
+// backbone springs (rest-length harmonic kappa/2 (r - r0)^2, or the Hookean
+// and FENE laws) plus Lennard-Jones self-association between non-adjacent
+// beads, free-draining (Eq. 1 with the self term Eq. 2 only).
+//
+// One bead per lane, P = floor(64/N) replicas per wavefront (N <= 64). The
+// state stays the bond vectors Q_j (as in the chain kernels, so FP32 keeps
+// bond-scale precision however far the chain drifts in the flow); the bead
+// positions relative to bead 0 are rebuilt every step by a segmented wave
+// scan of the bonds and shared through LDS for the O(N^2) pair forces. The
+// bond update is the difference of the bead updates of beads j+1 and j:
+//   Q_j' = Q_j + dt kappa Q_j + (dt/zeta) (F_{j+1} - F_j) + sigma (xi_{j+1} - xi_j)
+// with F_i the total force on bead i (springs + LJ).
+#include "ra_chain.hpp"
+#include "ra_launch.hpp"
+
+namespace ra {
+
+template <typename T> struct PairCo;
+template <> struct PairCo<float> {
+    const GroupDev& G;
+    __device__ float dtz() const { return G.dtz; }
+    __device__ float r0() const { return G.r0; }
+    __device__ float lj12u() const { return G.lj12u; }
+    __device__ float ljr2() const { return G.ljr2; }
+};
+template <> struct PairCo<double> {
+    const GroupDev& G;
+    __device__ double dtz() const { return G.dtz_d; }
+    __device__ double r0() const { return G.r0_d; }
+    __device__ double lj12u() const { return G.lj12u_d; }
+    __device__ double ljr2() const { return G.ljr2_d; }
+};
+
+// Force of the spring on bond Q acting on its first bead (toward the second).
+template <typename T, int SPRING>
+__device__ __forceinline__ void pair_spring_force(T qx, T qy, T qz, const GroupDev& G, T& fx, T& fy, T& fz,
+                                                  int& clamps) {
+    const T H = Co<T>{G}.H();
+    const T q2 = fmadd(qx, qx, fmadd(qy, qy, qz * qz));
+    T g;
+    if constexpr (SPRING == 0) {
+        g = (T)1;
+    } else if constexpr (SPRING == 1) {
+        g = fene_g(qx, qy, qz, q2, (T)G.inv_q0sq, G.inv_q0sq_d, clamps);
+    } else {
+        const T q = fast_sqrt(q2);
+        g = q > (T)0 ? (T)1 - PairCo<T>{G}.r0() * fast_rcp(q) : (T)0;
+    }
+    const T Hg = H * g;
+    fx = Hg * qx;
+    fy = Hg * qy;
+    fz = Hg * qz;
+}
+
+// Spring tension of Eq. 4: signed H (|Q| - r0) for the rest-length spring,
+// H g |Q| for the zero-rest-length laws.
+template <typename T, int SPRING>
+__device__ __forceinline__ T pair_tension(T qx, T qy, T qz, const GroupDev& G) {
+    const T H = Co<T>{G}.H();
+    const T q2 = fmadd(qx, qx, fmadd(qy, qy, qz * qz));
+    const T q = fast_sqrt(q2);
+    if constexpr (SPRING == 2) {
+        return H * (q - PairCo<T>{G}.r0());
+    } else if constexpr (SPRING == 1) {
+        int dummy = 0;
+        return H * fene_g(qx, qy, qz, q2, (T)G.inv_q0sq, G.inv_q0sq_d, dummy) * q;
+    } else {
+        return H * q;
+    }
+}
+
+// Inclusive scan of v over the lanes of each replica segment (bead index i
+// within the segment): after it, lane i holds the sum over beads 0..i.
+template <typename T>
+__device__ __forceinline__ T segment_scan(T v, int i) {
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const T u = __shfl_up(v, (unsigned)off, WAVE);
+        if (i >= off) v += u;
+    }
+    return v;
+}
+
+template <typename T, int SPRING, bool LJ>
+__device__ void run_pair(const FwdArgs& a, const GroupDev& G, int k_first, T (*xs)[4]) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int N = G.N, nm1 = N - 1;
+    const int seg = lane / N;
+    const int i = lane - seg * N;
+    const int k = k_first + seg;
+    const bool rep_ok = seg < G.P && k < G.R;
+    const bool bond_ok = rep_ok && i < nm1;
+    T* const state = (T*)a.state;
+    const int64_t sidx = ((int64_t)k * nm1 + i);
+    T qx = (T)0, qy = (T)0, qz = (T)0;
+    if (bond_ok) {
+        const int64_t o = G.state_off + sidx * 3;
+        qx = state[o];
+        qy = state[o + 1];
+        qz = state[o + 2];
+    }
+    const Co<T> c{G};
+    const PairCo<T> pc{G};
+    // coefficients are zero on lanes without a bond
+    const T kx = bond_ok ? c.kx() : (T)0, ky = bond_ok ? c.ky() : (T)0, kz = bond_ok ? c.kz() : (T)0;
+    const T kxz = bond_ok ? c.kxz() : (T)0;
+    const T dtz = bond_ok ? pc.dtz() : (T)0, sg = bond_ok ? c.sigma() : (T)0;
+    const T lj12u = pc.lj12u(), ljr2 = pc.ljr2();
+    const int base = rep_ok ? seg * N : 0;   // LDS rows of this lane's replica
+    const RoundKeys keys = round_keys(a.key0, a.key1);
+    const uint32_t n0 = (uint32_t)*a.step0;
+    const int S = a.S;
+    const int64_t smp_total = a.smp_total;
+    const bool tsf = a.tsf != nullptr;
+    double acc = 0.0;
+    if (tsf && bond_ok) acc = a.tsf_acc[G.smp_off + sidx];
+    int to_smp = S - (int)(n0 % (uint32_t)S);
+    int64_t w = (int64_t)(n0 / (uint32_t)S);
+    int clamps = 0;
+    const int n_steps = (int)a.n_steps;
+    for (int st = 0; st < n_steps; ++st) {
+        const uint32_t n = n0 + (uint32_t)st;
+        T gx, gy, gz;
+        pair_spring_force<T, SPRING>(qx, qy, qz, G, gx, gy, gz, clamps);
+        // net force on bead i: spring i pulls toward i+1, spring i-1 pulls back
+        // (the previous lane of bead 0 is the bondless last bead of the
+        // previous replica, or lane -1, and contributes 0)
+        T Fx = gx - from_prev_lane(gx), Fy = gy - from_prev_lane(gy), Fz = gz - from_prev_lane(gz);
+        if constexpr (LJ) {
+            const T px = segment_scan(qx, i) - qx, py = segment_scan(qy, i) - qy, pz = segment_scan(qz, i) - qz;
+            xs[lane][0] = px;
+            xs[lane][1] = py;
+            xs[lane][2] = pz;
+            // this wave alone uses its LDS rows: make the writes visible to
+            // its own reads (and keep the next step's writes after them)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            T lx = (T)0, ly = (T)0, lz = (T)0;
+            for (int j = 0; j < N; ++j) {
+                const T dx = px - xs[base + j][0];
+                const T dy = py - xs[base + j][1];
+                const T dz = pz - xs[base + j][2];
+                // pairs |i - j| >= 2 of an existing replica only; the others
+                // (the bead itself, bonded neighbours, lanes past the last
+                // replica, which all sit at the origin) never form 1/r^2
+                const int dj = j - i;
+                const bool use = rep_ok && (dj >= 2 || dj <= -2);
+                const T r2 = use ? fmadd(dx, dx, fmadd(dy, dy, dz * dz)) : (T)1;
+                const T inv = fast_rcp(r2);
+                const T s1 = ljr2 * inv;
+                const T s3 = s1 * s1 * s1;
+                const T cc = use ? lj12u * inv * fmadd(s3, s3, -s3) : (T)0;
+                lx = fmadd(cc, dx, lx);
+                ly = fmadd(cc, dy, ly);
+                lz = fmadd(cc, dz, lz);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            Fx += lx;
+            Fy += ly;
+            Fz += lz;
+        }
+        T ex, ey, ez;
+        normals3(philox10(n, (uint32_t)i, (uint32_t)k, G.stream, keys), ex, ey, ez);
+        const T Fnx = from_next_lane(Fx), Fny = from_next_lane(Fy), Fnz = from_next_lane(Fz);
+        const T enx = from_next_lane(ex), eny = from_next_lane(ey), enz = from_next_lane(ez);
+        const T ix = fmadd(kx, qx, fmadd(kxz, qz, fmadd(dtz, Fnx - Fx, sg * (enx - ex))));
+        const T iy = fmadd(ky, qy, fmadd(dtz, Fny - Fy, sg * (eny - ey)));
+        const T iz = fmadd(kz, qz, fmadd(dtz, Fnz - Fz, sg * (enz - ez)));
+        // lanes without a bond keep Q = 0 whatever their neighbours hold
+        qx = bond_ok ? qx + ix : (T)0;
+        qy = bond_ok ? qy + iy : (T)0;
+        qz = bond_ok ? qz + iz : (T)0;
+        const bool window_end = --to_smp == 0;
+        if (tsf || window_end) {
+            const T f = pair_tension<T, SPRING>(qx, qy, qz, G);
+            if (tsf) acc += (double)f;
+            if (window_end) {
+                bool bad = false;
+                if (bond_ok) {
+                    const int64_t o = w * smp_total + G.smp_off + sidx;
+                    ((T*)a.samples)[o] = f;
+                    bad = !__builtin_isfinite((double)f);
+                    if (tsf) {
+                        ((T*)a.tsf)[o] = (T)(acc / (double)S);
+                        acc = 0.0;
+                    }
+                }
+                if (bad) atomicOr(a.status, 2);
+                to_smp = S;
+                ++w;
+            }
+        }
+    }
+    if (bond_ok) {
+        const int64_t o = G.state_off + sidx * 3;
+        state[o] = qx;
+        state[o + 1] = qy;
+        state[o + 2] = qz;
+        if (tsf) a.tsf_acc[G.smp_off + sidx] = acc;
+    }
+    flush_clamps(clamps, a.clamps + (&G - a.groups));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fwd_pair_kernel(FwdArgs a) {
+    __shared__ T xs[4][WAVE][4];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int item = (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
+    if (item >= a.n_items) return;
+    if (*(const volatile int*)a.status & 1) return;   // invalid parent: no work
+    const Item it = a.items[item];
+    const GroupDev& G = a.groups[it.g];
+    const bool lj = G.lj12u_d > 0.0;
+    switch (G.spring * 2 + (lj ? 1 : 0)) {
+    case 0: run_pair<T, 0, false>(a, G, it.k0, xs[wave]); break;
+    case 1: run_pair<T, 0, true>(a, G, it.k0, xs[wave]); break;
+    case 2: run_pair<T, 1, false>(a, G, it.k0, xs[wave]); break;
+    case 3: run_pair<T, 1, true>(a, G, it.k0, xs[wave]); break;
+    case 4: run_pair<T, 2, false>(a, G, it.k0, xs[wave]); break;
+    default: run_pair<T, 2, true>(a, G, it.k0, xs[wave]); break;
+    }
+}
+
+hipError_t launch_forward_pair(const FwdArgs& a, int precision, int waves_per_block, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    if (a.n_items <= 0 || a.n_steps <= 0) return hipSuccess;
+    const int wpb = waves_per_block;
+    dim3 grid((a.n_items + wpb - 1) / wpb), block(WAVE * wpb);
+    if (precision == 64) hipLaunchKernelGGL(fwd_pair_kernel<double>, grid, block, 0, st, a);
+    else hipLaunchKernelGGL(fwd_pair_kernel<float>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace ra

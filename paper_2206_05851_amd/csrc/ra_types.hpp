@@ -11,7 +11,7 @@ constexpr int WAVE = 64;
 struct GroupDev {
     int32_t N, R;            // beads, replicas
     int32_t M, L, P;         // beads per lane, lanes per replica, replicas per wave
-    int32_t spring;          // 0 Hookean, 1 FENE
+    int32_t spring;          // 0 Hookean, 1 FENE, 2 rest-length harmonic
     uint32_t stream;         // counter word: tag<<24 | stream_id (tag 0)
     int32_t flow;            // 0..3 (shear adds the x <- z coupling)
     // bond-form EM increment: dQ = kdiag.*Q + kxz*Qz e_x + cF*lap(gQ) + sigma*(xi_{j+1}-xi_j)
@@ -26,6 +26,11 @@ struct GroupDev {
     int64_t smp_off;         // first element of this group's [R][N-1] block in a window
     int64_t spr_off;         // first spring of this group in a profile row
     int64_t pos_off;         // first element of this group's [R][N][3] positions (plain path)
+    // pair-interaction model (Sec. II collapsed polymer): spring 2 = rest-length
+    // harmonic, F = H (|Q| - r0) Q/|Q|; LJ u [(rmin/r)^12 - 2 (rmin/r)^6] between
+    // beads |i - j| >= 2, force (12u/r^2) [(rmin/r)^12 - (rmin/r)^6] (r_i - r_j)
+    float dtz, r0, lj12u, ljr2;          // dt/zeta, rest length, 12 u, rmin^2
+    double dtz_d, r0_d, lj12u_d, ljr2_d;
 };
 
 // One wavefront of work: replicas [k0, k0 + P) of group g.

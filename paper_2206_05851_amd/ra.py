@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libra.so")
 
 RA_OK, RA_EINVAL, RA_ENOMEM, RA_EDEVICE, RA_EUNSTABLE, RA_ESTATE = 0, -1, -2, -3, -4, -5
-HOOKEAN, FENE = 0, 1
+HOOKEAN, FENE, HARMONIC = 0, 1, 2
 QUIESCENT, UNIAXIAL, PLANAR, SHEAR = 0, 1, 2, 3
 _NAMES = {RA_EINVAL: "RA_EINVAL", RA_ENOMEM: "RA_ENOMEM", RA_EDEVICE: "RA_EDEVICE",
           RA_EUNSTABLE: "RA_EUNSTABLE", RA_ESTATE: "RA_ESTATE"}
@@ -36,8 +36,9 @@ class ChainDesc(ctypes.Structure):
                 ("spring", ctypes.c_int32), ("flow", ctypes.c_int32),
                 ("H", ctypes.c_double), ("b", ctypes.c_double), ("rate", ctypes.c_double),
                 ("kT", ctypes.c_double), ("zeta", ctypes.c_double), ("dt", ctypes.c_double),
-                ("noise_scale", ctypes.c_double), ("stream_id", ctypes.c_uint32),
-                ("pad_", ctypes.c_uint32)]
+                ("noise_scale", ctypes.c_double), ("rest_length", ctypes.c_double),
+                ("lj_eps", ctypes.c_double), ("lj_rmin", ctypes.c_double),
+                ("stream_id", ctypes.c_uint32), ("pad_", ctypes.c_uint32)]
 
 
 class RunDesc(ctypes.Structure):
@@ -50,7 +51,7 @@ class RunDesc(ctypes.Structure):
                 ("reserved_", ctypes.c_int32)]
 
 
-assert ctypes.sizeof(ChainDesc) == 80 and ctypes.sizeof(RunDesc) == 56
+assert ctypes.sizeof(ChainDesc) == 104 and ctypes.sizeof(RunDesc) == 56
 
 _lib = None
 
@@ -123,6 +124,9 @@ def make_desc(d, index):
     c.zeta = float(d.get("zeta", 1.0))
     c.dt = float(d["dt"])
     c.noise_scale = float(d.get("noise_scale", 1.0))
+    c.rest_length = float(d.get("rest_length", 0.0))
+    c.lj_eps = float(d.get("lj_eps", 0.0))
+    c.lj_rmin = float(d.get("lj_rmin", 0.0))
     c.stream_id = int(d.get("stream_id", index))
     return c
 

@@ -11,7 +11,7 @@ import math
 
 import numpy as np
 
-HOOKEAN, FENE = 0, 1
+HOOKEAN, FENE, HARMONIC = 0, 1, 2
 QUIESCENT, UNIAXIAL, PLANAR, SHEAR = 0, 1, 2, 3
 
 
@@ -65,11 +65,12 @@ def equilibrium_parent(n_beads, spring=HOOKEAN, H=1.0, b=0.0, kT=1.0, seed=0):
 
 
 def group(n_beads, n_replicas, dt, spring=HOOKEAN, H=1.0, b=0.0, flow=QUIESCENT, rate=0.0,
-          kT=1.0, zeta=1.0, noise_scale=1.0, stream_id=0):
+          kT=1.0, zeta=1.0, noise_scale=1.0, stream_id=0, rest_length=0.0, lj_eps=0.0, lj_rmin=0.0):
     return dict(n_beads=int(n_beads), n_replicas=int(n_replicas), spring=int(spring),
                 H=float(H), b=float(b), flow=int(flow), rate=float(rate), kT=float(kT),
                 zeta=float(zeta), dt=float(dt), noise_scale=float(noise_scale),
-                stream_id=int(stream_id))
+                stream_id=int(stream_id), rest_length=float(rest_length), lj_eps=float(lj_eps),
+                lj_rmin=float(lj_rmin))
 
 
 # ---------------------------------------------------------------------------
@@ -150,4 +151,40 @@ def rsf50(n_replicas=1000, n_windows=20):
     g = group(N, n_replicas, 1e-4, FENE, 1.0, 100.0, SHEAR, wi_to_rate(50.0, N))
     parent = equilibrium_parent(N, FENE, 1.0, 100.0, seed=104)
     return [g], [parent], dict(seed=5, sample_every=750, parent_steps=750, n_windows=n_windows,
+                               precision=32, k0=1e-6, x_dagger=0.1, blocks=(10, 20, 40, 50))
+
+
+def collapsed_parent(n_beads, seed=0, spacing=2.0, jitter=0.05):
+    """Compact self-avoiding conformation [N][3] for the collapsed-polymer
+    model: a serpentine path through a cubic lattice of the given spacing (the
+    bond rest length and the LJ minimum, 2a), so bonded and nearest
+    non-bonded beads sit at 2a; plus seeded Gaussian jitter; centre of mass
+    at the origin."""
+    side = 1
+    while side ** 3 < n_beads:
+        side += 1
+    sites = []
+    for z in range(side):
+        ys = range(side) if z % 2 == 0 else range(side - 1, -1, -1)
+        for yi, y in enumerate(ys):
+            xs = range(side) if (z * side + yi) % 2 == 0 else range(side - 1, -1, -1)
+            for x in xs:
+                sites.append((x, y, z))
+    r = spacing * np.array(sites[:n_beads], dtype=np.float64)
+    r += np.random.default_rng(seed).normal(0.0, jitter, size=r.shape)
+    return r - r.mean(axis=0)
+
+
+def collapsed50(n_replicas=1000, n_windows=20):
+    """The paper's collapsed polymer (Sec. II) without hydrodynamic
+    interaction: N=50 beads, harmonic backbone springs kappa=400 kT/a^2 with
+    rest length 2a, LJ self-association u=1 kT between non-adjacent beads,
+    zeta=1 (time in units of the single-bead diffusion time), dt=1e-5, simple
+    shear at gamma-dot=30; RSF cycle with a parent re-cloned into 1000
+    replicas every 750 steps (S = 0.0075), 20 windows."""
+    N = 50
+    g = group(N, n_replicas, 1e-5, HARMONIC, 400.0, 0.0, SHEAR, 30.0, rest_length=2.0, lj_eps=1.0,
+              lj_rmin=2.0)
+    parent = collapsed_parent(N, seed=105)
+    return [g], [parent], dict(seed=6, sample_every=750, parent_steps=750, n_windows=n_windows,
                                precision=32, k0=1e-6, x_dagger=0.1, blocks=(10, 20, 40, 50))
