@@ -37,6 +37,7 @@ class Group(ctypes.Structure):
                 ("kT", ctypes.c_double), ("zeta", ctypes.c_double), ("dt", ctypes.c_double),
                 ("noise_scale", ctypes.c_double), ("rest_length", ctypes.c_double),
                 ("lj_eps", ctypes.c_double), ("lj_rmin", ctypes.c_double),
+                ("hi_radius", ctypes.c_double),
                 ("stream_id", ctypes.c_uint32), ("pad_", ctypes.c_uint32)]
 
 
@@ -62,6 +63,9 @@ def lib():
         L.rao_spring.restype = ctypes.c_int
         L.rao_flow_velocity.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
         L.rao_lj.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+        L.rao_rpy_block.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.rao_cholesky.argtypes = [ctypes.c_int, dp]
+        L.rao_cholesky.restype = ctypes.c_int
         L.rao_lj.restype = ctypes.c_double
         L.ra_oracle_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(Group), ctypes.c_int32,
                                        ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
@@ -145,6 +149,21 @@ def lj(u, rmin, d):
     return U, F
 
 
+def rpy_block(kT, zeta, a, r):
+    """RPY block D_ij (3x3) for r = r_j - r_i (Eq. 3)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    D = np.zeros(9)
+    lib().rao_rpy_block(kT, zeta, a, _dp(r), _dp(D))
+    return D.reshape(3, 3)
+
+
+def cholesky(A):
+    """Lower Cholesky factor by the oracle's routine (None if not positive definite)."""
+    L = np.ascontiguousarray(A, dtype=np.float64).copy()
+    rc = lib().rao_cholesky(L.shape[0], _dp(L))
+    return None if rc != 0 else L
+
+
 def flow_velocity(flow, rate, r):
     r = np.ascontiguousarray(r, dtype=np.float64)
     v = np.zeros(3)
@@ -175,6 +194,7 @@ def make_groups(descs):
         g.rest_length = d.get("rest_length", 0.0)
         g.lj_eps = d.get("lj_eps", 0.0)
         g.lj_rmin = d.get("lj_rmin", 0.0)
+        g.hi_radius = d.get("hi_radius", 0.0)
         g.stream_id = d.get("stream_id", i)
     return arr
 

@@ -127,6 +127,51 @@ double rao_lj(double u, double rmin, const double d[3], double F[3])
     return u * (x6 * x6 - 2.0 * x6);
 }
 
+/* Rotne-Prager-Yamakawa block (Eq. 3) for two beads of radius a at
+ * separation r, in units of D0 = kT/zeta (zeta = 6 pi eta a, Eq. 2):
+ *   r >= 2a: (3a/4r) [(1 + 2a^2/(3r^2)) I + (1 - 2a^2/r^2) rhat rhat]
+ *   r <  2a: (1 - 9r/(32a)) I + (3r/(32a)) rhat rhat
+ * (the second line is the paper's overlap form with kT/(8 pi eta r) (r/2a)
+ * rewritten over D0). */
+void rao_rpy_block(double kT, double zeta, double a, const double r[3], double D[9])
+{
+    const double D0 = kT / zeta;
+    const double q = sqrt(dot3(r, r));
+    double ci, cr;
+    if (q >= 2.0 * a) {
+        ci = 0.75 * a / q * (1.0 + 2.0 * a * a / (3.0 * q * q));
+        cr = 0.75 * a / q * (1.0 - 2.0 * a * a / (q * q));
+    } else {
+        ci = 1.0 - 9.0 * q / (32.0 * a);
+        cr = 3.0 * q / (32.0 * a);
+    }
+    for (int x = 0; x < 3; ++x)
+        for (int y = 0; y < 3; ++y) {
+            double rr = q > 0.0 ? r[x] * r[y] / (q * q) : 0.0;
+            D[3 * x + y] = D0 * ((x == y ? ci : 0.0) + cr * rr);
+        }
+}
+
+/* Cholesky-Banachiewicz: row by row, L_ij = (A_ij - sum_{m<j} L_im L_jm) / L_jj,
+ * L_ii = sqrt(A_ii - sum_{m<i} L_im^2). */
+int rao_cholesky(int n, double* A)
+{
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double sum = A[i * n + j];
+            for (int m = 0; m < j; ++m) sum -= A[i * n + m] * A[j * n + m];
+            if (i == j) {
+                if (!(sum > 0.0)) return -1;
+                A[i * n + i] = sqrt(sum);
+            } else {
+                A[i * n + j] = sum / A[j * n + j];
+            }
+        }
+        for (int j = i + 1; j < n; ++j) A[i * n + j] = 0.0;
+    }
+    return 0;
+}
+
 /* Second spring parameter: b (FENE) or the rest length (harmonic). */
 static double spring_p2(const rao_group* d)
 {
@@ -233,10 +278,11 @@ int ra_oracle_create(rao_ctx** out, const rao_group* groups, int32_t n_groups,
             d->flow < 0 || d->flow > 3 || d->stream_id > 0xFFFFFFu ||
             (d->spring == RAO_FENE && !(d->b > 0)) ||
             (d->spring == RAO_HARMONIC && !(d->rest_length >= 0)) ||
-            !(d->lj_eps >= 0) || (d->lj_eps > 0 && !(d->lj_rmin > 0)))
+            !(d->lj_eps >= 0) || (d->lj_eps > 0 && !(d->lj_rmin > 0)) ||
+            !(d->hi_radius >= 0) || !isfinite(d->hi_radius))
             return RAO_EINVAL;
-        if (tangents && (d->spring == RAO_HARMONIC || d->lj_eps > 0))
-            return RAO_EINVAL;   /* gradients cover the Hookean and FENE laws only */
+        if (tangents && (d->spring == RAO_HARMONIC || d->lj_eps > 0 || d->hi_radius > 0))
+            return RAO_EINVAL;   /* gradients cover the free-draining Hookean and FENE chain only */
     }
     rao_ctx* c = calloc(1, sizeof *c);
     if (!c) return RAO_ENOMEM;
@@ -412,11 +458,61 @@ static double tension_tangent(int spring, double H, double b, double g, double s
     return df;
 }
 
+/* Eq. (1) with hydrodynamic interaction: the 3N x 3N tensor D of Eqs. (2)-(3)
+ * from the step-n positions, drift dt (v + D F / kT), random displacement
+ * sqrt(2 dt) L xi with D = L L^T (Cholesky) and xi the per-bead normals of the
+ * replica counter. hi holds (3N)^2 + 3N doubles. */
+static int hi_update(rao_ctx* c, const rao_group* d, int k, uint32_t n, double* r, const double* F,
+                     double* hi)
+{
+    const int N = d->n_beads, n3 = 3 * N;
+    double* D = hi;
+    double* xi = hi + (size_t)n3 * n3;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double B[9];
+            if (i == j) {
+                for (int e = 0; e < 9; ++e) B[e] = (e % 4 == 0) ? d->kT / d->zeta : 0.0;
+            } else {
+                double rij[3] = { r[3 * j] - r[3 * i], r[3 * j + 1] - r[3 * i + 1], r[3 * j + 2] - r[3 * i + 2] };
+                rao_rpy_block(d->kT, d->zeta, d->hi_radius, rij, B);
+            }
+            for (int x = 0; x < 3; ++x)
+                for (int y = 0; y < 3; ++y) D[(3 * i + x) * n3 + 3 * j + y] = B[3 * x + y];
+        }
+    double* step = malloc(sizeof(double) * (size_t)n3);
+    if (!step) return fail(c, RAO_ENOMEM, "out of host memory");
+    for (int a = 0; a < n3; ++a) {          /* drift: dt (v + D F / kT) */
+        double df = 0.0;
+        for (int b = 0; b < n3; ++b) df += D[a * n3 + b] * F[b];
+        step[a] = d->dt * df / d->kT;
+    }
+    for (int i = 0; i < N; ++i) {
+        double v[3];
+        rao_flow_velocity(d->flow, d->rate, r + 3 * i, v);
+        for (int x = 0; x < 3; ++x) step[3 * i + x] += d->dt * v[x];
+        rao_noise(c->seed, n, (uint32_t)i, (uint32_t)k, c->tag, d->stream_id, xi + 3 * i);
+    }
+    if (rao_cholesky(n3, D) != 0) {
+        free(step);
+        return fail(c, RAO_EINVAL, "diffusion tensor is not positive definite");
+    }
+    const double sc = d->noise_scale * sqrt(2.0 * d->dt);
+    for (int a = 0; a < n3; ++a) {          /* random displacement sqrt(2 dt) L xi */
+        double y = 0.0;
+        for (int b = 0; b <= a; ++b) y += D[a * n3 + b] * xi[b];
+        step[a] += sc * y;
+    }
+    for (int a = 0; a < n3; ++a) r[a] += step[a];
+    free(step);
+    return RAO_OK;
+}
+
 /* One Euler-Maruyama step of Eq. (1) with the free-draining tensor Eq. (2)
  * for replica k of group g: all beads advance together from the step-n
  * state; the random displacement has covariance 2 (kT/zeta) dt I. */
-static void em_step_replica(rao_ctx* c, int g, int kk, uint32_t n,
-                            double* Fbuf, double* Fnet, double* dF, double* dFnet)
+static int em_step_replica(rao_ctx* c, int g, int kk, uint32_t n,
+                           double* Fbuf, double* Fnet, double* dF, double* dFnet, double* hi)
 {
     const rao_group* d = &c->groups[g];
     const int N = d->n_beads;
@@ -470,6 +566,7 @@ static void em_step_replica(rao_ctx* c, int g, int kk, uint32_t n,
                     Fnet[3 * j + a] -= F[a];
                 }
             }
+    if (d->hi_radius > 0) return hi_update(c, d, k, n, r, Fnet, hi);
     /* position update */
     for (int i = 0; i < N; ++i) {
         double xi[3], v[3];
@@ -494,6 +591,7 @@ static void em_step_replica(rao_ctx* c, int g, int kk, uint32_t n,
     }
     for (int i = 0; i < 3 * N; ++i) r[i] += Fnet[i];
     (void)rs;
+    return RAO_OK;
 }
 
 /* Tension of every spring of replica kk (after the step), for RSF/TSF. */
@@ -542,25 +640,27 @@ int ra_oracle_step(rao_ctx* c, int64_t n_steps)
     double* Fnet = malloc(sizeof(double) * 3 * (size_t)nmax);
     double* dF = malloc(sizeof(double) * 9 * (size_t)nmax);
     double* dFnet = malloc(sizeof(double) * 9 * (size_t)nmax);
-    if (!Fbuf || !Fnet || !dF || !dFnet) {
-        free(Fbuf); free(Fnet); free(dF); free(dFnet);
+    double* hi = malloc(sizeof(double) * ((size_t)9 * nmax * nmax + 3 * (size_t)nmax));
+    if (!Fbuf || !Fnet || !dF || !dFnet || !hi) {
+        free(Fbuf); free(Fnet); free(dF); free(dFnet); free(hi);
         return fail(c, RAO_ENOMEM, "out of host memory");
     }
-    for (; c->step < end; ++c->step) {
+    int rc = RAO_OK;
+    for (; c->step < end && rc == RAO_OK; ++c->step) {
         uint32_t n = (uint32_t)c->step;
         int window_end = ((c->step + 1) % c->sample_every) == 0;
         int64_t w = (c->step + 1) / c->sample_every - 1;
-        for (int g = 0; g < c->n_groups; ++g) {
+        for (int g = 0; g < c->n_groups && rc == RAO_OK; ++g) {
             int rs = c->k_end[g] - c->k_begin[g];
-            for (int kk = 0; kk < rs; ++kk) {
-                em_step_replica(c, g, kk, n, Fbuf, Fnet, dF, dFnet);
+            for (int kk = 0; kk < rs && rc == RAO_OK; ++kk) {
+                rc = em_step_replica(c, g, kk, n, Fbuf, Fnet, dF, dFnet, hi);
                 if (c->tsf || window_end) sample_replica(c, g, kk, window_end, w);
             }
         }
         if (window_end) c->n_windows = w + 1;
     }
-    free(Fbuf); free(Fnet); free(dF); free(dFnet);
-    return RAO_OK;
+    free(Fbuf); free(Fnet); free(dF); free(dFnet); free(hi);
+    return rc;
 }
 
 /* RSF estimate (Sec. II): replica mean of the sampled tension and the

@@ -9,10 +9,12 @@
  *
  * Model (Kania, Nguyen, Oztekin, Webb, "Replica-Averaging", Sec. II):
  *   - bead-spring chain of N beads, spring j joins beads j and j+1;
- *   - Brownian-dynamics update Eq. (1) with only the self term Eq. (2) of the
- *     diffusion tensor (free-draining): D_ii = kT/zeta * I, D_ij = 0 (i != j);
+ *   - Brownian-dynamics update Eq. (1), free-draining (D_ii = kT/zeta * I,
+ *     D_ij = 0) or with hydrodynamic interaction through the RPY tensor of
+ *     Eqs. (2)-(3) when hi_radius > 0;
  *   - random displacement with zero mean and covariance 2*D*dt (Eq. 1 text),
- *     Gaussian, generated from a counter-based Philox4x32-10 stream;
+ *     Gaussian: sqrt(2 dt) L xi with L the Cholesky factor of D and xi from a
+ *     counter-based Philox4x32-10 stream (L = sqrt(kT/zeta) I free-draining);
  *   - homogeneous flow v = kappa . r (Sec. II; shear v = gdot * z * x-hat);
  *   - spring tension sampled per spring (Eq. 4: signed kappa (r - r0) for
  *     rest-length harmonic springs, H g |Q| for zero-rest-length Hookean and
@@ -53,6 +55,7 @@ typedef struct {
     double   rest_length;  /* RAO_HARMONIC: zero-force bond length (2a in Sec. II) */
     double   lj_eps;       /* Lennard-Jones well depth u between non-adjacent beads (0 = off) */
     double   lj_rmin;      /* position of the LJ minimum (2a in Sec. II) */
+    double   hi_radius;    /* bead radius a of the RPY tensor, Eqs. 2-3 (0 = free draining) */
     uint32_t stream_id;    /* group id in the Philox counter, < 2^24 */
     uint32_t pad_;
 } rao_group;
@@ -70,6 +73,12 @@ void   rao_noise(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
  * p2 is b for FENE and the rest length for RAO_HARMONIC; returns 1 if clamped */
 int    rao_spring(int spring, double H, double p2, double kT, const double Q[3],
                   double F[3], double* g, double* f);
+/* RPY diffusion tensor block D_ij (i != j) of Eq. 3 for r = r_j - r_i, with
+ * D_ii = kT/zeta I (Eq. 2, zeta = 6 pi eta a): row-major 3x3 into D */
+void   rao_rpy_block(double kT, double zeta, double a, const double r[3], double D[9]);
+/* in-place lower Cholesky of the row-major n x n matrix A (A = L L^T, upper
+ * part zeroed); returns 0, or -1 if a pivot is not positive */
+int    rao_cholesky(int n, double* A);
 /* Lennard-Jones force on bead i from bead j (Sec. II): U = u [(rmin/r)^12 - 2 (rmin/r)^6],
  * d = r_i - r_j; F = (12 u / r^2) [(rmin/r)^12 - (rmin/r)^6] d; returns U */
 double rao_lj(double u, double rmin, const double d[3], double F[3]);

@@ -65,12 +65,13 @@ def equilibrium_parent(n_beads, spring=HOOKEAN, H=1.0, b=0.0, kT=1.0, seed=0):
 
 
 def group(n_beads, n_replicas, dt, spring=HOOKEAN, H=1.0, b=0.0, flow=QUIESCENT, rate=0.0,
-          kT=1.0, zeta=1.0, noise_scale=1.0, stream_id=0, rest_length=0.0, lj_eps=0.0, lj_rmin=0.0):
+          kT=1.0, zeta=1.0, noise_scale=1.0, stream_id=0, rest_length=0.0, lj_eps=0.0, lj_rmin=0.0,
+          hi_radius=0.0):
     return dict(n_beads=int(n_beads), n_replicas=int(n_replicas), spring=int(spring),
                 H=float(H), b=float(b), flow=int(flow), rate=float(rate), kT=float(kT),
                 zeta=float(zeta), dt=float(dt), noise_scale=float(noise_scale),
                 stream_id=int(stream_id), rest_length=float(rest_length), lj_eps=float(lj_eps),
-                lj_rmin=float(lj_rmin))
+                lj_rmin=float(lj_rmin), hi_radius=float(hi_radius))
 
 
 # ---------------------------------------------------------------------------
