@@ -62,7 +62,7 @@ typedef enum {
 typedef enum { RA_HOOKEAN = 0, RA_FENE = 1, RA_HARMONIC = 2 } ra_spring;
 typedef enum { RA_QUIESCENT = 0, RA_UNIAXIAL = 1, RA_PLANAR = 2, RA_SHEAR = 3 } ra_flow;
 
-/* One group = one parent chain and its replicas (host struct, 104 bytes).
+/* One group = one parent chain and its replicas (host struct, 112 bytes).
  * Spring force on bead j from spring j: F = H g Q, Q = r_{j+1} - r_j, with
  *   Hookean  g = 1, tension f = H |Q|;
  *   FENE     g = 1/(1 - min(|Q|^2/Q0^2, 1 - 1e-3)), Q0^2 = b kT/H, f = H g |Q|;
@@ -73,10 +73,16 @@ typedef enum { RA_QUIESCENT = 0, RA_UNIAXIAL = 1, RA_PLANAR = 2, RA_SHEAR = 3 } 
  * (|i - j| >= 2, Sec. II): U = lj_eps [(lj_rmin/r)^12 - 2 (lj_rmin/r)^6].
  * Groups with a HARMONIC spring or lj_eps > 0 run the pair-interaction kernel
  * (N <= 64, no adjoint); a context holds either only such groups or none.
+ * Hydrodynamic interaction (hi_radius = a > 0): D_ii = kT/zeta I (Eq. 2, zeta
+ * = 6 pi eta a), D_ij the RPY tensor of Eq. 3, drift dt D F / kT and random
+ * displacement sqrt(2 dt) L xi with D = L L^T (Cholesky) every step; any spring
+ * law and LJ; one workgroup per replica (N <= 64 within the device's LDS per
+ * workgroup: 3N(3N+1)/2 + 1024 elements); a context holds only HI groups or
+ * none; no adjoint, no plain path.
  * Flow: uniaxial kappa = rate*diag(1,-1/2,-1/2); planar rate*diag(1,-1,0);
  * shear v_x = rate * z (the paper's convention, Sec. II). */
 typedef struct {
-    int32_t  n_beads;      /* N, 2 <= N <= 1024 (FP64: N <= 256; pair kernel: N <= 64) */
+    int32_t  n_beads;      /* N, 2 <= N <= 1024 (FP64: N <= 256; pair and HI kernels: N <= 64) */
     int32_t  n_replicas;   /* R >= 1 */
     int32_t  spring;       /* ra_spring */
     int32_t  flow;         /* ra_flow */
@@ -90,6 +96,7 @@ typedef struct {
     double   rest_length;  /* HARMONIC rest length r0 >= 0 (ignored otherwise) */
     double   lj_eps;       /* LJ well depth >= 0 (0 = no LJ) */
     double   lj_rmin;      /* LJ minimum position > 0 when lj_eps > 0 */
+    double   hi_radius;    /* bead radius a of the RPY tensor (Eqs. 2-3); 0 = free draining */
     uint32_t stream_id;    /* group id in the random counter, < 2^24 */
     uint32_t pad_;
 } ra_chain_desc;
@@ -232,7 +239,8 @@ RA_API ra_status ra_get_bonds(ra_ctx* ctx, double* out);
  * replicas per wavefront; kernel_family (host int32[1], may be NULL): 1 = one
  * bead per lane with a noise-producer wavefront per work item, 2 = the
  * pair-interaction kernel (one bead per lane; LJ and rest-length springs),
- * 4 = 1-4 beads per lane, 16 = 6-16 beads per lane, 0 = plain path. */
+ * 3 = hydrodynamic-interaction kernel (one workgroup per replica), 4 = 1-4
+ * beads per lane, 16 = 6-16 beads per lane, 0 = plain path. */
 RA_API ra_status ra_tile_info(ra_ctx* ctx, int32_t* beads_per_lane, int32_t* replicas_per_wave,
                               int32_t* kernel_family);
 

@@ -1,0 +1,322 @@
+// ra_hi.hip — forward kernel with hydrodynamic interaction (Eqs. 1-3).
+//
+// Per step and replica: the 3N x 3N Rotne-Prager-Yamakawa diffusion tensor D
+// (Eq. 2 on the diagonal, Eq. 3 off it) from the current positions, the drift
+// dt D F / kT, and the random displacement sqrt(2 dt) L xi with D = L L^T
+// (Cholesky), xi the per-bead normals of the replica counter. Forces F are the
+// springs (Hookean, FENE or rest-length harmonic) plus optional LJ between
+// non-adjacent beads, as in the pair kernel.
+//
+// One workgroup (256 threads) per replica. D lives in LDS as a packed lower
+// triangle (n = 3N <= 192: at most 18528 elements) and is factored in place by
+// a square-root-free right-looking Cholesky: for every column k, each thread
+// updates its share of the trailing triangle A_ij -= A_ik A_jk / A_kk on a
+// 16 x 16 thread grid (one barrier per column); a last pass scales column j by
+// 1/sqrt(A_jj). Wave 0 keeps the bond state in registers (lane i = bond i),
+// rebuilds positions by a wave scan, forms spring/LJ forces and the noise,
+// and applies the bond-form update Q_j += dt kappa Q_j + (Y_{j+1} - Y_j), Y the
+// bead displacements without the flow term.
+#include "ra_chain.hpp"
+#include "ra_launch.hpp"
+
+namespace ra {
+
+constexpr int HI_THREADS = 256;
+
+template <typename T> struct HiCo;
+template <> struct HiCo<float> {
+    const GroupDev& G;
+    __device__ float r0() const { return G.r0; }
+    __device__ float lj12u() const { return G.lj12u; }
+    __device__ float ljr2() const { return G.ljr2; }
+};
+template <> struct HiCo<double> {
+    const GroupDev& G;
+    __device__ double r0() const { return G.r0_d; }
+    __device__ double lj12u() const { return G.lj12u_d; }
+    __device__ double ljr2() const { return G.ljr2_d; }
+};
+
+__device__ __forceinline__ int tri(int i) { return (i * (i + 1)) >> 1; }
+
+// Lane force of the spring on bond Q (on its first bead, toward the second).
+template <typename T>
+__device__ __forceinline__ void hi_spring(T qx, T qy, T qz, const GroupDev& G, T& fx, T& fy, T& fz, int& clamps) {
+    const T H = Co<T>{G}.H();
+    const T q2 = fmadd(qx, qx, fmadd(qy, qy, qz * qz));
+    T g = (T)1;
+    if (G.spring == 1) {
+        g = fene_g(qx, qy, qz, q2, (T)G.inv_q0sq, G.inv_q0sq_d, clamps);
+    } else if (G.spring == 2) {
+        const T q = fast_sqrt(q2);
+        g = q > (T)0 ? (T)1 - HiCo<T>{G}.r0() * fast_rcp(q) : (T)0;
+    }
+    fx = H * g * qx;
+    fy = H * g * qy;
+    fz = H * g * qz;
+}
+
+template <typename T>
+__device__ __forceinline__ T hi_tension(T qx, T qy, T qz, const GroupDev& G) {
+    const T H = Co<T>{G}.H();
+    const T q2 = fmadd(qx, qx, fmadd(qy, qy, qz * qz));
+    const T q = fast_sqrt(q2);
+    if (G.spring == 2) return H * (q - HiCo<T>{G}.r0());
+    if (G.spring == 1) {
+        int dummy = 0;
+        return H * fene_g(qx, qy, qz, q2, (T)G.inv_q0sq, G.inv_q0sq_d, dummy) * q;
+    }
+    return H * q;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_scan_incl(T v, int lane) {
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const T u = __shfl_up(v, (unsigned)off, WAVE);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+// RPY block of Eq. 3 over D0 = kT/zeta for the pair separation (dx, dy, dz):
+// D_ab = D0 (ci delta_ab + cr rhat_a rhat_b).
+template <typename T>
+__device__ __forceinline__ void rpy_coeffs(T dx, T dy, T dz, T a, T& ci, T& cr, T& ux, T& uy, T& uz) {
+    const T r2 = fmadd(dx, dx, fmadd(dy, dy, dz * dz));
+    const T q = fast_sqrt(r2);
+    const T iq = q > (T)0 ? fast_rcp(q) : (T)0;
+    ux = dx * iq;
+    uy = dy * iq;
+    uz = dz * iq;
+    if (q >= (T)2 * a) {
+        const T s = (T)0.75 * a * iq;
+        const T a2r2 = a * a * iq * iq;
+        ci = s * fmadd((T)2 / (T)3, a2r2, (T)1);
+        cr = s * fmadd((T)-2, a2r2, (T)1);
+    } else {
+        const T t = q / a;
+        ci = fmadd((T)(-9.0 / 32.0), t, (T)1);
+        cr = (T)(3.0 / 32.0) * t;
+    }
+}
+
+template <typename T>
+__device__ void run_hi(const FwdArgs& a, const GroupDev& G, int k, T* lds) {
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const bool w0 = tid < WAVE;
+    const int N = G.N, nm1 = N - 1, n = 3 * N;
+    T* A = lds;                       // packed lower triangle, tri(n) elements
+    T* P = A + tri(n);                // positions [N][4]
+    T* F = P + 4 * WAVE;              // forces [n]
+    T* X = F + 3 * WAVE;              // normals [n]
+    T* DF = X + 3 * WAVE;             // D F [n]
+    T* Y = DF + 3 * WAVE;             // bead displacement without flow [n]
+    const bool bond_ok = w0 && lane < nm1;
+    const bool bead_ok = w0 && lane < N;
+    T* const state = (T*)a.state;
+    const int64_t sidx = (int64_t)k * nm1 + lane;
+    T qx = (T)0, qy = (T)0, qz = (T)0;
+    if (bond_ok) {
+        const int64_t o = G.state_off + sidx * 3;
+        qx = state[o];
+        qy = state[o + 1];
+        qz = state[o + 2];
+    }
+    const Co<T> c{G};
+    const HiCo<T> hc{G};
+    const T kx = c.kx(), ky = c.ky(), kz = c.kz(), kxz = c.kxz();
+    const T D0 = (T)(G.kT / G.zeta);
+    const T drift = (T)(G.dt / G.kT);                                 // dt / kT
+    const T nsc = (T)(G.sigma_d * sqrt(G.zeta / G.kT));               // noise_scale sqrt(2 dt)
+    const T ahi = (T)G.hi_a_d;
+    const bool lj = G.lj12u_d > 0.0;
+    const T lj12u = hc.lj12u(), ljr2 = hc.ljr2();
+    const RoundKeys keys = round_keys(a.key0, a.key1);
+    const uint32_t n0 = (uint32_t)*a.step0;
+    const int S = a.S;
+    const bool tsf = a.tsf != nullptr;
+    double acc = 0.0;
+    if (tsf && bond_ok) acc = a.tsf_acc[G.smp_off + sidx];
+    int to_smp = S - (int)(n0 % (uint32_t)S);
+    int64_t w = (int64_t)(n0 / (uint32_t)S);
+    int clamps = 0;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int n_steps = (int)a.n_steps;
+    for (int st = 0; st < n_steps; ++st) {
+        const uint32_t nstep = n0 + (uint32_t)st;
+        // 1. positions, forces, noise (wave 0)
+        if (w0) {
+            const T px = wave_scan_incl(qx, lane) - qx;
+            const T py = wave_scan_incl(qy, lane) - qy;
+            const T pz = wave_scan_incl(qz, lane) - qz;
+            P[4 * lane] = px;
+            P[4 * lane + 1] = py;
+            P[4 * lane + 2] = pz;
+            T gx, gy, gz;
+            hi_spring(qx, qy, qz, G, gx, gy, gz, clamps);
+            T fx = gx - from_prev_lane(gx), fy = gy - from_prev_lane(gy), fz = gz - from_prev_lane(gz);
+            if (lj) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int j = 0; j < N; ++j) {
+                    const T dx = px - P[4 * j], dy = py - P[4 * j + 1], dz = pz - P[4 * j + 2];
+                    const int dj = j - lane;
+                    const bool use = bead_ok && (dj >= 2 || dj <= -2);
+                    const T r2 = use ? fmadd(dx, dx, fmadd(dy, dy, dz * dz)) : (T)1;
+                    const T inv = fast_rcp(r2);
+                    const T s1 = ljr2 * inv;
+                    const T s3 = s1 * s1 * s1;
+                    const T cc = use ? lj12u * inv * fmadd(s3, s3, -s3) : (T)0;
+                    fx = fmadd(cc, dx, fx);
+                    fy = fmadd(cc, dy, fy);
+                    fz = fmadd(cc, dz, fz);
+                }
+            }
+            if (bead_ok) {
+                F[3 * lane] = fx;
+                F[3 * lane + 1] = fy;
+                F[3 * lane + 2] = fz;
+                T ex, ey, ez;
+                normals3(philox10(nstep, (uint32_t)lane, (uint32_t)k, G.stream, keys), ex, ey, ez);
+                X[3 * lane] = ex;
+                X[3 * lane + 1] = ey;
+                X[3 * lane + 2] = ez;
+            }
+        }
+        __syncthreads();
+        // 2. D: one pair (i >= j) at a time, its 3x3 block (lower part on the diagonal)
+        const int n_pairs = tri(N);
+        for (int p = tid; p < n_pairs; p += HI_THREADS) {
+            int i = (int)((fast_sqrt(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+            while (tri(i) > p) --i;
+            while (tri(i + 1) <= p) ++i;
+            const int j = p - tri(i);
+            if (i == j) {
+                const int r0 = 3 * i;
+                A[tri(r0) + r0] = D0;
+                A[tri(r0 + 1) + r0] = (T)0;
+                A[tri(r0 + 1) + r0 + 1] = D0;
+                A[tri(r0 + 2) + r0] = (T)0;
+                A[tri(r0 + 2) + r0 + 1] = (T)0;
+                A[tri(r0 + 2) + r0 + 2] = D0;
+            } else {
+                T ci, cr, ux, uy, uz;
+                rpy_coeffs(P[4 * j] - P[4 * i], P[4 * j + 1] - P[4 * i + 1], P[4 * j + 2] - P[4 * i + 2], ahi, ci,
+                           cr, ux, uy, uz);
+                const T u[3] = {ux, uy, uz};
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    T* row = A + tri(3 * i + x) + 3 * j;
+#pragma unroll
+                    for (int y = 0; y < 3; ++y) row[y] = D0 * fmadd(cr, u[x] * u[y], x == y ? ci : (T)0);
+                }
+            }
+        }
+        __syncthreads();
+        // 3. drift D F (before the factorization overwrites D)
+        for (int r = tid; r < n; r += HI_THREADS) {
+            T s = (T)0;
+            for (int b = 0; b < n; ++b) s = fmadd(b <= r ? A[tri(r) + b] : A[tri(b) + r], F[b], s);
+            DF[r] = s;
+        }
+        // 4. square-root-free Cholesky: A_ij -= A_ik A_jk / A_kk, column by column
+        for (int kk = 0; kk < n; ++kk) {
+            __syncthreads();
+            const T d = A[tri(kk) + kk];
+            if (tid == 0 && !(d > (T)0)) atomicOr(a.status, 4);
+            const T inv = (T)1 / d;
+            for (int i = kk + 1 + ty; i < n; i += 16) {
+                const T aik = A[tri(i) + kk] * inv;
+                T* row = A + tri(i);
+                for (int j = kk + 1 + tx; j <= i; j += 16) row[j] = fmadd(-aik, A[tri(j) + kk], row[j]);
+            }
+        }
+        __syncthreads();
+        // scale: L_ij = A_ij / sqrt(A_jj) below the diagonal, then L_jj = sqrt(A_jj)
+        for (int i = ty; i < n; i += 16)
+            for (int j = tx; j < i; j += 16) A[tri(i) + j] *= (T)1 / fast_sqrt(A[tri(j) + j]);
+        __syncthreads();
+        for (int j = tid; j < n; j += HI_THREADS) A[tri(j) + j] = fast_sqrt(A[tri(j) + j]);
+        __syncthreads();
+        // 5. bead displacement without the flow term: dt D F / kT + sqrt(2 dt) L xi
+        for (int r = tid; r < n; r += HI_THREADS) {
+            T y = (T)0;
+            for (int b = 0; b <= r; ++b) y = fmadd(A[tri(r) + b], X[b], y);
+            Y[r] = fmadd(drift, DF[r], nsc * y);
+        }
+        __syncthreads();
+        // 6. bond update and sampling (wave 0)
+        if (w0) {
+            if (bond_ok) {
+                const T ix = fmadd(kx, qx, fmadd(kxz, qz, Y[3 * lane + 3] - Y[3 * lane]));
+                const T iy = fmadd(ky, qy, Y[3 * lane + 4] - Y[3 * lane + 1]);
+                const T iz = fmadd(kz, qz, Y[3 * lane + 5] - Y[3 * lane + 2]);
+                qx += ix;
+                qy += iy;
+                qz += iz;
+            }
+            const bool window_end = --to_smp == 0;
+            if (tsf || window_end) {
+                const T f = hi_tension(qx, qy, qz, G);
+                if (tsf) acc += (double)f;
+                if (window_end) {
+                    bool bad = false;
+                    if (bond_ok) {
+                        const int64_t o = w * a.smp_total + G.smp_off + sidx;
+                        ((T*)a.samples)[o] = f;
+                        bad = !__builtin_isfinite((double)f);
+                        if (tsf) {
+                            ((T*)a.tsf)[o] = (T)(acc / (double)S);
+                            acc = 0.0;
+                        }
+                    }
+                    if (bad) atomicOr(a.status, 2);
+                    to_smp = S;
+                    ++w;
+                }
+            }
+        }
+    }
+    if (bond_ok) {
+        const int64_t o = G.state_off + sidx * 3;
+        state[o] = qx;
+        state[o + 1] = qy;
+        state[o + 2] = qz;
+        if (tsf) a.tsf_acc[G.smp_off + sidx] = acc;
+    }
+    if (w0) flush_clamps(clamps, a.clamps + (&G - a.groups));
+}
+
+template <typename T>
+__global__ __launch_bounds__(HI_THREADS) void fwd_hi_kernel(FwdArgs a) {
+    extern __shared__ __align__(16) unsigned char hi_lds[];
+    const int item = (int)blockIdx.x;
+    if (item >= a.n_items) return;
+    if (*(const volatile int*)a.status & 1) return;   // invalid parent: no work (whole block)
+    const Item it = a.items[item];
+    const GroupDev& G = a.groups[it.g];
+    if (it.k0 >= G.R) return;
+    run_hi<T>(a, G, it.k0, (T*)hi_lds);
+}
+
+size_t hi_lds_bytes(int max_beads, int precision) {
+    const int n = 3 * max_beads;
+    const size_t elems = (size_t)n * (n + 1) / 2 + 4 * WAVE + 12 * WAVE;
+    return elems * (precision == 64 ? 8 : 4);
+}
+
+hipError_t launch_forward_hi(const FwdArgs& a, int precision, int max_beads, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    if (a.n_items <= 0 || a.n_steps <= 0) return hipSuccess;
+    const size_t lds = hi_lds_bytes(max_beads, precision);
+    dim3 grid((unsigned)a.n_items), block(HI_THREADS);
+    // the host checked lds against the device's per-workgroup limit
+    if (precision == 64) hipLaunchKernelGGL(fwd_hi_kernel<double>, grid, block, lds, st, a);
+    else hipLaunchKernelGGL(fwd_hi_kernel<float>, grid, block, lds, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace ra

@@ -60,6 +60,7 @@ struct ra_ctx {
     int64_t step = 0;
     bool initialised = false;
     bool recloned = false;          // a re-clone since the last init (no adjoint)
+    int hi_nmax = 0;                // largest N of an HI context (sizes the kernel's LDS)
     std::map<int64_t, hipGraphExec_t> graphs;
     std::string err;
 };
@@ -84,8 +85,12 @@ ra_status fail(ra_ctx* c, ra_status code, const std::string& msg) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Groups of the collapsed-polymer force field run the pair-interaction kernel.
-bool is_pair_group(const ra_chain_desc& d) { return d.spring == RA_HARMONIC || d.lj_eps > 0.0; }
+// Groups with hydrodynamic interaction run the HI kernel; other groups of the
+// collapsed-polymer force field run the pair-interaction kernel.
+bool is_hi_group(const ra_chain_desc& d) { return d.hi_radius > 0.0; }
+bool is_pair_group(const ra_chain_desc& d) {
+    return !is_hi_group(d) && (d.spring == RA_HARMONIC || d.lj_eps > 0.0);
+}
 
 ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std::string& why) {
     char buf[256];
@@ -104,20 +109,32 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
     if (r->reserved_ != 0) { why = "reserved_ must be 0"; return RA_EINVAL; }
     const int wpb = r->waves_per_block ? r->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4) { why = "waves_per_block must be 0, 1, 2 or 4"; return RA_EINVAL; }
-    int n_pair = 0;
-    for (int i = 0; i < n; ++i) n_pair += is_pair_group(g[i]) ? 1 : 0;
-    if (n_pair > 0 && n_pair < n) {
-        why = "a context holds either only pair-interaction groups (HARMONIC spring or LJ) or none";
+    int n_pair = 0, n_hi = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!(std::isfinite(g[i].hi_radius) && g[i].hi_radius >= 0)) {
+            std::snprintf(buf, sizeof buf, "group %d: hi_radius must be finite and >= 0", i);
+            why = buf;
+            return RA_EINVAL;
+        }
+        n_pair += is_pair_group(g[i]) ? 1 : 0;
+        n_hi += is_hi_group(g[i]) ? 1 : 0;
+    }
+    if ((n_pair > 0 && n_pair < n) || (n_hi > 0 && n_hi < n)) {
+        why = "a context holds only pair-interaction groups (HARMONIC spring or LJ), only "
+              "hydrodynamic-interaction groups (hi_radius > 0), or only chain-model groups";
         return RA_EINVAL;
     }
-    if (n_pair > 0 && r->checkpoint_every > 0) {
-        why = "the adjoint covers the Hookean and FENE chain model only";
+    if ((n_pair > 0 || n_hi > 0) && r->checkpoint_every > 0) {
+        why = "the adjoint covers the free-draining Hookean and FENE chain model only";
         return RA_EINVAL;
     }
-    if (n_pair > 0 && r->plain) { why = "the pair-interaction model has no plain path"; return RA_EINVAL; }
+    if ((n_pair > 0 || n_hi > 0) && r->plain) {
+        why = "the pair-interaction and HI models have no plain path";
+        return RA_EINVAL;
+    }
     for (int i = 0; i < n; ++i) {
         const ra_chain_desc& d = g[i];
-        const int nmax = n_pair ? WAVE : r->precision == 64 ? 256 : 1024;
+        const int nmax = (n_pair || n_hi) ? WAVE : r->precision == 64 ? 256 : 1024;
         const char* bad = nullptr;
         if (d.n_beads < 2 || d.n_beads > nmax) bad = "n_beads out of range";
         else if (d.n_replicas < 1) bad = "n_replicas < 1";
@@ -172,6 +189,7 @@ GroupDev make_group(const ra_chain_desc& d, int M, int tag) {
     G.lj12u_d = 12.0 * d.lj_eps;
     G.ljr2_d = d.lj_eps > 0.0 ? d.lj_rmin * d.lj_rmin : 0.0;
     G.dtz = (float)G.dtz_d; G.r0 = (float)G.r0_d; G.lj12u = (float)G.lj12u_d; G.ljr2 = (float)G.ljr2_d;
+    G.hi_a_d = d.hi_radius;
     return G;
 }
 
@@ -235,12 +253,33 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
         if (groups[i].n_beads > 4 * WAVE) family = 16;
     if (run->precision == 64) family = 4;
     const bool pair = is_pair_group(groups[0]);   // validated: all groups or none
+    const bool hi = is_hi_group(groups[0]);
     if (pair) family = 2;
+    if (hi) {
+        family = 3;
+        int nmax = 2;
+        for (int i = 0; i < n_groups; ++i) nmax = std::max(nmax, groups[i].n_beads);
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+            ra_destroy(c);
+            return fail(nullptr, RA_EDEVICE, "cannot query the LDS size per workgroup");
+        }
+        const size_t need = hi_lds_bytes(nmax, run->precision);
+        if (need > (size_t)lds_max) {
+            char b2[200];
+            std::snprintf(b2, sizeof b2, "n_beads %d needs %zu B of LDS per workgroup for the HI kernel at "
+                          "precision %d; the device has %d", nmax, need, run->precision, lds_max);
+            ra_destroy(c);
+            return fail(nullptr, RA_EINVAL, b2);
+        }
+        c->hi_nmax = nmax;
+    }
     for (int i = 0; i < n_groups; ++i) {
         int forced = run->tile_policy > 1000 ? run->tile_policy - 1000 : 0;
-        Ms[i] = pair ? 1 : choose_beads_per_lane(groups[i].n_beads, groups[i].n_replicas, family, forced);
+        Ms[i] = (pair || hi) ? 1 : choose_beads_per_lane(groups[i].n_beads, groups[i].n_replicas, family, forced);
     }
-    if (run->tile_policy == 1 && !run->plain && !pair) {
+    if (run->tile_policy == 1 && !run->plain && !pair && !hi) {
         ra_status st = autotune_tiles(c->descs, *run, family, c->wpb, c->stream, Ms, why);
         if (st != RA_OK) {
             ra_destroy(c);
@@ -274,6 +313,7 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     int64_t par = 0;
     for (int i = 0; i < n_groups; ++i) {
         GroupDev G = make_group(groups[i], Ms[i], run->noise_tag);
+        if (hi) G.P = 1;   // one replica per workgroup
         const int64_t nm1 = G.N - 1;
         G.state_off = c->state_total;
         G.smp_off = c->smp_total;
@@ -427,6 +467,7 @@ static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps) {
         a.n_steps = std::min(chunk, n_steps - done);
         if (c->family == 1) HIPCHK(c, launch_forward_split(a, c->stream));
         else if (c->family == 2) HIPCHK(c, launch_forward_pair(a, c->run.precision, c->wpb, c->stream));
+        else if (c->family == 3) HIPCHK(c, launch_forward_hi(a, c->run.precision, c->hi_nmax, c->stream));
         else HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->stream));
         HIPCHK(c, launch_advance(c->dstep, a.n_steps, c->stream));
     }

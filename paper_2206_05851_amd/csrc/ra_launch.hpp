@@ -78,6 +78,10 @@ hipError_t launch_grad_reduce(const int32_t* item_begin, int n_groups, const dou
 // pair-interaction (collapsed-polymer) forward kernel (ra_pair.hip)
 hipError_t launch_forward_pair(const FwdArgs& a, int precision, int waves_per_block, hipStream_t st);
 
+// hydrodynamic-interaction forward kernel (ra_hi.hip)
+size_t hi_lds_bytes(int max_beads, int precision);
+hipError_t launch_forward_hi(const FwdArgs& a, int precision, int max_beads, hipStream_t st);
+
 // RSF cycle and estimators (ra_rsf.hip)
 hipError_t launch_reclone(const GroupDev* groups, const GroupDev* pgroups, int n_groups, int64_t max_elems,
                           const void* pstate, void* state, double* tsf_acc, int32_t* status, int precision,

@@ -31,6 +31,7 @@ struct GroupDev {
     // beads |i - j| >= 2, force (12u/r^2) [(rmin/r)^12 - (rmin/r)^6] (r_i - r_j)
     float dtz, r0, lj12u, ljr2;          // dt/zeta, rest length, 12 u, rmin^2
     double dtz_d, r0_d, lj12u_d, ljr2_d;
+    double hi_a_d;                       // RPY bead radius (Eqs. 2-3), 0 = free draining
 };
 
 // One wavefront of work: replicas [k0, k0 + P) of group g.

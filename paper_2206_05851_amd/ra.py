@@ -38,6 +38,7 @@ class ChainDesc(ctypes.Structure):
                 ("kT", ctypes.c_double), ("zeta", ctypes.c_double), ("dt", ctypes.c_double),
                 ("noise_scale", ctypes.c_double), ("rest_length", ctypes.c_double),
                 ("lj_eps", ctypes.c_double), ("lj_rmin", ctypes.c_double),
+                ("hi_radius", ctypes.c_double),
                 ("stream_id", ctypes.c_uint32), ("pad_", ctypes.c_uint32)]
 
 
@@ -51,7 +52,7 @@ class RunDesc(ctypes.Structure):
                 ("reserved_", ctypes.c_int32)]
 
 
-assert ctypes.sizeof(ChainDesc) == 104 and ctypes.sizeof(RunDesc) == 56
+assert ctypes.sizeof(ChainDesc) == 112 and ctypes.sizeof(RunDesc) == 56
 
 _lib = None
 
@@ -127,6 +128,7 @@ def make_desc(d, index):
     c.rest_length = float(d.get("rest_length", 0.0))
     c.lj_eps = float(d.get("lj_eps", 0.0))
     c.lj_rmin = float(d.get("lj_rmin", 0.0))
+    c.hi_radius = float(d.get("hi_radius", 0.0))
     c.stream_id = int(d.get("stream_id", index))
     return c
 

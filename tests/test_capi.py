@@ -44,8 +44,8 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_sizes_match_header():
     from paper_2206_05851_amd import ra
     text = open(os.path.join(ROOT, "include", "ra.h")).read()
-    assert "104 bytes" in text and "56 bytes" in text
-    assert ctypes.sizeof(ra.ChainDesc) == 104
+    assert "112 bytes" in text and "56 bytes" in text
+    assert ctypes.sizeof(ra.ChainDesc) == 112
     assert ctypes.sizeof(ra.RunDesc) == 56
 
 
@@ -83,6 +83,10 @@ def _create(lib, desc_kw, run_kw):
     (dict(spring=2, rest_length=2.0, n_beads=65), {}, "n_beads"),
     (dict(spring=2, rest_length=2.0), dict(checkpoint_every=10), "adjoint"),
     (dict(spring=2, rest_length=2.0), dict(plain=1), "plain"),
+    (dict(hi_radius=-0.5), {}, "hi_radius"),
+    (dict(hi_radius=0.5, n_beads=65), {}, "n_beads"),
+    (dict(hi_radius=0.5), dict(checkpoint_every=10), "adjoint"),
+    (dict(hi_radius=0.5), dict(plain=1), "plain"),
     ({}, dict(reserved_=1), "reserved_"),
 ])
 def test_invalid_descriptors_rejected_on_host(lib, desc_kw, run_kw, frag):
@@ -101,3 +105,15 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.ra_mftu(None, None, 1, None) == -1
     assert lib.ra_conformation(None, None, None, None, None) == -1
     lib.ra_destroy(None)
+
+
+def test_mixed_model_classes_rejected_on_host(lib):
+    from paper_2206_05851_amd import ra
+    run = ra.RunDesc(seed=0, precision=32, sample_every=10, max_windows=4)
+    for extra in (dict(hi_radius=0.5), dict(spring=2, rest_length=2.0), dict(lj_eps=1.0, lj_rmin=1.0)):
+        d0 = ra.make_desc(dict(n_beads=10, n_replicas=4, dt=1e-3), 0)
+        d1 = ra.make_desc(dict(dict(n_beads=10, n_replicas=4, dt=1e-3), **extra), 1)
+        arr = (ra.ChainDesc * 2)(d0, d1)
+        p = ctypes.c_void_p()
+        assert lib.ra_create(ctypes.byref(p), arr, 2, ctypes.byref(run), None) == -1
+        assert "only" in lib.ra_last_error(None).decode()
