@@ -16,8 +16,9 @@ adjoint (N = 100, 4096 replicas, 2000 steps, checkpoints every 100), the
 batched run (512 uneven FENE chains, one graph-captured persistent launch),
 the 1000-bead transient (8192 replicas, 2e4 steps, RSF + TSF) and the RSF
 sampling cycle (a parent trajectory re-cloned into 1000 replicas every 750
-steps, 20 windows, with ISF/TSF/RSF, sigma(N_R) and MFTU) on the FENE chain
-and on the paper's collapsed polymer (rest-length springs + LJ, no HI).
+steps, 20 windows, with ISF/TSF/RSF, sigma(N_R) and MFTU) on the FENE chain,
+on the paper's collapsed polymer (rest-length springs + LJ) and on the full
+model with hydrodynamic interaction (parent + 50 replicas, 4 windows).
 The roofline object is for the fused forward kernel; its time is taken with
 HIP events on the stream the kernel runs on. cpu_baseline is the FP64 oracle
 on a bounded sample of the same workload, on the host's cores.
@@ -154,7 +155,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="plain,adjoint,batched,large1000,rsf50,collapsed50",
+    ap.add_argument("--extras", default="plain,adjoint,batched,large1000,rsf50,collapsed50,hi50",
                     help="comma-separated extra workloads to measure once")
     ap.add_argument("--cpu-replicas", type=int, default=384)
     ap.add_argument("--tile-policy", type=int, default=0,
@@ -350,7 +351,11 @@ def main():
                          ("collapsed50", "RSF cycle on the collapsed polymer without HI: N=50, harmonic "
                                          "backbone kappa=400 rest length 2, LJ u=1 between non-adjacent "
                                          "beads, shear 30, dt=1e-5, parent + 1000 replicas re-cloned every "
-                                         "750 steps (S=0.0075), 20 windows, ISF/TSF/RSF, sigma(N_R), MFTU")):
+                                         "750 steps (S=0.0075), 20 windows, ISF/TSF/RSF, sigma(N_R), MFTU"),
+                         ("hi50", "RSF cycle on the paper's full model: N=50, harmonic backbone kappa=400 "
+                                  "rest length 2, LJ u=1, RPY hydrodynamic interaction a=1 (Cholesky noise "
+                                  "every step), shear 30, dt=1e-5, parent + N_R=50 replicas re-cloned every "
+                                  "750 steps, 4 windows, ISF/TSF/RSF, sigma(N_R), MFTU")):
         if rname in extras:
             out[rname] = rsf_cycle_bench(getattr(wl, rname)(), rdesc, dev, rname)
 

@@ -7,12 +7,11 @@
 // springs (Hookean, FENE or rest-length harmonic) plus optional LJ between
 // non-adjacent beads, as in the pair kernel.
 //
-// One workgroup (256 threads) per replica. D lives in LDS as a packed lower
-// triangle (n = 3N <= 192: at most 18528 elements) and is factored in place by
-// a square-root-free right-looking Cholesky: for every column k, each thread
-// updates its share of the trailing triangle A_ij -= A_ik A_jk / A_kk on a
-// 16 x 16 thread grid (one barrier per column); a last pass scales column j by
-// 1/sqrt(A_jj). Wave 0 keeps the bond state in registers (lane i = bond i),
+// One workgroup (256 threads) per replica. D is assembled in LDS as a packed
+// lower triangle (n = 3N <= 192: at most 18528 elements), from which the drift
+// D F is taken; the factorization then runs on a copy of the lower triangle
+// held in registers (see factor_apply), exchanging one column per step of the
+// elimination through LDS. Wave 0 keeps the bond state in registers (lane i = bond i),
 // rebuilds positions by a wave scan, forms spring/LJ forces and the noise,
 // and applies the bond-form update Q_j += dt kappa Q_j + (Y_{j+1} - Y_j), Y the
 // bead displacements without the flow term.
@@ -101,8 +100,97 @@ __device__ __forceinline__ void rpy_coeffs(T dx, T dy, T dz, T a, T& ci, T& cr, 
     }
 }
 
-template <typename T>
-__device__ void run_hi(const FwdArgs& a, const GroupDev& G, int k, T* lds) {
+// Cholesky D = L L^T of the packed tensor A (n = 3N rows) with the lower
+// triangle held in registers: thread (tx, ty) of the 16 x 16 grid owns rows
+// i = ty + 16a and columns j = tx + 16b (b <= a). Square-root-free right-
+// looking elimination R_ij -= R_ik R_jk / R_kk; per column k the owners of
+// column k publish it through a double-buffered LDS column (one barrier per
+// column). The block-column loop is unrolled so every register index is a
+// compile-time constant. Then L = R diag(1/sqrt(R_jj)), y = L xi by 16-lane
+// butterflies (fixed order), and Y_i = drift DF_i + nsc y_i.
+template <typename T, int NB>
+__device__ __forceinline__ void factor_apply(const T* A, int n, int tx, int ty, T* cbuf, const T* X, const T* DF,
+                                             T* Y, T drift, T nsc, int32_t* status) {
+    T R[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        const int i = ty + 16 * a;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int j = tx + 16 * b;
+            R[a][b] = (T)0;
+            if (i < n && j <= i) R[a][b] = A[tri(i) + j];
+        }
+    }
+#pragma unroll
+    for (int bk = 0; bk < NB; ++bk) {
+        for (int kb = 0; kb < 16; ++kb) {
+            const int kk = 16 * bk + kb;
+            if (kk >= n) break;
+            T* cb = cbuf + (kk & 1) * (16 * NB);
+            if (tx == kb) {
+#pragma unroll
+                for (int a = bk; a < NB; ++a) {
+                    const int i = ty + 16 * a;
+                    if (i >= kk && i < n) cb[i] = R[a][bk];
+                }
+            }
+            __syncthreads();
+            const T d = cb[kk];
+            if (tx == 0 && ty == 0 && !(d > (T)0)) atomicOr(status, 4);
+            const T inv = (T)1 / d;
+            T ci[NB], cj[NB];
+#pragma unroll
+            for (int a = bk; a < NB; ++a) {
+                const int i = ty + 16 * a;
+                ci[a] = (T)0;
+                if (i > kk && i < n) ci[a] = cb[i] * inv;
+                const int j = tx + 16 * a;
+                cj[a] = (T)0;
+                if (j > kk && j < n) cj[a] = cb[j];
+            }
+#pragma unroll
+            for (int a = bk; a < NB; ++a)
+#pragma unroll
+                for (int b = bk; b <= a; ++b) R[a][b] = fmadd(-ci[a], cj[b], R[a][b]);
+        }
+    }
+    __syncthreads();
+    T* dg = cbuf;   // pivots d_j
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        const int i = ty + 16 * a;
+        if (tx == ty && i < n) dg[i] = R[a][a];
+    }
+    __syncthreads();
+    T rs[NB], xj[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = tx + 16 * b;
+        rs[b] = (T)0;
+        xj[b] = (T)0;
+        if (j < n) {
+            rs[b] = (T)1 / fast_sqrt(dg[j]);
+            xj[b] = X[j];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        const int i = ty + 16 * a;
+        T part = (T)0;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int j = tx + 16 * b;
+            if (j <= i) part = fmadd(R[a][b] * rs[b], xj[b], part);
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) part += __shfl_xor(part, off, 16);
+        if (tx == 0 && i < n) Y[i] = fmadd(drift, DF[i], nsc * part);
+    }
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int k, T* lds) {
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const bool w0 = tid < WAVE;
@@ -113,6 +201,7 @@ __device__ void run_hi(const FwdArgs& a, const GroupDev& G, int k, T* lds) {
     T* X = F + 3 * WAVE;              // normals [n]
     T* DF = X + 3 * WAVE;             // D F [n]
     T* Y = DF + 3 * WAVE;             // bead displacement without flow [n]
+    T* C = Y + 3 * WAVE;              // Cholesky column exchange, 2 x 192
     const bool bond_ok = w0 && lane < nm1;
     const bool bead_ok = w0 && lane < N;
     T* const state = (T*)a.state;
@@ -216,37 +305,16 @@ __device__ void run_hi(const FwdArgs& a, const GroupDev& G, int k, T* lds) {
             }
         }
         __syncthreads();
-        // 3. drift D F (before the factorization overwrites D)
+        // 3. drift D F from the packed tensor (the factorization below keeps D in LDS intact)
         for (int r = tid; r < n; r += HI_THREADS) {
-            T s = (T)0;
-            for (int b = 0; b < n; ++b) s = fmadd(b <= r ? A[tri(r) + b] : A[tri(b) + r], F[b], s);
-            DF[r] = s;
+            T s0 = (T)0, s1 = (T)0;
+            const T* row = A + tri(r);
+            for (int b = 0; b <= r; ++b) s0 = fmadd(row[b], F[b], s0);
+            for (int b = r + 1; b < n; ++b) s1 = fmadd(A[tri(b) + r], F[b], s1);
+            DF[r] = s0 + s1;
         }
-        // 4. square-root-free Cholesky: A_ij -= A_ik A_jk / A_kk, column by column
-        for (int kk = 0; kk < n; ++kk) {
-            __syncthreads();
-            const T d = A[tri(kk) + kk];
-            if (tid == 0 && !(d > (T)0)) atomicOr(a.status, 4);
-            const T inv = (T)1 / d;
-            for (int i = kk + 1 + ty; i < n; i += 16) {
-                const T aik = A[tri(i) + kk] * inv;
-                T* row = A + tri(i);
-                for (int j = kk + 1 + tx; j <= i; j += 16) row[j] = fmadd(-aik, A[tri(j) + kk], row[j]);
-            }
-        }
-        __syncthreads();
-        // scale: L_ij = A_ij / sqrt(A_jj) below the diagonal, then L_jj = sqrt(A_jj)
-        for (int i = ty; i < n; i += 16)
-            for (int j = tx; j < i; j += 16) A[tri(i) + j] *= (T)1 / fast_sqrt(A[tri(j) + j]);
-        __syncthreads();
-        for (int j = tid; j < n; j += HI_THREADS) A[tri(j) + j] = fast_sqrt(A[tri(j) + j]);
-        __syncthreads();
-        // 5. bead displacement without the flow term: dt D F / kT + sqrt(2 dt) L xi
-        for (int r = tid; r < n; r += HI_THREADS) {
-            T y = (T)0;
-            for (int b = 0; b <= r; ++b) y = fmadd(A[tri(r) + b], X[b], y);
-            Y[r] = fmadd(drift, DF[r], nsc * y);
-        }
+        // 4-5. Cholesky in registers and the displacement Y = dt D F / kT + sqrt(2 dt) L xi
+        factor_apply<T, NB>(A, n, tx, ty, C, X, DF, Y, drift, nsc, a.status);
         __syncthreads();
         // 6. bond update and sampling (wave 0)
         if (w0) {
@@ -290,7 +358,10 @@ __device__ void run_hi(const FwdArgs& a, const GroupDev& G, int k, T* lds) {
     if (w0) flush_clamps(clamps, a.clamps + (&G - a.groups));
 }
 
-template <typename T>
+// One kernel per register tile NB (16-row blocks of the tensor): the host
+// picks the smallest NB with 16 NB >= 3 N_max, so each instance gets its own
+// register allocation.
+template <typename T, int NB>
 __global__ __launch_bounds__(HI_THREADS) void fwd_hi_kernel(FwdArgs a) {
     extern __shared__ __align__(16) unsigned char hi_lds[];
     const int item = (int)blockIdx.x;
@@ -299,23 +370,34 @@ __global__ __launch_bounds__(HI_THREADS) void fwd_hi_kernel(FwdArgs a) {
     const Item it = a.items[item];
     const GroupDev& G = a.groups[it.g];
     if (it.k0 >= G.R) return;
-    run_hi<T>(a, G, it.k0, (T*)hi_lds);
+    run_hi<T, NB>(a, G, it.k0, (T*)hi_lds);
 }
 
 size_t hi_lds_bytes(int max_beads, int precision) {
     const int n = 3 * max_beads;
-    const size_t elems = (size_t)n * (n + 1) / 2 + 4 * WAVE + 12 * WAVE;
+    const size_t elems = (size_t)n * (n + 1) / 2 + 4 * WAVE + 12 * WAVE + 2 * 3 * WAVE;
     return elems * (precision == 64 ? 8 : 4);
+}
+
+template <typename T>
+static void launch_hi_nb(const FwdArgs& a, int nb, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+    if (nb <= 2) hipLaunchKernelGGL((fwd_hi_kernel<T, 2>), grid, block, lds, st, a);
+    else if (nb <= 4) hipLaunchKernelGGL((fwd_hi_kernel<T, 4>), grid, block, lds, st, a);
+    else if (nb <= 6) hipLaunchKernelGGL((fwd_hi_kernel<T, 6>), grid, block, lds, st, a);
+    else if (nb <= 8) hipLaunchKernelGGL((fwd_hi_kernel<T, 8>), grid, block, lds, st, a);
+    else if (nb <= 10) hipLaunchKernelGGL((fwd_hi_kernel<T, 10>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((fwd_hi_kernel<T, 12>), grid, block, lds, st, a);
 }
 
 hipError_t launch_forward_hi(const FwdArgs& a, int precision, int max_beads, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     if (a.n_items <= 0 || a.n_steps <= 0) return hipSuccess;
-    const size_t lds = hi_lds_bytes(max_beads, precision);
+    if (max_beads < 2 || max_beads > WAVE) return hipErrorInvalidValue;
+    const size_t lds = hi_lds_bytes(max_beads, precision);   // checked against the device limit by the host
+    const int nb = (3 * max_beads + 15) / 16;
     dim3 grid((unsigned)a.n_items), block(HI_THREADS);
-    // the host checked lds against the device's per-workgroup limit
-    if (precision == 64) hipLaunchKernelGGL(fwd_hi_kernel<double>, grid, block, lds, st, a);
-    else hipLaunchKernelGGL(fwd_hi_kernel<float>, grid, block, lds, st, a);
+    if (precision == 64) launch_hi_nb<double>(a, nb, grid, block, lds, st);
+    else launch_hi_nb<float>(a, nb, grid, block, lds, st);
     return hipGetLastError();
 }
 

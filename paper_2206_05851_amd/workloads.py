@@ -189,3 +189,17 @@ def collapsed50(n_replicas=1000, n_windows=20):
     parent = collapsed_parent(N, seed=105)
     return [g], [parent], dict(seed=6, sample_every=750, parent_steps=750, n_windows=n_windows,
                                precision=32, k0=1e-6, x_dagger=0.1, blocks=(10, 20, 40, 50))
+
+
+def hi50(n_replicas=50, n_windows=4):
+    """The paper's full model (Sec. II): N=50 beads, harmonic backbone
+    kappa=400 kT/a^2 with rest length 2a, LJ u=1 kT between non-adjacent
+    beads, hydrodynamic interaction through the RPY tensor (Eqs. 2-3, a=1),
+    simple shear gamma-dot=30, dt=1e-5; RSF cycle with N_R=50 replicas
+    re-cloned from the parent every 750 steps (S = 0.0075), 4 windows."""
+    N = 50
+    g = group(N, n_replicas, 1e-5, HARMONIC, 400.0, 0.0, SHEAR, 30.0, rest_length=2.0, lj_eps=1.0,
+              lj_rmin=2.0, hi_radius=1.0)
+    parent = collapsed_parent(N, seed=106)
+    return [g], [parent], dict(seed=7, sample_every=750, parent_steps=750, n_windows=n_windows,
+                               precision=32, k0=1e-6, x_dagger=0.1, blocks=(10, 25, 50))
