@@ -362,15 +362,27 @@ __device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int 
 // picks the smallest NB with 16 NB >= 3 N_max, so each instance gets its own
 // register allocation.
 template <typename T, int NB>
-__global__ __launch_bounds__(HI_THREADS) void fwd_hi_kernel(FwdArgs a) {
-    extern __shared__ __align__(16) unsigned char hi_lds[];
-    const int item = (int)blockIdx.x;
+__device__ __forceinline__ void hi_item(const FwdArgs& a, int item, T* lds) {
     if (item >= a.n_items) return;
     if (*(const volatile int*)a.status & 1) return;   // invalid parent: no work (whole block)
     const Item it = a.items[item];
     const GroupDev& G = a.groups[it.g];
     if (it.k0 >= G.R) return;
-    run_hi<T, NB>(a, G, it.k0, (T*)hi_lds);
+    run_hi<T, NB>(a, G, it.k0, lds);
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(HI_THREADS) void fwd_hi_kernel(FwdArgs a) {
+    extern __shared__ __align__(16) unsigned char hi_lds[];
+    hi_item<T, NB>(a, (int)blockIdx.x, (T*)hi_lds);
+}
+
+// Two contexts in one launch (see fwd_dual_kernel): blocks [0, n_items of a) run a.
+template <typename T, int NB>
+__global__ __launch_bounds__(HI_THREADS) void fwd_hi_dual_kernel(FwdArgs a, FwdArgs b) {
+    extern __shared__ __align__(16) unsigned char hi_lds[];
+    if ((int)blockIdx.x < a.n_items) hi_item<T, NB>(a, (int)blockIdx.x, (T*)hi_lds);
+    else hi_item<T, NB>(b, (int)blockIdx.x - a.n_items, (T*)hi_lds);
 }
 
 size_t hi_lds_bytes(int max_beads, int precision) {
@@ -398,6 +410,29 @@ hipError_t launch_forward_hi(const FwdArgs& a, int precision, int max_beads, hip
     dim3 grid((unsigned)a.n_items), block(HI_THREADS);
     if (precision == 64) launch_hi_nb<double>(a, nb, grid, block, lds, st);
     else launch_hi_nb<float>(a, nb, grid, block, lds, st);
+    return hipGetLastError();
+}
+
+template <typename T>
+static void launch_hi_dual_nb(const FwdArgs& a, const FwdArgs& b, int nb, dim3 grid, dim3 block, size_t lds,
+                              hipStream_t st) {
+    if (nb <= 2) hipLaunchKernelGGL((fwd_hi_dual_kernel<T, 2>), grid, block, lds, st, a, b);
+    else if (nb <= 4) hipLaunchKernelGGL((fwd_hi_dual_kernel<T, 4>), grid, block, lds, st, a, b);
+    else if (nb <= 6) hipLaunchKernelGGL((fwd_hi_dual_kernel<T, 6>), grid, block, lds, st, a, b);
+    else if (nb <= 8) hipLaunchKernelGGL((fwd_hi_dual_kernel<T, 8>), grid, block, lds, st, a, b);
+    else if (nb <= 10) hipLaunchKernelGGL((fwd_hi_dual_kernel<T, 10>), grid, block, lds, st, a, b);
+    else hipLaunchKernelGGL((fwd_hi_dual_kernel<T, 12>), grid, block, lds, st, a, b);
+}
+
+hipError_t launch_forward_hi_dual(const FwdArgs& a, const FwdArgs& b, int precision, int max_beads, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    if (a.n_items + b.n_items <= 0) return hipSuccess;
+    if (max_beads < 2 || max_beads > WAVE) return hipErrorInvalidValue;
+    const size_t lds = hi_lds_bytes(max_beads, precision);
+    const int nb = (3 * max_beads + 15) / 16;
+    dim3 grid((unsigned)(a.n_items + b.n_items)), block(HI_THREADS);
+    if (precision == 64) launch_hi_dual_nb<double>(a, b, nb, grid, block, lds, st);
+    else launch_hi_dual_nb<float>(a, b, nb, grid, block, lds, st);
     return hipGetLastError();
 }
 

@@ -442,7 +442,7 @@ ra_status ra_init_chains(ra_ctx* c, const double* parent_xyz) {
     return RA_OK;
 }
 
-static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps) {
+static FwdArgs fwd_args(const ra_ctx* c) {
     FwdArgs a{};
     a.groups = c->dgroups;
     a.items = c->ditems;
@@ -461,16 +461,42 @@ static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps) {
     a.step0 = c->dstep;
     a.status = c->status;
     a.clamps = c->clamps;
+    return a;
+}
+
+// Forward launches of n_steps on stream st (the context's own stream unless a
+// caller orders it on another one), each followed by the step-counter advance.
+static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps, hipStream_t st) {
+    FwdArgs a = fwd_args(c);
     // the kernel counts steps in 32-bit ints: split very long calls
     const int64_t chunk = (int64_t)1 << 30;
     for (int64_t done = 0; done < n_steps; done += chunk) {
         a.n_steps = std::min(chunk, n_steps - done);
-        if (c->family == 1) HIPCHK(c, launch_forward_split(a, c->stream));
-        else if (c->family == 2) HIPCHK(c, launch_forward_pair(a, c->run.precision, c->wpb, c->stream));
-        else if (c->family == 3) HIPCHK(c, launch_forward_hi(a, c->run.precision, c->hi_nmax, c->stream));
-        else HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->stream));
-        HIPCHK(c, launch_advance(c->dstep, a.n_steps, c->stream));
+        if (c->family == 1) HIPCHK(c, launch_forward_split(a, st));
+        else if (c->family == 2) HIPCHK(c, launch_forward_pair(a, c->run.precision, c->wpb, st));
+        else if (c->family == 3) HIPCHK(c, launch_forward_hi(a, c->run.precision, c->hi_nmax, st));
+        else HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, st));
+        HIPCHK(c, launch_advance(c->dstep, a.n_steps, st));
     }
+    return RA_OK;
+}
+
+static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps) { return enqueue_forward(c, n_steps, c->stream); }
+
+// n_a steps of context a and n_b steps of context b in one launch on a's
+// stream (same kernel family, precision and waves per block), then both
+// step-counter advances.
+static ra_status enqueue_forward_dual(ra_ctx* ca, int64_t n_a, ra_ctx* cb, int64_t n_b) {
+    FwdArgs a = fwd_args(ca), b = fwd_args(cb);
+    a.n_steps = n_a;
+    b.n_steps = n_b;
+    hipStream_t st = ca->stream;
+    if (ca->family == 2) HIPCHK(ca, launch_forward_pair_dual(a, b, ca->run.precision, ca->wpb, st));
+    else if (ca->family == 3)
+        HIPCHK(ca, launch_forward_hi_dual(a, b, ca->run.precision, std::max(ca->hi_nmax, cb->hi_nmax), st));
+    else HIPCHK(ca, launch_forward_dual(a, b, ca->run.precision, ca->family, ca->wpb, st));
+    HIPCHK(ca, launch_advance(ca->dstep, n_a, st));
+    HIPCHK(ca, launch_advance(cb->dstep, n_b, st));
     return RA_OK;
 }
 
@@ -671,6 +697,38 @@ ra_status ra_rsf_cycle(ra_ctx* c, ra_ctx* parent, int64_t n_windows, int64_t par
     if (two && !c->ev_parent) {
         HIPCHK(c, hipEventCreateWithFlags(&c->ev_parent, hipEventDisableTiming));
         HIPCHK(c, hipEventCreateWithFlags(&c->ev_reclone, hipEventDisableTiming));
+    }
+    // One-launch schedule: the parent's segment w+1 runs in the same launch as
+    // the replicas' window w (fwd_dual_kernel and its pair/HI forms), all on
+    // the replicas' stream, so the two overlap on any queue mapping.
+    const bool dual = n_windows > 0 && c->family == parent->family && c->wpb == parent->wpb &&
+                      (c->family == 2 || c->family == 3 || c->family == 4 || c->family == 16) &&
+                      S <= (1 << 30) && parent_steps <= (1 << 30);
+    if (dual) {
+        if (two) {   // the parent's queued work comes first
+            HIPCHK(c, hipEventRecord(c->ev_parent, parent->stream));
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_parent, 0));
+        }
+        st = enqueue_forward(parent, parent_steps, c->stream);
+        if (st != RA_OK) return fail(c, st, "parent: " + parent->err);
+        parent->step += parent_steps;
+        for (int64_t w = 0; w < n_windows; ++w) {
+            st = ra_reclone(c, parent);
+            if (st != RA_OK) return st;
+            if (w + 1 < n_windows) {
+                st = enqueue_forward_dual(c, S, parent, parent_steps);
+                parent->step += parent_steps;
+            } else {
+                st = enqueue_forward(c, S);
+            }
+            if (st != RA_OK) return st;
+            c->step += S;
+        }
+        if (two) {   // later parent work waits for the cycle
+            HIPCHK(c, hipEventRecord(c->ev_reclone, c->stream));
+            HIPCHK(c, hipStreamWaitEvent(parent->stream, c->ev_reclone, 0));
+        }
+        return RA_OK;
     }
     for (int64_t w = 0; w < n_windows; ++w) {
         // the parent's next window may start once the last re-clone has read its state

@@ -77,6 +77,12 @@ hipError_t launch_grad_reduce(const int32_t* item_begin, int n_groups, const dou
 
 // pair-interaction (collapsed-polymer) forward kernel (ra_pair.hip)
 hipError_t launch_forward_pair(const FwdArgs& a, int precision, int waves_per_block, hipStream_t st);
+// two contexts (same kernel family) in one launch: blocks of a first, then b
+hipError_t launch_forward_dual(const FwdArgs& a, const FwdArgs& b, int precision, int family, int waves_per_block,
+                               hipStream_t st);
+hipError_t launch_forward_pair_dual(const FwdArgs& a, const FwdArgs& b, int precision, int waves_per_block,
+                                    hipStream_t st);
+hipError_t launch_forward_hi_dual(const FwdArgs& a, const FwdArgs& b, int precision, int max_beads, hipStream_t st);
 
 // hydrodynamic-interaction forward kernel (ra_hi.hip)
 size_t hi_lds_bytes(int max_beads, int precision);

@@ -206,23 +206,37 @@ __device__ void run_pair(const FwdArgs& a, const GroupDev& G, int k_first, T (*x
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void fwd_pair_kernel(FwdArgs a) {
-    __shared__ T xs[4][WAVE][4];
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int item = (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
+__device__ __forceinline__ void pair_item(const FwdArgs& a, int item, T (*xs)[4]) {
     if (item >= a.n_items) return;
     if (*(const volatile int*)a.status & 1) return;   // invalid parent: no work
     const Item it = a.items[item];
     const GroupDev& G = a.groups[it.g];
     const bool lj = G.lj12u_d > 0.0;
     switch (G.spring * 2 + (lj ? 1 : 0)) {
-    case 0: run_pair<T, 0, false>(a, G, it.k0, xs[wave]); break;
-    case 1: run_pair<T, 0, true>(a, G, it.k0, xs[wave]); break;
-    case 2: run_pair<T, 1, false>(a, G, it.k0, xs[wave]); break;
-    case 3: run_pair<T, 1, true>(a, G, it.k0, xs[wave]); break;
-    case 4: run_pair<T, 2, false>(a, G, it.k0, xs[wave]); break;
-    default: run_pair<T, 2, true>(a, G, it.k0, xs[wave]); break;
+    case 0: run_pair<T, 0, false>(a, G, it.k0, xs); break;
+    case 1: run_pair<T, 0, true>(a, G, it.k0, xs); break;
+    case 2: run_pair<T, 1, false>(a, G, it.k0, xs); break;
+    case 3: run_pair<T, 1, true>(a, G, it.k0, xs); break;
+    case 4: run_pair<T, 2, false>(a, G, it.k0, xs); break;
+    default: run_pair<T, 2, true>(a, G, it.k0, xs); break;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fwd_pair_kernel(FwdArgs a) {
+    __shared__ T xs[4][WAVE][4];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    pair_item<T>(a, (int)blockIdx.x * (int)(blockDim.x >> 6) + wave, xs[wave]);
+}
+
+// Two contexts in one launch (see fwd_dual_kernel): blocks [0, blocks_a) run a.
+template <typename T>
+__global__ __launch_bounds__(256) void fwd_pair_dual_kernel(FwdArgs a, FwdArgs b, int blocks_a) {
+    __shared__ T xs[4][WAVE][4];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wpb = (int)(blockDim.x >> 6);
+    if ((int)blockIdx.x < blocks_a) pair_item<T>(a, (int)blockIdx.x * wpb + wave, xs[wave]);
+    else pair_item<T>(b, ((int)blockIdx.x - blocks_a) * wpb + wave, xs[wave]);
 }
 
 hipError_t launch_forward_pair(const FwdArgs& a, int precision, int waves_per_block, hipStream_t st) {
@@ -232,6 +246,18 @@ hipError_t launch_forward_pair(const FwdArgs& a, int precision, int waves_per_bl
     dim3 grid((a.n_items + wpb - 1) / wpb), block(WAVE * wpb);
     if (precision == 64) hipLaunchKernelGGL(fwd_pair_kernel<double>, grid, block, 0, st, a);
     else hipLaunchKernelGGL(fwd_pair_kernel<float>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_pair_dual(const FwdArgs& a, const FwdArgs& b, int precision, int waves_per_block,
+                                    hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    const int wpb = waves_per_block;
+    const int ba = (a.n_items + wpb - 1) / wpb, bb = (b.n_items + wpb - 1) / wpb;
+    if (ba + bb == 0) return hipSuccess;
+    dim3 grid((unsigned)(ba + bb)), block(WAVE * wpb);
+    if (precision == 64) hipLaunchKernelGGL(fwd_pair_dual_kernel<double>, grid, block, 0, st, a, b, ba);
+    else hipLaunchKernelGGL(fwd_pair_dual_kernel<float>, grid, block, 0, st, a, b, ba);
     return hipGetLastError();
 }
 
