@@ -156,7 +156,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <int M, bool FENE>
-__device__ void run_adjoint(const AdjArgs& a, const GroupDev& G, int item, int k_first) {
+__device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G, int item, int k_first) {
     // kernel arguments into locals (the loops must not address the argument block)
     const int S = a.S, K = a.K;
     const int64_t n_end = a.n_end, state_total = a.state_total, spr_total = a.spr_total;
@@ -237,8 +237,16 @@ void adjoint_kernel(AdjArgs a, int item_begin, int item_end) {
     if (item >= item_end) return;
     const Item it = a.items[item];
     const GroupDev& G = a.groups[it.g];
-    if (G.spring == 1) run_adjoint<M, true>(a, G, item, it.k0);
-    else run_adjoint<M, false>(a, G, item, it.k0);
+    if constexpr (M <= 4) {
+        // the group's constants as a local value: read through the reference,
+        // the recompute loop re-loads them from memory every step
+        const GroupDev Gl = G;
+        if (Gl.spring == 1) run_adjoint<M, true>(a, Gl, item, it.k0);
+        else run_adjoint<M, false>(a, Gl, item, it.k0);
+    } else {
+        if (G.spring == 1) run_adjoint<M, true>(a, G, item, it.k0);
+        else run_adjoint<M, false>(a, G, item, it.k0);
+    }
 }
 
 // lam_mu[w][s] = grad_mean + grad_rates * dk/dmean, dk/dmean = k * x_dagger / kT.

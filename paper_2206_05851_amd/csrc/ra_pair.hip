@@ -83,7 +83,11 @@ __device__ __forceinline__ T segment_scan(T v, int i) {
 }
 
 template <typename T, int SPRING, bool LJ>
-__device__ void run_pair(const FwdArgs& a, const GroupDev& G, int k_first, T (*xs)[4]) {
+__device__ __forceinline__ void run_pair(const FwdArgs& a, const GroupDev& Gm, int k_first, T (*xs)[4]) {
+    // the group's constants as a local value: read through the reference,
+    // the step loop re-loads them from memory every iteration
+    const GroupDev G = Gm;
+    const int gidx = (int)(&Gm - a.groups);
     const int lane = threadIdx.x & (WAVE - 1);
     const int N = G.N, nm1 = N - 1;
     const int seg = lane / N;
@@ -202,7 +206,7 @@ __device__ void run_pair(const FwdArgs& a, const GroupDev& G, int k_first, T (*x
         state[o + 2] = qz;
         if (tsf) a.tsf_acc[G.smp_off + sidx] = acc;
     }
-    flush_clamps(clamps, a.clamps + (&G - a.groups));
+    flush_clamps(clamps, a.clamps + gidx);
 }
 
 template <typename T>
