@@ -100,17 +100,31 @@ __device__ __forceinline__ void rpy_coeffs(T dx, T dy, T dz, T a, T& ci, T& cr, 
     }
 }
 
-// Cholesky D = L L^T of the packed tensor A (n = 3N rows) with the lower
-// triangle held in registers: thread (tx, ty) of the 16 x 16 grid owns rows
-// i = ty + 16a and columns j = tx + 16b (b <= a). Square-root-free right-
-// looking elimination R_ij -= R_ik R_jk / R_kk; per column k the owners of
-// column k publish it through a double-buffered LDS column (one barrier per
-// column). The block-column loop is unrolled so every register index is a
-// compile-time constant. Then L = R diag(1/sqrt(R_jj)), y = L xi by 16-lane
-// butterflies (fixed order), and Y_i = drift DF_i + nsc y_i.
+constexpr int HI_CB = 16 * 12 + 16;   // one column-exchange buffer: 16 NB rows (NB <= 12), pivot slot, pad
+
+// Drift, Cholesky factor and displacement for the packed tensor A (n = 3N rows).
+//
+// The lower triangle is loaded into registers: thread (tx, ty) of the 16 x 16
+// grid owns rows i = ty + 16a and columns j = tx + 16b (b <= a); every loop
+// over a and b is unrolled so the register indices are compile-time constants.
+//
+// Drift D F: from the registers, as row sums (reduced over tx) plus the
+// transposed contributions of the strictly lower part (reduced over ty, per
+// wavefront in registers and over the four wavefronts through LDS, in the
+// space of A, which is free once it has been loaded). Fixed order throughout.
+//
+// Factorization: square-root-free right-looking elimination R_ij -= R_ik R_jk / R_kk.
+// Per column k the owners of column k publish it through a double-buffered LDS
+// column, already masked (zero above and at k and past n) with the pivot in its
+// own slot, so the readers load without conditions and wait once; one barrier
+// per column. A non-positive pivot sets status bit 4 after the loop.
+//
+// Then L = R diag(1/sqrt(R_jj)), y = L xi by 16-lane butterflies (fixed order)
+// and Y_i = dt/kT (D F)_i + nsc y_i.
 template <typename T, int NB>
-__device__ __forceinline__ void factor_apply(const T* A, int n, int tx, int ty, T* cbuf, const T* X, const T* DF,
+__device__ __forceinline__ void factor_apply(T* A, int n, int tx, int ty, T* cbuf, const T* X, const T* F, T* DF,
                                              T* Y, T drift, T nsc, int32_t* status) {
+    constexpr int NP = 16 * NB;
     T R[NB][NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
@@ -118,43 +132,84 @@ __device__ __forceinline__ void factor_apply(const T* A, int n, int tx, int ty, 
 #pragma unroll
         for (int b = 0; b <= a; ++b) {
             const int j = tx + 16 * b;
-            R[a][b] = (T)0;
-            if (i < n && j <= i) R[a][b] = A[tri(i) + j];
+            const bool ok = i < n && j <= i;
+            const T v = A[ok ? tri(i) + j : 0];
+            R[a][b] = ok ? v : (T)0;
         }
     }
+    // drift: row part pr (all j <= i) and column part qc (j < i, transposed)
+    T fr[NB], fc[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        const T u = F[ty + 16 * a], v = F[tx + 16 * a];
+        fr[a] = ty + 16 * a < n ? u : (T)0;
+        fc[a] = tx + 16 * a < n ? v : (T)0;
+    }
+    T pr[NB], qc[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        pr[a] = (T)0;
+        qc[a] = (T)0;
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            pr[a] = fmadd(R[a][b], fc[b], pr[a]);
+            const T r = (b == a && tx == ty) ? (T)0 : R[a][b];
+            qc[b] = fmadd(r, fr[a], qc[b]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) pr[a] += __shfl_xor(pr[a], off, 16);
+        qc[a] += __shfl_xor(qc[a], 16, WAVE);
+        qc[a] += __shfl_xor(qc[a], 32, WAVE);
+    }
+    __syncthreads();   // every thread has read A: its space takes the per-wavefront column parts
+    {
+        T* colp = A + (ty >> 2) * NP;
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            if (tx == 0) DF[ty + 16 * a] = pr[a];
+            if ((ty & 3) == 0) colp[tx + 16 * a] = qc[a];
+        }
+    }
+    bool bad = false;
 #pragma unroll
     for (int bk = 0; bk < NB; ++bk) {
         for (int kb = 0; kb < 16; ++kb) {
             const int kk = 16 * bk + kb;
             if (kk >= n) break;
-            T* cb = cbuf + (kk & 1) * (16 * NB);
+            T* cb = cbuf + (kk & 1) * HI_CB;
             if (tx == kb) {
 #pragma unroll
                 for (int a = bk; a < NB; ++a) {
                     const int i = ty + 16 * a;
-                    if (i >= kk && i < n) cb[i] = R[a][bk];
+                    cb[i] = (i > kk && i < n) ? R[a][bk] : (T)0;
                 }
+                if (ty == kb) cb[NP] = R[bk][bk];
             }
             __syncthreads();
-            const T d = cb[kk];
-            if (tx == 0 && ty == 0 && !(d > (T)0)) atomicOr(status, 4);
-            const T inv = (T)1 / d;
+            const T d = cb[NP];
             T ci[NB], cj[NB];
 #pragma unroll
             for (int a = bk; a < NB; ++a) {
-                const int i = ty + 16 * a;
-                ci[a] = (T)0;
-                if (i > kk && i < n) ci[a] = cb[i] * inv;
-                const int j = tx + 16 * a;
-                cj[a] = (T)0;
-                if (j > kk && j < n) cj[a] = cb[j];
+                ci[a] = cb[ty + 16 * a];
+                cj[a] = cb[tx + 16 * a];
             }
+            bad |= !(d > (T)0);
+            const T inv = fast_rcp(d);
+#pragma unroll
+            for (int a = bk; a < NB; ++a) ci[a] *= inv;
 #pragma unroll
             for (int a = bk; a < NB; ++a)
 #pragma unroll
                 for (int b = bk; b <= a; ++b) R[a][b] = fmadd(-ci[a], cj[b], R[a][b]);
         }
     }
+    if (tx == 0 && ty == 0 && bad) atomicOr(status, 4);
     __syncthreads();
     T* dg = cbuf;   // pivots d_j
 #pragma unroll
@@ -163,16 +218,12 @@ __device__ __forceinline__ void factor_apply(const T* A, int n, int tx, int ty, 
         if (tx == ty && i < n) dg[i] = R[a][a];
     }
     __syncthreads();
-    T rs[NB], xj[NB];
+    T sx[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = tx + 16 * b;
-        rs[b] = (T)0;
-        xj[b] = (T)0;
-        if (j < n) {
-            rs[b] = (T)1 / fast_sqrt(dg[j]);
-            xj[b] = X[j];
-        }
+        const T dj = dg[j < n ? j : 0], x = X[j];
+        sx[b] = j < n ? x / fast_sqrt(dj) : (T)0;
     }
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
@@ -180,12 +231,15 @@ __device__ __forceinline__ void factor_apply(const T* A, int n, int tx, int ty, 
         T part = (T)0;
 #pragma unroll
         for (int b = 0; b <= a; ++b) {
-            const int j = tx + 16 * b;
-            if (j <= i) part = fmadd(R[a][b] * rs[b], xj[b], part);
+            const T r = (b == a && tx > ty) ? (T)0 : R[a][b];
+            part = fmadd(r, sx[b], part);
         }
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) part += __shfl_xor(part, off, 16);
-        if (tx == 0 && i < n) Y[i] = fmadd(drift, DF[i], nsc * part);
+        if (tx == 0 && i < n) {
+            const T df = DF[i] + A[i] + A[NP + i] + A[2 * NP + i] + A[3 * NP + i];
+            Y[i] = fmadd(drift, df, nsc * part);
+        }
     }
 }
 
@@ -195,13 +249,13 @@ __device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int 
     const int lane = tid & (WAVE - 1);
     const bool w0 = tid < WAVE;
     const int N = G.N, nm1 = N - 1, n = 3 * N;
-    T* A = lds;                       // packed lower triangle, tri(n) elements
-    T* P = A + tri(n);                // positions [N][4]
+    T* A = lds;                       // packed lower triangle, tri(n) elements (at least 4 x 16 NB)
+    T* P = A + (tri(n) > 64 * NB ? tri(n) : 64 * NB);   // positions [N][4]
     T* F = P + 4 * WAVE;              // forces [n]
     T* X = F + 3 * WAVE;              // normals [n]
     T* DF = X + 3 * WAVE;             // D F [n]
     T* Y = DF + 3 * WAVE;             // bead displacement without flow [n]
-    T* C = Y + 3 * WAVE;              // Cholesky column exchange, 2 x 192
+    T* C = Y + 3 * WAVE;              // Cholesky column exchange, 2 x HI_CB
     const bool bond_ok = w0 && lane < nm1;
     const bool bead_ok = w0 && lane < N;
     T* const state = (T*)a.state;
@@ -305,16 +359,8 @@ __device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int 
             }
         }
         __syncthreads();
-        // 3. drift D F from the packed tensor (the factorization below keeps D in LDS intact)
-        for (int r = tid; r < n; r += HI_THREADS) {
-            T s0 = (T)0, s1 = (T)0;
-            const T* row = A + tri(r);
-            for (int b = 0; b <= r; ++b) s0 = fmadd(row[b], F[b], s0);
-            for (int b = r + 1; b < n; ++b) s1 = fmadd(A[tri(b) + r], F[b], s1);
-            DF[r] = s0 + s1;
-        }
-        // 4-5. Cholesky in registers and the displacement Y = dt D F / kT + sqrt(2 dt) L xi
-        factor_apply<T, NB>(A, n, tx, ty, C, X, DF, Y, drift, nsc, a.status);
+        // 3-5. drift, Cholesky in registers and the displacement Y = dt D F / kT + sqrt(2 dt) L xi
+        factor_apply<T, NB>(A, n, tx, ty, C, X, F, DF, Y, drift, nsc, a.status);
         __syncthreads();
         // 6. bond update and sampling (wave 0)
         if (w0) {
@@ -385,9 +431,13 @@ __global__ __launch_bounds__(HI_THREADS) void fwd_hi_dual_kernel(FwdArgs a, FwdA
     else hi_item<T, NB>(b, (int)blockIdx.x - a.n_items, (T*)hi_lds);
 }
 
+// Register tile of the kernel instance launched for nb = ceil(3 N_max / 16).
+static int hi_nb_instance(int nb) { return nb <= 2 ? 2 : nb <= 4 ? 4 : nb <= 6 ? 6 : nb <= 8 ? 8 : nb <= 10 ? 10 : 12; }
+
 size_t hi_lds_bytes(int max_beads, int precision) {
     const int n = 3 * max_beads;
-    const size_t elems = (size_t)n * (n + 1) / 2 + 4 * WAVE + 12 * WAVE + 2 * 3 * WAVE;
+    const size_t a_elems = std::max((size_t)n * (n + 1) / 2, (size_t)64 * hi_nb_instance((n + 15) / 16));
+    const size_t elems = a_elems + 4 * WAVE + 12 * WAVE + 2 * HI_CB;
     return elems * (precision == 64 ? 8 : 4);
 }
 

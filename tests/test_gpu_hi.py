@@ -22,7 +22,7 @@ def _lds_limit():
 
 def _fits(N, precision):
     n = 3 * N
-    return (n * (n + 1) // 2 + 1024) * (8 if precision == 64 else 4) <= _lds_limit()
+    return (n * (n + 1) // 2 + 1440) * (8 if precision == 64 else 4) <= _lds_limit()
 
 
 CASES = [
