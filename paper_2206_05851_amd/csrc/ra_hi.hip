@@ -100,7 +100,9 @@ __device__ __forceinline__ void rpy_coeffs(T dx, T dy, T dz, T a, T& ci, T& cr, 
     }
 }
 
-constexpr int HI_CB = 16 * 12 + 16;   // one column-exchange buffer: 16 NB rows (NB <= 12), pivot slot, pad
+// Columns per exchange in the elimination (a panel): 4, or 2 for the FP64
+// instances with the largest register tiles (register and LDS budget).
+__host__ __device__ constexpr int hi_panel(bool fp64, int nb) { return (fp64 && nb >= 10) ? 2 : 4; }
 
 // Drift, Cholesky factor and displacement for the packed tensor A (n = 3N rows).
 //
@@ -113,11 +115,14 @@ constexpr int HI_CB = 16 * 12 + 16;   // one column-exchange buffer: 16 NB rows 
 // wavefront in registers and over the four wavefronts through LDS, in the
 // space of A, which is free once it has been loaded). Fixed order throughout.
 //
-// Factorization: square-root-free right-looking elimination R_ij -= R_ik R_jk / R_kk.
-// Per column k the owners of column k publish it through a double-buffered LDS
-// column, already masked (zero above and at k and past n) with the pivot in its
-// own slot, so the readers load without conditions and wait once; one barrier
-// per column. A non-positive pivot sets status bit 4 after the loop.
+// Factorization: square-root-free right-looking elimination R_ij -= R_ik R_jk / R_kk,
+// W columns (a panel) per exchange: the owners of the panel's columns publish
+// their raw values (all earlier panels applied) through a double-buffered LDS
+// panel, one barrier per panel; every thread then eliminates within the panel
+// the values it needs (its rows, its columns and the W x W diagonal block) in
+// the same expressions and order as the register update, so all copies of a
+// panel value are bit-identical, and applies the rank-W update to its
+// registers. A non-positive pivot sets status bit 4 after the loop.
 //
 // Then L = R diag(1/sqrt(R_jj)), y = L xi by 16-lane butterflies (fixed order)
 // and Y_i = dt/kT (D F)_i + nsc y_i.
@@ -125,6 +130,7 @@ template <typename T, int NB>
 __device__ __forceinline__ void factor_apply(T* A, int n, int tx, int ty, T* cbuf, const T* X, const T* F, T* DF,
                                              T* Y, T drift, T nsc, int32_t* status) {
     constexpr int NP = 16 * NB;
+    constexpr int W = hi_panel(sizeof(T) == 8, NB);
     T R[NB][NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
@@ -179,34 +185,70 @@ __device__ __forceinline__ void factor_apply(T* A, int n, int tx, int ty, T* cbu
     bool bad = false;
 #pragma unroll
     for (int bk = 0; bk < NB; ++bk) {
-        for (int kb = 0; kb < 16; ++kb) {
-            const int kk = 16 * bk + kb;
-            if (kk >= n) break;
-            T* cb = cbuf + (kk & 1) * HI_CB;
-            if (tx == kb) {
+        for (int kp = 0; kp < 16 / W; ++kp) {
+            const int k0 = 16 * bk + W * kp;   // panel: columns k0 .. k0 + W - 1
+            if (k0 >= n) break;
+            // 16 / W is even, so the buffers alternate across block columns too
+            T* cb = (T*)__builtin_assume_aligned(cbuf + (kp & 1) * (NP * W), 16);
+            const int own = tx - W * kp;
+            if (own >= 0 && own < W) {
 #pragma unroll
-                for (int a = bk; a < NB; ++a) {
-                    const int i = ty + 16 * a;
-                    cb[i] = (i > kk && i < n) ? R[a][bk] : (T)0;
-                }
-                if (ty == kb) cb[NP] = R[bk][bk];
+                for (int a = bk; a < NB; ++a) cb[(ty + 16 * a) * W + own] = R[a][bk];
             }
             __syncthreads();
-            const T d = cb[NP];
-            T ci[NB], cj[NB];
-#pragma unroll
-            for (int a = bk; a < NB; ++a) {
-                ci[a] = cb[ty + 16 * a];
-                cj[a] = cb[tx + 16 * a];
-            }
-            bad |= !(d > (T)0);
-            const T inv = fast_rcp(d);
-#pragma unroll
-            for (int a = bk; a < NB; ++a) ci[a] *= inv;
+            // raw panel values (all updates of earlier panels applied) at this
+            // thread's rows (ri) and columns (rj), and the W x W diagonal block
+            T ri[NB][W], rj[NB][W], D[W][W];
 #pragma unroll
             for (int a = bk; a < NB; ++a)
 #pragma unroll
-                for (int b = bk; b <= a; ++b) R[a][b] = fmadd(-ci[a], cj[b], R[a][b]);
+                for (int m = 0; m < W; ++m) {
+                    ri[a][m] = cb[(ty + 16 * a) * W + m];
+                    rj[a][m] = cb[(tx + 16 * a) * W + m];
+                }
+#pragma unroll
+            for (int l = 0; l < W; ++l)
+#pragma unroll
+                for (int m = 0; m < W; ++m) D[l][m] = cb[(k0 + l) * W + m];
+            // Eliminate within the panel, column by column, with the same
+            // expressions as the register update below (scaled row value times
+            // raw column value, accumulated in column order), so every copy of
+            // a panel value is bit-identical to its owner's register.
+            T inv[W];
+#pragma unroll
+            for (int m = 0; m < W; ++m) {
+                const bool live = k0 + m < n;
+                bad |= live && !(D[m][m] > (T)0);
+                inv[m] = live ? fast_rcp(D[m][m]) : (T)0;
+#pragma unroll
+                for (int r = m + 1; r < W; ++r) {
+                    const T c = D[r][m] * inv[m];
+#pragma unroll
+                    for (int l = m + 1; l <= r; ++l) D[r][l] = fmadd(-c, D[l][m], D[r][l]);
+                }
+#pragma unroll
+                for (int a = bk; a < NB; ++a) {
+                    ri[a][m] *= inv[m];   // from here on the scaled row value R_im / d_m
+                    const T cjm = rj[a][m] * inv[m];
+#pragma unroll
+                    for (int l = m + 1; l < W; ++l) {
+                        ri[a][l] = fmadd(-ri[a][m], D[l][m], ri[a][l]);
+                        rj[a][l] = fmadd(-cjm, D[l][m], rj[a][l]);
+                    }
+                }
+            }
+            // rows and columns at or above each panel column take no update
+#pragma unroll
+            for (int m = 0; m < W; ++m) {
+                if (ty <= W * kp + m) ri[bk][m] = (T)0;
+                if (tx <= W * kp + m) rj[bk][m] = (T)0;
+            }
+#pragma unroll
+            for (int a = bk; a < NB; ++a)
+#pragma unroll
+                for (int b = bk; b <= a; ++b)
+#pragma unroll
+                    for (int m = 0; m < W; ++m) R[a][b] = fmadd(-ri[a][m], rj[b][m], R[a][b]);
         }
     }
     if (tx == 0 && ty == 0 && bad) atomicOr(status, 4);
@@ -250,12 +292,13 @@ __device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int 
     const bool w0 = tid < WAVE;
     const int N = G.N, nm1 = N - 1, n = 3 * N;
     T* A = lds;                       // packed lower triangle, tri(n) elements (at least 4 x 16 NB)
-    T* P = A + (tri(n) > 64 * NB ? tri(n) : 64 * NB);   // positions [N][4]
+    // region offsets are multiples of 4 elements (16-byte aligned panel rows)
+    T* P = A + (((tri(n) > 64 * NB ? tri(n) : 64 * NB) + 3) & ~3);   // positions [N][4]
     T* F = P + 4 * WAVE;              // forces [n]
     T* X = F + 3 * WAVE;              // normals [n]
     T* DF = X + 3 * WAVE;             // D F [n]
     T* Y = DF + 3 * WAVE;             // bead displacement without flow [n]
-    T* C = Y + 3 * WAVE;              // Cholesky column exchange, 2 x HI_CB
+    T* C = Y + 3 * WAVE;              // Cholesky panel exchange, 2 x 16 NB x panel width
     const bool bond_ok = w0 && lane < nm1;
     const bool bead_ok = w0 && lane < N;
     T* const state = (T*)a.state;
@@ -436,8 +479,9 @@ static int hi_nb_instance(int nb) { return nb <= 2 ? 2 : nb <= 4 ? 4 : nb <= 6 ?
 
 size_t hi_lds_bytes(int max_beads, int precision) {
     const int n = 3 * max_beads;
-    const size_t a_elems = std::max((size_t)n * (n + 1) / 2, (size_t)64 * hi_nb_instance((n + 15) / 16));
-    const size_t elems = a_elems + 4 * WAVE + 12 * WAVE + 2 * HI_CB;
+    const size_t a_elems = (std::max((size_t)n * (n + 1) / 2, (size_t)64 * hi_nb_instance((n + 15) / 16)) + 3) & ~(size_t)3;
+    const int nbi = hi_nb_instance((n + 15) / 16);
+    const size_t elems = a_elems + 4 * WAVE + 12 * WAVE + (size_t)2 * 16 * nbi * hi_panel(precision == 64, nbi);
     return elems * (precision == 64 ? 8 : 4);
 }
 

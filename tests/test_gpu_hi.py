@@ -21,8 +21,13 @@ def _lds_limit():
 
 
 def _fits(N, precision):
+    # packed tensor (at least the drift partials 4 x 16 NB), positions, forces,
+    # normals, drift, displacement, and the double-buffered elimination panel
     n = 3 * N
-    return (n * (n + 1) // 2 + 1440) * (8 if precision == 64 else 4) <= _lds_limit()
+    nb = next(b for b in (2, 4, 6, 8, 10, 12) if 16 * b >= n)
+    width = 2 if (precision == 64 and nb >= 10) else 4
+    elems = max(n * (n + 1) // 2, 64 * nb) + 16 * 64 + 2 * 16 * nb * width
+    return elems * (8 if precision == 64 else 4) <= _lds_limit()
 
 
 CASES = [
@@ -31,6 +36,8 @@ CASES = [
                                                 rest_length=2.0, lj_eps=1.0, lj_rmin=2.0, hi_radius=1.0), 1e-5),
     ("FENE N=50 uniaxial", lambda: wl.group(50, 3, 1e-4, wl.FENE, 1.0, 100.0, wl.UNIAXIAL, 0.05, hi_radius=0.4),
      1e-4),
+    ("Hookean N=64 planar, largest tile", lambda: wl.group(64, 2, 1e-3, wl.HOOKEAN, 1.0, 0.0, wl.PLANAR, 0.2,
+                                                           hi_radius=0.3), 1e-3),
 ]
 
 
