@@ -366,7 +366,7 @@ __device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int 
     const int n_steps = (int)a.n_steps;
     for (int st = 0; st < n_steps; ++st) {
         const uint32_t nstep = n0 + (uint32_t)st;
-        // 1. positions, forces, noise (wave 0)
+        // 1. positions, spring forces, noise (wave 0)
         if (w0) {
             const T px = wave_scan_incl(qx) - qx;
             const T py = wave_scan_incl(qy) - qy;
@@ -376,29 +376,10 @@ __device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int 
             P[4 * lane + 2] = pz;
             T gx, gy, gz;
             hi_spring(qx, qy, qz, G, gx, gy, gz, clamps);
-            T fx = gx - from_prev_lane(gx), fy = gy - from_prev_lane(gy), fz = gz - from_prev_lane(gz);
-            if (lj) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                for (int j = 0; j < N; ++j) {
-                    const T dx = px - P[4 * j], dy = py - P[4 * j + 1], dz = pz - P[4 * j + 2];
-                    const int dj = j - lane;
-                    const bool use = bead_ok && (dj >= 2 || dj <= -2);
-                    const T r2 = use ? fmadd(dx, dx, fmadd(dy, dy, dz * dz)) : (T)1;
-                    const T inv = fast_rcp(r2);
-                    const T s1 = ljr2 * inv;
-                    const T s3 = s1 * s1 * s1;
-                    const T cc = use ? lj12u * inv * fmadd(s3, s3, -s3) : (T)0;
-                    fx = fmadd(cc, dx, fx);
-                    fy = fmadd(cc, dy, fy);
-                    fz = fmadd(cc, dz, fz);
-                }
-            }
             if (bead_ok) {
-                F[3 * lane] = fx;
-                F[3 * lane + 1] = fy;
-                F[3 * lane + 2] = fz;
+                F[3 * lane] = gx - from_prev_lane(gx);
+                F[3 * lane + 1] = gy - from_prev_lane(gy);
+                F[3 * lane + 2] = gz - from_prev_lane(gz);
                 T ex, ey, ez;
                 normals3(philox10(nstep, (uint32_t)lane, (uint32_t)k, G.stream, keys), ex, ey, ez);
                 X[3 * lane] = ex;
@@ -407,6 +388,36 @@ __device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int 
             }
         }
         __syncthreads();
+        // LJ between non-adjacent beads: wavefront v sums over the beads j of
+        // its quarter of the chain for every bead i (lane), into its own rows
+        // of the (not yet used) panel buffer
+        if (lj) {
+            const int wv = tid >> 6;
+            const int q = (N + 3) >> 2;
+            const int j0 = wv * q, j1 = j0 + q < N ? j0 + q : N;
+            const bool mine = lane < N;
+            const T px = P[4 * lane], py = P[4 * lane + 1], pz = P[4 * lane + 2];
+            T fx = (T)0, fy = (T)0, fz = (T)0;
+            for (int j = j0; j < j1; ++j) {
+                const T dx = px - P[4 * j], dy = py - P[4 * j + 1], dz = pz - P[4 * j + 2];
+                const int dj = j - lane;
+                const bool use = mine && (dj >= 2 || dj <= -2);
+                const T r2 = use ? fmadd(dx, dx, fmadd(dy, dy, dz * dz)) : (T)1;
+                const T inv = fast_rcp(r2);
+                const T s1 = ljr2 * inv;
+                const T s3 = s1 * s1 * s1;
+                const T cc = use ? lj12u * inv * fmadd(s3, s3, -s3) : (T)0;
+                fx = fmadd(cc, dx, fx);
+                fy = fmadd(cc, dy, fy);
+                fz = fmadd(cc, dz, fz);
+            }
+            if (mine) {
+                T* fl = C + wv * n + 3 * lane;
+                fl[0] = fx;
+                fl[1] = fy;
+                fl[2] = fz;
+            }
+        }
         // 2. D: one pair (i >= j) at a time, its 3x3 block (lower part on the diagonal)
         const int n_pairs = tri(N);
         for (int p = tid; p < n_pairs; p += HI_THREADS) {
@@ -436,6 +447,17 @@ __device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int 
             }
         }
         __syncthreads();
+        if (lj) {
+            // total force: springs + the four LJ partial sums in fixed order
+            if (bead_ok) {
+#pragma unroll
+                for (int c3 = 0; c3 < 3; ++c3) {
+                    const int r = 3 * lane + c3;
+                    F[r] += ((C[r] + C[n + r]) + C[2 * n + r]) + C[3 * n + r];
+                }
+            }
+            __syncthreads();
+        }
         // 3-5. drift, Cholesky in registers and the displacement Y = dt D F / kT + sqrt(2 dt) L xi
         factor_apply<T, NB>(A, n, tx, ty, C, X, F, DF, Y, drift, nsc, a.status);
         __syncthreads();
