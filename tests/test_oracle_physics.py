@@ -135,6 +135,29 @@ def test_hookean_dumbbell_variance():
     assert abs(q2.mean() - expect) < 4.5 * q2.std() / np.sqrt(R)
 
 
+def test_em_weak_order_one_hookean_dumbbell():
+    # Euler-Maruyama is weakly first order: the stationary bias of <Q^2> about
+    # the continuous 3 kT/H halves when dt halves. The EM-exact biases give the
+    # ratio [1/(1 - 0.08) - 1] / [1/(1 - 0.04) - 1] = 2.087 (1 would mean no
+    # convergence, 4 second order). Estimated from the oracle's tension
+    # samples f = H |Q| over 10 decorrelated windows of 8000 replicas each.
+    H, R = 1.0, 8000
+    parent = np.array([[0.0, 0.0, 0.0], [0.3, 0.0, 0.0]])
+    bias, se = [], []
+    for dt, S in ((0.08, 25), (0.04, 50)):
+        o = ora.Oracle([g(2, R, dt, H=H)], seed=31, sample_every=S, max_windows=12)
+        o.init_chains([parent])
+        o.step(12 * S)        # windows 2 time units = 8 relaxation times zeta/4H apart
+        q2 = (o.samples()[0][2:, :, 0] / H) ** 2
+        bias.append(q2.mean() - 3.0 / H)
+        se.append(q2.std() / np.sqrt(q2.size))
+    ratio = bias[0] / bias[1]
+    ratio_se = ratio * np.hypot(se[0] / bias[0], se[1] / bias[1])
+    expect = (1.0 / (1.0 - 0.08) - 1.0) / (1.0 / (1.0 - 0.04) - 1.0)
+    assert abs(ratio - expect) < 4.0 * ratio_se, (ratio, ratio_se)
+    assert abs(ratio - 1.0) > 4.0 * ratio_se and abs(ratio - 4.0) > 4.0 * ratio_se
+
+
 def test_fene_dumbbell_equilibrium_q2():
     # <Q^2> = 3 (kT/H) b/(b+5) for the FENE dumbbell; EM bias O(dt) << SE here
     R, dt, H, b = 8000, 1e-3, 1.0, 10.0
