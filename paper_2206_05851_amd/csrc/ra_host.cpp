@@ -495,8 +495,7 @@ static ra_status enqueue_forward_dual(ra_ctx* ca, int64_t n_a, ra_ctx* cb, int64
     else if (ca->family == 3)
         HIPCHK(ca, launch_forward_hi_dual(a, b, ca->run.precision, std::max(ca->hi_nmax, cb->hi_nmax), st));
     else HIPCHK(ca, launch_forward_dual(a, b, ca->run.precision, ca->family, ca->wpb, st));
-    HIPCHK(ca, launch_advance(ca->dstep, n_a, st));
-    HIPCHK(ca, launch_advance(cb->dstep, n_b, st));
+    HIPCHK(ca, launch_advance2(ca->dstep, n_a, cb->dstep, n_b, st));
     return RA_OK;
 }
 
@@ -671,11 +670,9 @@ ra_status ra_reclone(ra_ctx* c, const ra_ctx* parent) {
     if (c->step % c->run.sample_every != 0)
         return fail(c, RA_EINVAL, "re-clone only at a window boundary (step count a multiple of S)");
     const int ng = (int)c->hgroups.size();
+    // one launch: replica states, clone source, and the device step counter
     HIPCHK(c, launch_reclone(c->dgroups, parent->dgroups, ng, c->max_group_elems, parent->state, c->state, c->tsf_acc,
-                             c->status, c->run.precision, c->stream));
-    HIPCHK(c, launch_src_from_bonds(c->dgroups, parent->dgroups, ng, parent->state, c->dpar_off, c->src,
-                                    c->run.precision, c->stream));
-    HIPCHK(c, launch_set_step(c->dstep, c->step, c->stream));
+                             c->status, c->dpar_off, c->src, c->dstep, c->step, c->run.precision, c->stream));
     c->initialised = true;
     c->recloned = true;
     return RA_OK;

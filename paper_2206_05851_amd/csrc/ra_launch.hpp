@@ -90,13 +90,11 @@ hipError_t launch_forward_hi(const FwdArgs& a, int precision, int max_beads, hip
 
 // RSF cycle and estimators (ra_rsf.hip)
 hipError_t launch_reclone(const GroupDev* groups, const GroupDev* pgroups, int n_groups, int64_t max_elems,
-                          const void* pstate, void* state, double* tsf_acc, int32_t* status, int precision,
-                          hipStream_t st);
-hipError_t launch_set_step(int64_t* step, int64_t value, hipStream_t st);
+                          const void* pstate, void* state, double* tsf_acc, int32_t* status, const int64_t* par_off,
+                          double* src, int64_t* step, int64_t step_value, int precision, hipStream_t st);
+hipError_t launch_advance2(int64_t* a, int64_t na, int64_t* b, int64_t nb, hipStream_t st);
 hipError_t launch_src_from_xyz(const GroupDev* groups, int n_groups, const double* parent, const int64_t* par_off,
                                double* src, hipStream_t st);
-hipError_t launch_src_from_bonds(const GroupDev* groups, const GroupDev* pgroups, int n_groups, const void* pstate,
-                                 const int64_t* par_off, double* src, int precision, hipStream_t st);
 hipError_t launch_conformation(const GroupDev* groups, int n_groups, const int64_t* rep_off, int64_t n_reps,
                                const void* state, const int64_t* par_off, const double* src, double* dbar,
                                double* d_bead, double* rg2, double* src_rg2, int precision, hipStream_t st);

@@ -15,43 +15,6 @@
 namespace ra {
 
 // ---------------------------------------------------------------------------
-// Re-clone: state of every replica of group g := replica 0 of the parent
-// context's group g. A FENE bond at or past full extension (or non-finite)
-// marks the parent invalid (status bit 1), as at the first clone.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void reclone_kernel(const GroupDev* __restrict__ groups, const GroupDev* __restrict__ pgroups,
-                               const T* __restrict__ pstate, T* __restrict__ state,
-                               double* __restrict__ tsf_acc, int32_t* status) {
-    const GroupDev& G = groups[blockIdx.y];
-    const GroupDev& PG = pgroups[blockIdx.y];
-    const int nm1 = G.N - 1;
-    const int64_t total = (int64_t)G.R * nm1;
-    const T* p = pstate + PG.state_off;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = e / nm1;
-        const int j = (int)(e - k * nm1);
-        const T qx = p[3 * j], qy = p[3 * j + 1], qz = p[3 * j + 2];
-        if (k == 0) {
-            const double x = qx, y = qy, z = qz;
-            bool bad = !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z));
-            if (G.spring == 1 && !((x * x + y * y + z * z) * G.inv_q0sq_d < 1.0)) bad = true;
-            if (bad) atomicOr(status, 1);
-        }
-        const int64_t o = G.state_off + e * 3;
-        state[o] = qx;
-        state[o + 1] = qy;
-        state[o + 2] = qz;
-        if (tsf_acc) tsf_acc[G.smp_off + e] = 0.0;
-    }
-}
-
-__global__ void set_step_kernel(int64_t* step, int64_t value) {
-    if (threadIdx.x == 0) step[0] = value;
-}
-
-// ---------------------------------------------------------------------------
 // Wave helpers (FP64): fixed-shape butterfly sum and an inclusive Hillis-Steele
 // scan over the 64 lanes.
 // ---------------------------------------------------------------------------
@@ -135,15 +98,52 @@ __global__ __launch_bounds__(64) void src_from_xyz_kernel(const GroupDev* __rest
     }
 }
 
-// Clone source from the parent context's bonds (replica 0 of each group).
+// ---------------------------------------------------------------------------
+// Re-clone: state of every replica of group g := replica 0 of the parent
+// context's group g. A FENE bond at or past full extension (or non-finite)
+// marks the parent invalid (status bit 1), as at the first clone. In the same
+// launch: the first wave of block (0, g) writes group g's clone source (the
+// parent's beads in its centre-of-mass frame, for Eq. 5), and one thread sets
+// the replicas' device step counter to the window start.
+// ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(64) void src_from_bonds_kernel(const GroupDev* __restrict__ groups,
-                                                            const GroupDev* __restrict__ pgroups,
-                                                            const T* __restrict__ pstate,
-                                                            const int64_t* __restrict__ par_off,
-                                                            double* __restrict__ src) {
-    const GroupDev& G = groups[blockIdx.x];
-    com_frame_from_bonds<T>(pstate + pgroups[blockIdx.x].state_off, G.N, src + par_off[blockIdx.x], threadIdx.x);
+__global__ void reclone_kernel(const GroupDev* __restrict__ groups, const GroupDev* __restrict__ pgroups,
+                               const T* __restrict__ pstate, T* __restrict__ state,
+                               double* __restrict__ tsf_acc, int32_t* status, const int64_t* __restrict__ par_off,
+                               double* __restrict__ src, int64_t* step, int64_t step_value) {
+    const GroupDev& G = groups[blockIdx.y];
+    const GroupDev& PG = pgroups[blockIdx.y];
+    const int nm1 = G.N - 1;
+    const int64_t total = (int64_t)G.R * nm1;
+    const T* p = pstate + PG.state_off;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / nm1;
+        const int j = (int)(e - k * nm1);
+        const T qx = p[3 * j], qy = p[3 * j + 1], qz = p[3 * j + 2];
+        if (k == 0) {
+            const double x = qx, y = qy, z = qz;
+            bool bad = !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z));
+            if (G.spring == 1 && !((x * x + y * y + z * z) * G.inv_q0sq_d < 1.0)) bad = true;
+            if (bad) atomicOr(status, 1);
+        }
+        const int64_t o = G.state_off + e * 3;
+        state[o] = qx;
+        state[o + 1] = qy;
+        state[o + 2] = qz;
+        if (tsf_acc) tsf_acc[G.smp_off + e] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < WAVE)
+        com_frame_from_bonds<T>(p, G.N, src + par_off[blockIdx.y], (int)threadIdx.x);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) step[0] = step_value;
+}
+
+// Both step counters of a dual launch advance in one kernel.
+__global__ void advance2_kernel(int64_t* a, int64_t na, int64_t* b, int64_t nb) {
+    if (threadIdx.x == 0) {
+        a[0] += na;
+        b[0] += nb;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -285,23 +285,23 @@ __global__ __launch_bounds__(64) void mftu_kernel(const double* __restrict__ rat
 // Launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_reclone(const GroupDev* groups, const GroupDev* pgroups, int n_groups, int64_t max_elems,
-                          const void* pstate, void* state, double* tsf_acc, int32_t* status, int precision,
-                          hipStream_t st) {
+                          const void* pstate, void* state, double* tsf_acc, int32_t* status, const int64_t* par_off,
+                          double* src, int64_t* step, int64_t step_value, int precision, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     const int64_t blocks = std::min<int64_t>(1024, (max_elems + 255) / 256);
     dim3 grid((unsigned)std::max<int64_t>(1, blocks), (unsigned)n_groups), block(256);
     if (precision == 64)
         hipLaunchKernelGGL(reclone_kernel<double>, grid, block, 0, st, groups, pgroups, (const double*)pstate,
-                           (double*)state, tsf_acc, status);
+                           (double*)state, tsf_acc, status, par_off, src, step, step_value);
     else
         hipLaunchKernelGGL(reclone_kernel<float>, grid, block, 0, st, groups, pgroups, (const float*)pstate,
-                           (float*)state, tsf_acc, status);
+                           (float*)state, tsf_acc, status, par_off, src, step, step_value);
     return hipGetLastError();
 }
 
-hipError_t launch_set_step(int64_t* step, int64_t value, hipStream_t st) {
+hipError_t launch_advance2(int64_t* a, int64_t na, int64_t* b, int64_t nb, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
-    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, st, step, value);
+    hipLaunchKernelGGL(advance2_kernel, dim3(1), dim3(64), 0, st, a, na, b, nb);
     return hipGetLastError();
 }
 
@@ -309,18 +309,6 @@ hipError_t launch_src_from_xyz(const GroupDev* groups, int n_groups, const doubl
                                double* src, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     hipLaunchKernelGGL(src_from_xyz_kernel, dim3((unsigned)n_groups), dim3(64), 0, st, groups, parent, par_off, src);
-    return hipGetLastError();
-}
-
-hipError_t launch_src_from_bonds(const GroupDev* groups, const GroupDev* pgroups, int n_groups, const void* pstate,
-                                 const int64_t* par_off, double* src, int precision, hipStream_t st) {
-    (void)hipGetLastError();   // report only this launch's own error
-    if (precision == 64)
-        hipLaunchKernelGGL(src_from_bonds_kernel<double>, dim3((unsigned)n_groups), dim3(64), 0, st, groups, pgroups,
-                           (const double*)pstate, par_off, src);
-    else
-        hipLaunchKernelGGL(src_from_bonds_kernel<float>, dim3((unsigned)n_groups), dim3(64), 0, st, groups, pgroups,
-                           (const float*)pstate, par_off, src);
     return hipGetLastError();
 }
 
