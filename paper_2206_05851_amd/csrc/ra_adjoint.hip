@@ -30,17 +30,20 @@ __device__ __forceinline__ void factor_gs(float qx, float qy, float qz, const Gr
     } else {
         const float q2 = fmadd(qx, qx, fmadd(qy, qy, qz * qz));
         const float sf = q2 * G.inv_q0sq;
-        if (sf > FENE_FP64_BAND) {
-            const double dx = qx, dy = qy, dz = qz;
-            double sd = (dx * dx + dy * dy + dz * dz) * G.inv_q0sq_d;
-            smooth = !(sd > 1.0 - FENE_DELTA);
-            if (!smooth) sd = 1.0 - FENE_DELTA;
-            g = (float)(1.0 / (1.0 - sd));
-            s = (float)sd;
-        } else {
-            g = fast_rcp(1.0f - sf);
-            s = sf;
-            smooth = true;
+        g = fast_rcp(1.0f - sf);
+        s = sf;
+        smooth = true;
+        // wave vote, as in the forward step: the FP64 recomputation runs only
+        // in wavefronts where some lane is near full extension
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(sf > FENE_FP64_BAND) != 0, 0)) {
+            if (sf > FENE_FP64_BAND) {
+                const double dx = qx, dy = qy, dz = qz;
+                double sd = (dx * dx + dy * dy + dz * dz) * G.inv_q0sq_d;
+                smooth = !(sd > 1.0 - FENE_DELTA);
+                if (!smooth) sd = 1.0 - FENE_DELTA;
+                g = (float)(1.0 / (1.0 - sd));
+                s = (float)sd;
+            }
         }
     }
 }
@@ -107,6 +110,7 @@ __device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const bool
     else if (G.flow == 2) { px = dt; py = -dt; }
     else if (G.flow == 3) { pxz = dt; }
     const float dtz = (float)(G.dt / G.zeta);
+    const float inv_b = FENE ? 1.0f / (float)G.b : 0.0f;
     const float plx = from_prev_lane(lx[M - 1]), ply = from_prev_lane(ly[M - 1]), plz = from_prev_lane(lz[M - 1]);
     const float nlx = from_next_lane(lx[0]), nly = from_next_lane(ly[0]), nlz = from_next_lane(lz[0]);
     float ux[M], uy[M], uz[M];
@@ -132,7 +136,7 @@ __device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const bool
         gr += fmadd(lx[m], fmadd(px, Qx, pxz * Qz), fmadd(ly[m], py * Qy, lz[m] * pz * Qz));
         const float muQ = fmadd(ux[m], Qx, fmadd(uy[m], Qy, uz[m] * Qz));
         const float wH = (FENE && smooth) ? dtz * g * fmadd(g, s, 1.0f) : dtz * g;
-        const float wb = (FENE && smooth) ? -cF * g * g * (s / (float)G.b) : 0.0f;
+        const float wb = (FENE && smooth) ? -cF * g * g * (s * inv_b) : 0.0f;
         gH = fmadd(wH, muQ, gH);
         gb = fmadd(wb, muQ, gb);
         // lambda^n = lambda + (dt kappa)^T lambda + cF J mu
