@@ -107,3 +107,39 @@ def test_hi_rsf_cycle_matches_oracle():
     e = [rel_err(isf, oisf, 1.0), rel_err(tsf, otsf, 1.0), rel_err(rsf, orsf, 1.0)]
     announce("hi rsf: " + " ".join("%.1e" % x for x in e))
     assert max(e) < 1e-4
+
+
+def test_hi_full_size_hi50_first_window_per_replica():
+    # The hi50 workload in full (the paper's model with HI: 50 replicas and the
+    # parent, 4 windows of 750 steps), launched as bench.py runs it (parent on
+    # its own stream, graphs on); the oracle replays the parent and replicas
+    # 0..1 of the first window with the same counters.
+    import torch
+    from oracle import ora
+    from paper_2206_05851_amd import ra
+    groups, parents, run = wl.hi50()
+    g = groups[0]
+    S, P, W = run["sample_every"], run["parent_steps"], run["n_windows"]
+    announce("hi50 full size")
+    pstream = torch.cuda.Stream()
+    par = ra.Replicas([dict(g, n_replicas=1)], run["seed"], sample_every=P, max_windows=W, tsf=True, noise_tag=1,
+                      stream=pstream, use_graph=True)
+    par.init_chains(parents)
+    rep = ra.Replicas(groups, run["seed"], sample_every=S, max_windows=W, use_graph=True)
+    rep.rsf_cycle(par, W, P)
+    smp = rep.samples()[0].cpu().numpy()
+    psmp = par.samples()[0].cpu().numpy()
+    par.sync_status()
+    rep.sync_status()
+    assert rep.kernel_family() == 3
+    assert np.all(np.isfinite(smp)) and smp.shape == (W, 50, 49)
+    op = ora.Oracle([dict(g, n_replicas=1)], run["seed"], P, 1, tsf=True)
+    op.set_tag(ora.TAG_PARENT)
+    op.init_chains(parents)
+    orr = ora.Oracle(groups, run["seed"], S, 1)
+    orr.set_replicas(0, 0, 2)
+    orr.rsf_cycle(op, 1, P)
+    fl = float(np.sqrt(g["H"] * g["kT"]))
+    e = [rel_err(psmp[0], op.samples()[0][0], fl), rel_err(smp[0, :2], orr.samples()[0][0], fl)]
+    announce("hi50 window 0: parent rel err %.2e, replicas 0-1 rel err %.2e" % tuple(e))
+    assert max(e) < 1e-4

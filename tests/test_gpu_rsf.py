@@ -168,3 +168,39 @@ def test_reclone_and_cycle_errors():
     rep.step(10)
     rep.backward(mean[:1].contiguous(), torch.zeros_like(mean[:1]))
     rep.sync_status()
+
+
+def test_rsf50_full_size_first_window_per_replica():
+    # The rsf50 workload in full (FENE N=50 in shear at Wi=50, the parent and
+    # 1000 replicas, 20 windows of 750 steps), launched as bench.py runs it
+    # (parent on its own stream, graphs on, dual launches); the oracle replays
+    # the parent's first two windows and replicas 0..3 of the first window.
+    import torch
+    from oracle import ora
+    from paper_2206_05851_amd import ra
+    groups, parents, run = wl.rsf50()
+    g = groups[0]
+    S, P, W = run["sample_every"], run["parent_steps"], run["n_windows"]
+    announce("rsf50 full size")
+    pstream = torch.cuda.Stream()
+    par = ra.Replicas([dict(g, n_replicas=1)], run["seed"], sample_every=P, max_windows=W, tsf=True, noise_tag=1,
+                      stream=pstream, use_graph=True)
+    par.init_chains(parents)
+    rep = ra.Replicas(groups, run["seed"], sample_every=S, max_windows=W, use_graph=True)
+    rep.rsf_cycle(par, W, P)
+    smp = rep.samples()[0].cpu().numpy()
+    psmp, ptsf = [t[0].cpu().numpy() for t in par.samples(tsf=True)]
+    par.sync_status()
+    rep.sync_status()
+    assert np.all(np.isfinite(smp)) and smp.shape == (W, 1000, 49)
+    op = ora.Oracle([dict(g, n_replicas=1)], run["seed"], P, 2, tsf=True)
+    op.set_tag(ora.TAG_PARENT)
+    op.init_chains(parents)
+    orr = ora.Oracle(groups, run["seed"], S, 2)
+    orr.set_replicas(0, 0, 4)
+    orr.rsf_cycle(op, 2, P)
+    osmp, otsf = op.samples(tsf=True)
+    e = [rel_err(psmp[:2], osmp[0], 1.0), rel_err(ptsf[:2], otsf[0], 1.0),
+         rel_err(smp[:2, :4], orr.samples()[0], 1.0)]
+    announce("rsf50 windows 0-1: parent %.2e, parent TSF %.2e, replicas 0-3 %.2e" % tuple(e))
+    assert max(e) < 1e-4
