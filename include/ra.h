@@ -50,6 +50,8 @@ extern "C" {
 
 typedef struct ra_ctx ra_ctx;
 
+#define RA_CKPT_AUTO (-1)   /* ra_run_desc.checkpoint_every: choose the interval (see there) */
+
 typedef enum {
     RA_OK = 0,
     RA_EINVAL = -1,     /* invalid argument or descriptor; nothing changed */
@@ -108,7 +110,10 @@ typedef struct {
     int32_t  sample_every;      /* S >= 1: sample after every S-th step */
     int32_t  max_windows;       /* capacity of the per-replica sample store */
     int32_t  tsf;               /* 1: also keep per-replica window time averages */
-    int32_t  checkpoint_every;  /* K > 0 enables ra_backward (precision 32 only) */
+    int32_t  checkpoint_every;  /* K > 0 enables ra_backward (precision 32 only), keeping the
+                                   state every K steps; RA_CKPT_AUTO: every step when the
+                                   trajectory, (max_steps + 1) states, fits in a quarter of
+                                   the free device memory, else every ceil(sqrt(max_steps)) */
     int32_t  max_steps;         /* steps since ra_init_chains the checkpoints must hold */
     int32_t  plain;             /* 1: plain path, one launch per step, state in HBM */
     int32_t  use_graph;         /* 1: capture ra_step's launch sequence in a hipGraph */
@@ -162,7 +167,8 @@ RA_API ra_status ra_bell_rates(ra_ctx* ctx, const double* mean, int64_t n_window
  * with respect to (rate, H, b) of every group, through all steps since init.
  * mean: the profile from ra_average_forces (device, used for the rates term);
  * grad_rates may be NULL; grad_params: device FP64 [n_groups][3]. Needs
- * checkpoint_every > 0; replays each K-step segment from its checkpoint.
+ * checkpoint_every != 0; replays each K-step segment from its checkpoint
+ * (with K = 1 it reads every state and recomputes only the last step).
  * FENE springs on the guard are treated as having ds = 0. */
 RA_API ra_status ra_backward(ra_ctx* ctx, const double* mean, const double* grad_mean,
                              const double* grad_rates, double k0, double x_dagger,
@@ -241,6 +247,11 @@ RA_API ra_status ra_get_bonds(ra_ctx* ctx, double* out);
  * pair-interaction kernel (one bead per lane; LJ and rest-length springs),
  * 3 = hydrodynamic-interaction kernel (one workgroup per replica), 4 = 1-4
  * beads per lane, 16 = 6-16 beads per lane, 0 = plain path. */
+/* The checkpoint interval in use (RA_CKPT_AUTO resolved at ra_create; 0 when
+ * the context keeps no checkpoints). With an interval of 1 ra_backward reads
+ * every step's state instead of recomputing it. */
+RA_API ra_status ra_checkpoint_interval(ra_ctx* ctx, int32_t* steps);
+
 RA_API ra_status ra_tile_info(ra_ctx* ctx, int32_t* beads_per_lane, int32_t* replicas_per_wave,
                               int32_t* kernel_family);
 

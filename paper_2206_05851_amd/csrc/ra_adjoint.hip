@@ -182,7 +182,39 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
     constexpr int STRIDE = M * 3 * WAVE;      // floats per stored state
     const AdjArgs* ap = &a;                   // for inject(); not touched in the step loops
     const int n_seg = (int)((n_end + K - 1) / K);
-    for (int sgi = n_seg - 1; sgi >= 0; --sgi) {
+    if (K == 1 && n_end > 0) {
+        // Every state is a checkpoint: no recompute. The state after the last
+        // step is rebuilt by one step from the last checkpoint; the sweep then
+        // reads Q^n from checkpoint n (one step ahead), in the same order and
+        // expressions as the segment loop below with segments of one step.
+        const float* cp = ckpt + (int64_t)(n_end - 1) * state_total;
+        load_lane<float, M>(qn, valid, cp, G, tg);
+        kc = slot_coef<float, M>(G, valid);
+        s = qn;
+        em_step<float, M, FENE>(s, G, valid, kc, (uint32_t)(n_end - 1), (uint32_t)tg.j0, (uint32_t)tg.k, keys, dummy);
+        int rr = (int)(n_end % S);
+        int w = (int)(n_end / S) - 1;
+        for (int n = (int)n_end - 1; n >= 0; --n) {
+            q = qn;
+            cp -= state_total;
+            if (n > 0) load_lane<float, M>(qn, valid, cp, G, tg);
+            if (rr == 0) {
+                double dH = 0.0, db = 0.0;
+                inject<M, FENE>(s, valid, G, *ap, tg, w, lx, ly, lz, dH, db);
+                gH += dH;
+                gb += db;
+                --w;
+            }
+            float pr = 0.0f, pH = 0.0f, pb = 0.0f;
+            reverse_step<M, FENE>(q, valid, G, lx, ly, lz, pr, pH, pb);
+            gr += (double)pr;
+            gH += (double)pH;
+            gb += (double)pb;
+            s = q;
+            rr = rr == 0 ? S - 1 : rr - 1;
+        }
+    }
+    for (int sgi = (K == 1 && n_end > 0) ? -1 : n_seg - 1; sgi >= 0; --sgi) {
         const int s0 = sgi * K;
         const int s1 = (int)min(n_end, (int64_t)s0 + K);
         load_lane<float, M>(s, valid, ckpt + (int64_t)sgi * state_total, G, tg);

@@ -97,12 +97,12 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
     if (!g || n < 1 || !r) { why = "null descriptor or n_groups < 1"; return RA_EINVAL; }
     if (r->precision != 32 && r->precision != 64) { why = "precision must be 32 or 64"; return RA_EINVAL; }
     if (r->sample_every < 1) { why = "sample_every must be >= 1"; return RA_EINVAL; }
-    if (r->max_windows < 0 || r->checkpoint_every < 0 || r->max_steps < 0 || r->waves_per_block < 0) {
+    if (r->max_windows < 0 || r->checkpoint_every < RA_CKPT_AUTO || r->max_steps < 0 || r->waves_per_block < 0) {
         why = "negative capacity";
         return RA_EINVAL;
     }
-    if (r->checkpoint_every > 0 && (r->precision != 32 || r->plain)) {
-        why = "the adjoint (checkpoint_every > 0) needs precision 32 and the fused path";
+    if (r->checkpoint_every != 0 && (r->precision != 32 || r->plain)) {
+        why = "the adjoint (checkpoint_every != 0) needs precision 32 and the fused path";
         return RA_EINVAL;
     }
     if (r->noise_tag != 0 && r->noise_tag != 1) { why = "noise_tag must be 0 or 1"; return RA_EINVAL; }
@@ -124,7 +124,7 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
               "hydrodynamic-interaction groups (hi_radius > 0), or only chain-model groups";
         return RA_EINVAL;
     }
-    if ((n_pair > 0 || n_hi > 0) && r->checkpoint_every > 0) {
+    if ((n_pair > 0 || n_hi > 0) && r->checkpoint_every != 0) {
         why = "the adjoint covers the free-draining Hookean and FENE chain model only";
         return RA_EINVAL;
     }
@@ -350,6 +350,16 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     }
 
     const size_t esz = run->precision == 64 ? 8 : 4;
+    if (c->run.checkpoint_every == RA_CKPT_AUTO) {
+        // every state when the whole trajectory fits in a quarter of the free
+        // device memory (the backward then recomputes nothing), else the
+        // interval that minimises checkpoints + segment buffer, sqrt(max_steps)
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+        const double need = ((double)run->max_steps + 1.0) * (double)c->state_total * (double)esz;
+        c->run.checkpoint_every =
+            need <= 0.25 * (double)free_b ? 1 : std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, run->max_steps))));
+    }
     ra_status st = RA_OK;
 #define ALLOC(ptr, n)                                              \
     do {                                                           \
@@ -382,8 +392,8 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
         c->tsf = p8;
         ALLOC(c->tsf_acc, c->smp_total);
     }
-    if (run->checkpoint_every > 0) {
-        const int K = run->checkpoint_every;
+    if (c->run.checkpoint_every > 0) {
+        const int K = c->run.checkpoint_every;
         c->n_ckpt = ((int64_t)run->max_steps + K - 1) / K + 1;
         ALLOC(p8, c->n_ckpt * c->state_total * esz);
         c->ckpt = p8;
@@ -808,6 +818,13 @@ ra_status ra_get_bonds(ra_ctx* c, double* out) {
                                       c->run.precision, c->stream));
     else
         HIPCHK(c, launch_to_f64(c->state, out, c->state_total, c->run.precision, c->stream));
+    return RA_OK;
+}
+
+ra_status ra_checkpoint_interval(ra_ctx* c, int32_t* steps) {
+    if (!c) return fail(nullptr, RA_EINVAL, "null context");
+    if (!steps) return fail(c, RA_EINVAL, "steps is null");
+    *steps = c->run.checkpoint_every;
     return RA_OK;
 }
 

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "libra.so")
 
 RA_OK, RA_EINVAL, RA_ENOMEM, RA_EDEVICE, RA_EUNSTABLE, RA_ESTATE = 0, -1, -2, -3, -4, -5
 HOOKEAN, FENE, HARMONIC = 0, 1, 2
+CKPT_AUTO = -1
 QUIESCENT, UNIAXIAL, PLANAR, SHEAR = 0, 1, 2, 3
 _NAMES = {RA_EINVAL: "RA_EINVAL", RA_ENOMEM: "RA_ENOMEM", RA_EDEVICE: "RA_EDEVICE",
           RA_EUNSTABLE: "RA_EUNSTABLE", RA_ESTATE: "RA_ESTATE"}
@@ -22,7 +23,7 @@ _NAMES = {RA_EINVAL: "RA_EINVAL", RA_ENOMEM: "RA_ENOMEM", RA_EDEVICE: "RA_EDEVIC
 EXPORTS = ["ra_create", "ra_init_chains", "ra_step", "ra_average_forces", "ra_bell_rates",
            "ra_backward", "ra_reclone", "ra_rsf_cycle", "ra_block_sigma", "ra_mftu", "ra_conformation",
            "ra_sync_status", "ra_guard_counts", "ra_get_samples", "ra_get_bonds",
-           "ra_tile_info", "ra_debug_noise", "ra_last_error", "ra_destroy"]
+           "ra_checkpoint_interval", "ra_tile_info", "ra_debug_noise", "ra_last_error", "ra_destroy"]
 
 
 class RAError(RuntimeError):
@@ -83,6 +84,7 @@ def library():
         "ra_guard_counts": [P, ctypes.POINTER(i64)],
         "ra_get_samples": [P, P, P],
         "ra_get_bonds": [P, P],
+        "ra_checkpoint_interval": [P, ctypes.POINTER(i32)],
         "ra_tile_info": [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "ra_debug_noise": [P, i64, u64, P, P, P, P],
         "ra_destroy": [P],
@@ -327,6 +329,12 @@ class Replicas:
             off += m
         return outs
 
+    def checkpoint_interval(self):
+        """Steps between kept states (CKPT_AUTO resolved; 0: no checkpoints)."""
+        k = ctypes.c_int32()
+        self._check(self.L.ra_checkpoint_interval(self.ptr, ctypes.byref(k)))
+        return k.value
+
     def tile_info(self):
         """(beads per lane per group, replicas per wave per group)."""
         G = len(self.groups)
@@ -366,7 +374,7 @@ class ReplicaAverage(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, params, groups, parents, n_steps, seed, sample_every, k0, x_dagger,
-                checkpoint_every=100):
+                checkpoint_every=CKPT_AUTO):
         gs = []
         for g, p in zip(groups, params.detach().cpu().double().tolist()):
             d = dict(g)

@@ -75,6 +75,8 @@ def _create(lib, desc_kw, run_kw):
     ({}, dict(sample_every=0), "sample_every"),
     ({}, dict(checkpoint_every=10, precision=64), "adjoint"),
     ({}, dict(checkpoint_every=10, plain=1), "adjoint"),
+    ({}, dict(checkpoint_every=-1, precision=64), "adjoint"),
+    ({}, dict(checkpoint_every=-2), "negative"),
     ({}, dict(waves_per_block=3), "waves_per_block"),
     ({}, dict(noise_tag=2), "noise_tag"),
     (dict(spring=2, rest_length=-1.0), {}, "rest_length"),
@@ -104,6 +106,7 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.ra_block_sigma(None, 1, None) == -1
     assert lib.ra_mftu(None, None, 1, None) == -1
     assert lib.ra_conformation(None, None, None, None, None) == -1
+    assert lib.ra_checkpoint_interval(None, None) == -1
     lib.ra_destroy(None)
 
 

@@ -25,6 +25,7 @@ def _grad_pair(groups, parents, seed, steps, S, K, k0=1e-6, xd=0.1, wseed=0, rat
     gr = rng.normal(size=(W, nspr)) * rate_scale
     rep = run_gpu(groups, parents, seed, steps, S, checkpoint_every=K, max_steps=steps,
                   tile_policy=tile_policy)
+    assert rep.checkpoint_interval() == (1 if K == -1 else K)
     mean, _ = rep.average_forces()
     g_gpu = rep.backward(mean, torch.from_numpy(gm).cuda(), torch.from_numpy(gr).cuda(), k0, xd)
     g_gpu = g_gpu.cpu().numpy()
@@ -66,6 +67,25 @@ def test_adjoint_batch_and_guard():
     announce("adjoint batch with guard")
     g_gpu, g_ref = _grad_pair(gs, ps, 5, 150, 50, 30)
     _check(g_gpu, g_ref, 1e-4)
+
+
+@pytest.mark.parametrize("K", [1, 7, -1])
+def test_adjoint_checkpoint_interval_keeps_the_gradient(K):
+    # K = 1 keeps every state, so the backward reads each reverse step's state
+    # from its checkpoint instead of recomputing it; any interval must give the
+    # oracle's tangents and, up to FP32 summation order, the gradient of K = 50.
+    # K = -1 (automatic) keeps every state when they fit, as here.
+    N = 6
+    guard = np.zeros((N, 3))
+    guard[1:, 0] = np.cumsum([0.5, np.sqrt(0.9995) * 10.0, 1.0, np.sqrt(0.95) * 10.0, 0.7])
+    gs = [wl.group(N, 32, 1e-4, wl.FENE, 1.0, 100.0, wl.UNIAXIAL, 0.1, stream_id=2),
+          wl.group(24, 40, 1e-4, wl.FENE, 1.0, 50.0, wl.SHEAR, 10.0, stream_id=7)]
+    ps = [guard, wl.equilibrium_parent(24, wl.FENE, 1.0, 50.0, seed=4)]
+    announce("adjoint checkpoint interval %d" % K)
+    g_k, g_ref = _grad_pair(gs, ps, 5, 150, 50, K)
+    _check(g_k, g_ref, 1e-4)
+    g_50, _ = _grad_pair(gs, ps, 5, 150, 50, 50)
+    assert np.max(np.abs(g_k - g_50) / np.maximum(np.abs(g_50), 1e-3 * np.max(np.abs(g_50)))) < 1e-5
 
 
 def test_adjoint_long_horizon():
