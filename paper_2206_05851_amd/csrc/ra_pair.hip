@@ -142,6 +142,10 @@ __device__ __forceinline__ void run_pair(const FwdArgs& a, const GroupDev& Gm, i
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             T lx = (T)0, ly = (T)0, lz = (T)0;
+            // unrolled by 8: eight independent reciprocal-and-multiply chains
+            // fill the issue slots of the single wavefront per SIMD (measured
+            // 4% faster than the compiler's 4; 16 is slower)
+#pragma unroll 8
             for (int j = 0; j < N; ++j) {
                 const T dx = px - xs[base + j][0];
                 const T dy = py - xs[base + j][1];
