@@ -223,16 +223,19 @@ __global__ __launch_bounds__(64) void src_rg2_kernel(const GroupDev* __restrict_
 // ---------------------------------------------------------------------------
 // sigma(N_R): per (window, spring), B = floor(R/block) consecutive blocks;
 // each block's mean tension is one RSF estimate; sigma = their standard
-// deviation (B - 1). Wave v of 4 takes a contiguous quarter of the blocks in
-// order; the quarters combine in order; two passes (mean, then deviations).
+// deviation (B - 1). Wave v of 16 takes a contiguous sixteenth of the blocks
+// in order; the sixteenths combine in order; two passes (mean, then deviations).
 // ---------------------------------------------------------------------------
+constexpr int BSIG_WAVES = 16;
+
 template <typename T>
-__global__ __launch_bounds__(256) void block_sigma_kernel(const GroupDev* __restrict__ groups,
-                                                          const ColTile* __restrict__ tiles,
-                                                          const T* __restrict__ smp, int64_t smp_total,
-                                                          int64_t spr_total, int block,
-                                                          double* __restrict__ sigma) {
-    __shared__ double part[4][WAVE];
+__global__ __launch_bounds__(1024) void block_sigma_kernel(const GroupDev* __restrict__ groups,
+                                                           const ColTile* __restrict__ tiles,
+                                                           const T* __restrict__ smp, int64_t smp_total,
+                                                           int64_t spr_total, int block,
+                                                           double* __restrict__ sigma) {
+    constexpr int NW = BSIG_WAVES;
+    __shared__ double part[NW][WAVE];
     const ColTile tile = tiles[blockIdx.x];
     const int64_t w = blockIdx.y;
     const GroupDev& G = groups[tile.g];
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(256) void block_sigma_kernel(const GroupDev* __rest
     const int j = tile.j0 + lane;
     const bool ok = j < nm1;
     const int B = G.R / block;
-    const int cb = (B + 3) / 4;
+    const int cb = (B + NW - 1) / NW;
     const int b0 = min(B, wv * cb), b1 = min(B, b0 + cb);
     const T* base = smp + w * smp_total + G.smp_off + (ok ? j : 0);
     auto block_mean = [&](int b) {
@@ -250,12 +253,18 @@ __global__ __launch_bounds__(256) void block_sigma_kernel(const GroupDev* __rest
         for (int q = 0; q < block; ++q) m += (double)base[(int64_t)(b * block + q) * nm1];
         return m / block;
     };
+    auto combine = [&]() {   // the wavefronts' partials in wavefront order
+        double t = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) t += part[v][lane];
+        return t;
+    };
     double acc = 0.0;
     if (ok)
         for (int b = b0; b < b1; ++b) acc += block_mean(b);
     part[wv][lane] = acc;
     __syncthreads();
-    const double mu = B > 0 ? (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) / B : 0.0;
+    const double mu = B > 0 ? combine() / B : 0.0;
     __syncthreads();
     double ss = 0.0;
     if (ok)
@@ -266,7 +275,7 @@ __global__ __launch_bounds__(256) void block_sigma_kernel(const GroupDev* __rest
     part[wv][lane] = ss;
     __syncthreads();
     if (wv == 0 && ok) {
-        const double tot = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        const double tot = combine();
         sigma[w * spr_total + G.spr_off + j] = B > 1 ? sqrt(tot / (double)(B - 1)) : 0.0;
     }
 }
@@ -337,7 +346,7 @@ hipError_t launch_block_sigma(const GroupDev* groups, const ColTile* tiles, int 
                               int precision, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     if (n_tiles == 0 || n_windows == 0) return hipSuccess;
-    dim3 grid((unsigned)n_tiles, (unsigned)n_windows), blk(256);
+    dim3 grid((unsigned)n_tiles, (unsigned)n_windows), blk(WAVE * BSIG_WAVES);
     if (precision == 64)
         hipLaunchKernelGGL(block_sigma_kernel<double>, grid, blk, 0, st, groups, tiles, (const double*)smp, smp_total,
                            spr_total, block, sigma);
