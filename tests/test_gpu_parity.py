@@ -193,6 +193,24 @@ def test_long_chain_parity():
     assert max(e) < TOL32
 
 
+@pytest.mark.parametrize("N,M", [(256, 4), (1024, 16)])
+def test_largest_chain_of_each_family(N, M):
+    # the longest chain each one-wave family holds: every one of the 64 lanes
+    # carries M beads, the last lane's last bead included
+    g = wl.group(N, 5, 5e-5, wl.FENE, 1.0, 400.0, wl.PLANAR, wl.wi_to_rate(5.0, N))
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 400.0, seed=N)
+    announce("largest chain N=%d" % N)
+    rep = run_gpu([g], [parent], 8, 200, 100, tile_policy=1000 + M)
+    assert rep.tile_info() == ([M], [1])
+    smp = rep.samples()[0].cpu().numpy()
+    bonds = rep.bonds()[0].cpu().numpy()
+    rep.sync_status()
+    o = run_oracle([g], [parent], 8, 200, 100)
+    e = (rel_err(smp, o.samples()[0]), np.max(np.abs(bonds - np.diff(o.positions()[0], axis=1))))
+    announce("N=%d rel err samples %.2e bonds abs %.2e" % ((N,) + e))
+    assert e[0] < TOL32 and e[1] < 1e-4
+
+
 def test_mixed_batch_parity():
     groups, parents, run = wl.batched512(n_groups=512, steps=200)
     pick = [0, 1, 17, 255, 256, 300, 511]
