@@ -213,17 +213,18 @@ const char* ra_last_error(const ra_ctx* ctx) { return ctx ? ctx->err.c_str() : g
 
 void ra_destroy(ra_ctx* c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    // teardown: errors are not actionable here, so their codes are dropped
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     // pos[1] points into the pos[0] allocation and is not freed on its own
     void* ptrs[] = {c->dgroups, c->ditems, c->dtiles, c->dpar_off, c->ditem_begin, c->state, c->pos[0],
                     c->samples, c->tsf, c->tsf_acc, c->ckpt, c->segbuf, c->dseg_off,
                     c->partial, c->lam_mu, c->status, c->clamps, c->dstep, c->src, c->drep_off};
     for (void* p : ptrs)
-        if (p) hipFree(p);
-    if (c->ev_parent) hipEventDestroy(c->ev_parent);
-    if (c->ev_reclone) hipEventDestroy(c->ev_reclone);
-    if (c->own_stream) hipStreamDestroy(c->stream);
+        if (p) (void)hipFree(p);
+    if (c->ev_parent) (void)hipEventDestroy(c->ev_parent);
+    if (c->ev_reclone) (void)hipEventDestroy(c->ev_reclone);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -560,13 +561,13 @@ ra_status ra_step(ra_ctx* c, int64_t n_steps) {
             st = enqueue_forward(c, n_steps);
             hipError_t e = hipStreamEndCapture(c->stream, &graph);
             if (st != RA_OK) {
-                if (e == hipSuccess) hipGraphDestroy(graph);
+                if (e == hipSuccess) (void)hipGraphDestroy(graph);
                 return st;
             }
             HIPCHK(c, e);
             hipGraphExec_t exec;
             hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             HIPCHK(c, ei);
             it = c->graphs.emplace(n_steps, exec).first;
         }

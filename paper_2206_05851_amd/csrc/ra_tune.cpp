@@ -96,22 +96,23 @@ double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int M, int wpb,
         hipEventCreate(&e0) == hipSuccess) {
         if (hipEventCreate(&e1) == hipSuccess) {
             if (ra_init_chains(ctx, dp) == RA_OK && ra_step(ctx, 32) == RA_OK) {
-                hipEventRecord(e0, st);
+                (void)hipEventRecord(e0, st);
                 if (ra_step(ctx, 96) == RA_OK) {
-                    hipEventRecord(e1, st);
+                    (void)hipEventRecord(e1, st);
                     if (hipEventSynchronize(e1) == hipSuccess) {
                         float t = 0.f;
-                        hipEventElapsedTime(&t, e0, e1);
+                        (void)hipEventElapsedTime(&t, e0, e1);
                         ms = t;
                     }
                 }
             }
-            hipEventDestroy(e1);
+            (void)hipEventDestroy(e1);
         }
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
     }
-    hipStreamSynchronize(st);
-    if (dp) hipFree(dp);
+    // a timing probe: failures above leave ms < 0 and the candidate unused
+    (void)hipStreamSynchronize(st);
+    if (dp) (void)hipFree(dp);
     ra_destroy(ctx);
     return ms;
 }
