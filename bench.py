@@ -332,12 +332,22 @@ def main():
         bat_step()
         tbat = min(time_once(bat_step) for _ in range(2))
         bat.sync_status()
+        bat.close()
+        # the same batch with tiles chosen by the timing autotuner (each chain
+        # length timed alone on 256 replicas) instead of the cost model
+        bat = ra.Replicas(bg, brun["seed"], precision=32, sample_every=brun["sample_every"],
+                          max_windows=brun["steps"] // brun["sample_every"], use_graph=True, device=dev,
+                          tile_policy=1)
+        bat_step()
+        ttun = min(time_once(bat_step) for _ in range(2))
+        bat.sync_status()
+        bat.close()
         bwork = sum(x["n_replicas"] * x["n_beads"] for x in bg) * brun["steps"]
         out["batched"] = {"workload": "batched512: 512 FENE chains N~U{20..200}, b~U[50,200], planar "
                                       "Wi~U[0.5,5] / shear Wi~U[1,50], R~U{16..256}, 5000 steps",
-                          "value": bwork / tbat, "ms_per_step": 1e3 * tbat, "graph": True}
-        bat.close()
-        log("batched: %.2f ms" % (1e3 * tbat))
+                          "value": bwork / tbat, "ms_per_step": 1e3 * tbat, "graph": True,
+                          "tiles": "cost model", "autotuned_tiles_ms_per_step": 1e3 * ttun}
+        log("batched: %.2f ms (cost-model tiles), %.2f ms (autotuned tiles)" % (1e3 * tbat, 1e3 * ttun))
 
     if "large1000" in extras:
         # 1000-bead transient with TSF
