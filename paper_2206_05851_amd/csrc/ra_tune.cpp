@@ -1,6 +1,7 @@
 // ra_tune.cpp — cost-model and timing autotuner for the per-group tile.
 #include "ra_tune.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -40,7 +41,7 @@ int choose_beads_per_lane(int n_beads, int n_replicas, int family, int forced) {
 namespace {
 
 using Key = std::tuple<int, int, int, int, int>;   // N, spring, precision, family, wpb
-constexpr int TUNE_REPLICAS = 256;                 // replicas in each timing run
+constexpr int TUNE_WAVES_PER_SIMD = 4;             // timing runs fill every SIMD this many times
 std::mutex g_mu;
 std::map<Key, int> g_cache;
 bool g_loaded = false;
@@ -72,10 +73,19 @@ void append_cache_file(const Key& k, int M) {
       << ", \"M\": " << M << "}\n";
 }
 
-// time `steps` fused steps of one group with a forced tile; returns ms or -1
+// Time 96 fused steps of one group with a forced tile M and enough replicas
+// to give every SIMD TUNE_WAVES_PER_SIMD wavefronts of that packing, so the
+// candidates are ranked by throughput (as in a saturated batch), not by the
+// latency of a few wavefronts. Returns ms per replica, or -1.
 double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int M, int wpb, hipStream_t st) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    const int lanes = (d.n_beads + M - 1) / M;
+    const int per_wave = std::max(1, 64 / lanes);
     ra_chain_desc g = d;
-    g.n_replicas = TUNE_REPLICAS;
+    g.n_replicas = TUNE_WAVES_PER_SIMD * 4 * cus * per_wave;
     ra_run_desc r{};
     r.seed = run.seed;
     r.precision = run.precision;
@@ -102,7 +112,7 @@ double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int M, int wpb,
                     if (hipEventSynchronize(e1) == hipSuccess) {
                         float t = 0.f;
                         (void)hipEventElapsedTime(&t, e0, e1);
-                        ms = t;
+                        ms = t / g.n_replicas;
                     }
                 }
             }
@@ -132,7 +142,7 @@ ra_status autotune_tiles(const std::vector<ra_chain_desc>& descs, const ra_run_d
         int best = Ms[i];
         for (int M : family_beads_per_lane(family)) {
             if (!legal(d.n_beads, M)) continue;
-            const double ms = time_tile(d, run, M, waves_per_block, stream);
+            const double ms = time_tile(d, run, M, waves_per_block, stream);   // per replica
             if (ms < 0) { why = "timing run failed"; return RA_EDEVICE; }
             if (best_ms < 0 || ms < best_ms) { best_ms = ms; best = M; }
         }
