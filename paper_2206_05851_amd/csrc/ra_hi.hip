@@ -402,7 +402,9 @@ __device__ __forceinline__ void run_hi(const FwdArgs& a, const GroupDev& G, int 
                 const T dx = px - P[4 * j], dy = py - P[4 * j + 1], dz = pz - P[4 * j + 2];
                 const int dj = j - lane;
                 const bool use = mine && (dj >= 2 || dj <= -2);
-                const T r2 = use ? fmadd(dx, dx, fmadd(dy, dy, dz * dz)) : (T)1;
+                // excluded pairs get a zero coefficient below (the select also
+                // drops the self pair's Inf/NaN from 1/r^2 at r = 0)
+                const T r2 = fmadd(dx, dx, fmadd(dy, dy, dz * dz));
                 const T inv = fast_rcp(r2);
                 const T s1 = ljr2 * inv;
                 const T s3 = s1 * s1 * s1;

@@ -150,12 +150,13 @@ __device__ __forceinline__ void run_pair(const FwdArgs& a, const GroupDev& Gm, i
                 const T dx = px - xs[base + j][0];
                 const T dy = py - xs[base + j][1];
                 const T dz = pz - xs[base + j][2];
-                // pairs |i - j| >= 2 of an existing replica only; the others
-                // (the bead itself, bonded neighbours, lanes past the last
-                // replica, which all sit at the origin) never form 1/r^2
+                // pairs |i - j| >= 2 of an existing replica only; for the
+                // others (the bead itself, bonded neighbours, lanes past the
+                // last replica) the coefficient is replaced by 0 below, which
+                // also discards the Inf/NaN of the self pair's 1/r^2
                 const int dj = j - i;
                 const bool use = rep_ok && (dj >= 2 || dj <= -2);
-                const T r2 = use ? fmadd(dx, dx, fmadd(dy, dy, dz * dz)) : (T)1;
+                const T r2 = fmadd(dx, dx, fmadd(dy, dy, dz * dz));
                 const T inv = fast_rcp(r2);
                 const T s1 = ljr2 * inv;
                 const T s3 = s1 * s1 * s1;
