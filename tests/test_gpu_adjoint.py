@@ -88,6 +88,16 @@ def test_adjoint_checkpoint_interval_keeps_the_gradient(K):
     assert np.max(np.abs(g_k - g_50) / np.maximum(np.abs(g_50), 1e-3 * np.max(np.abs(g_50)))) < 1e-5
 
 
+def test_adjoint_every_state_kept_multi_bead_lanes():
+    # the no-recompute backward (automatic interval = 1) with 3 beads per lane
+    N = 150
+    g = wl.group(N, 64, 1e-4, wl.FENE, 1.3, 40.0, wl.PLANAR, 0.8)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.3, 40.0, seed=N)
+    announce("adjoint N=150, every state kept")
+    g_gpu, g_ref = _grad_pair([g], [parent], 17, 200, 50, -1)
+    _check(g_gpu, g_ref, 1e-4)
+
+
 def test_adjoint_long_horizon():
     N = 20
     g = wl.group(N, 128, 1e-4, wl.FENE, 1.0, 100.0, wl.UNIAXIAL, wl.wi_to_rate(4.0, N))
