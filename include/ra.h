@@ -241,17 +241,17 @@ RA_API ra_status ra_get_samples(ra_ctx* ctx, double* out, double* tsf_out);
  * [sum_g R_g (N_g-1) 3]. */
 RA_API ra_status ra_get_bonds(ra_ctx* ctx, double* out);
 
+/* The checkpoint interval in use (RA_CKPT_AUTO resolved at ra_create; 0 when
+ * the context keeps no checkpoints). With an interval of 1 ra_backward reads
+ * every step's state instead of recomputing it. */
+RA_API ra_status ra_checkpoint_interval(ra_ctx* ctx, int32_t* steps);
+
 /* Tile chosen per group (host int32[n_groups] each): beads per lane and
  * replicas per wavefront; kernel_family (host int32[1], may be NULL): 1 = one
  * bead per lane with a noise-producer wavefront per work item, 2 = the
  * pair-interaction kernel (one bead per lane; LJ and rest-length springs),
  * 3 = hydrodynamic-interaction kernel (one workgroup per replica), 4 = 1-4
  * beads per lane, 16 = 6-16 beads per lane, 0 = plain path. */
-/* The checkpoint interval in use (RA_CKPT_AUTO resolved at ra_create; 0 when
- * the context keeps no checkpoints). With an interval of 1 ra_backward reads
- * every step's state instead of recomputing it. */
-RA_API ra_status ra_checkpoint_interval(ra_ctx* ctx, int32_t* steps);
-
 RA_API ra_status ra_tile_info(ra_ctx* ctx, int32_t* beads_per_lane, int32_t* replicas_per_wave,
                               int32_t* kernel_family);
 
