@@ -75,6 +75,41 @@ def test_fp32_fene50_parity_200_steps():
 
 
 @pytest.mark.parametrize("precision,tol", [(32, TOL32), (64, TOL64)])
+def test_degenerate_sizes_match_oracle(precision, tol):
+    # one replica (std defined as 0), the two-bead dumbbell (a single spring),
+    # a one-replica chain filling a whole wavefront, zero-step calls, and calls
+    # that end inside a window; on the fused path and on the plain path
+    from paper_2206_05851_amd import ra
+    cases = [wl.group(2, 1, 1e-3, wl.FENE, 1.0, 10.0, wl.UNIAXIAL, 0.5, stream_id=2),
+             wl.group(2, 7, 1e-3, wl.HOOKEAN, 1.0, 0.0, wl.SHEAR, 2.0, stream_id=3),
+             wl.group(64, 1, 1e-4, wl.FENE, 1.0, 60.0, wl.PLANAR, 0.3, stream_id=4)]
+    for i, g in enumerate(cases):
+        parent = wl.equilibrium_parent(g["n_beads"], g["spring"], g["H"], g["b"], seed=20 + i)
+        o = run_oracle([g], [parent], 13, 100, 20)
+        om, osd = o.average_forces()
+        for plain in (False, True):
+            announce("degenerate case %d N=%d R=%d precision=%d plain=%d"
+                     % (i, g["n_beads"], g["n_replicas"], precision, plain))
+            rep = ra.Replicas([g], 13, sample_every=20, max_windows=5, precision=precision, plain=plain)
+            rep.init_chains([parent])
+            b0 = rep.bonds()[0].cpu().numpy()
+            rep.step(0)
+            assert np.array_equal(rep.bonds()[0].cpu().numpy(), b0)
+            for n in (0, 55, 0, 45):
+                rep.step(n)
+            mean, std = rep.average_forces()
+            smp = rep.samples()[0].cpu().numpy()
+            rep.sync_status()
+            assert smp.shape == (5, g["n_replicas"], g["n_beads"] - 1)
+            assert rel_err(smp, o.samples()[0]) < tol
+            assert rel_err(mean.cpu().numpy(), om) < tol
+            if g["n_replicas"] == 1:
+                assert np.all(std.cpu().numpy() == 0.0) and np.all(osd == 0.0)
+            else:
+                assert rel_err(std.cpu().numpy(), osd) < tol
+
+
+@pytest.mark.parametrize("precision,tol", [(32, TOL32), (64, TOL64)])
 def test_plain_path_parity(precision, tol):
     N = 30
     g = wl.group(N, 96, 1e-4, wl.FENE, 1.0, 60.0, wl.SHEAR, 40.0)
