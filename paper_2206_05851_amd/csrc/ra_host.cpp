@@ -368,6 +368,14 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
         if (st != RA_OK) { std::string m_ = c->err; ra_destroy(c); \
                            return fail(nullptr, st, m_); }         \
     } while (0)
+    // host-to-device copy during set-up; on failure the context is released
+#define HCOPY(dst, src, bytes)                                                              \
+    do {                                                                                    \
+        const hipError_t e_ = hipMemcpy((dst), (src), (bytes), hipMemcpyHostToDevice);      \
+        if (e_ != hipSuccess) { ra_destroy(c);                                              \
+                                return fail(nullptr, RA_EDEVICE,                            \
+                                            std::string("hipMemcpy: ") + hipGetErrorString(e_)); } \
+    } while (0)
     char* p8 = nullptr;
     ALLOC(c->dgroups, n_groups);
     ALLOC(c->ditems, c->hitems.size());
@@ -409,26 +417,37 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
         ALLOC(c->partial, 3 * c->hitems.size());
         ALLOC(c->lam_mu, (int64_t)run->max_windows * c->spr_total);
         ALLOC(c->ditem_begin, 2 * n_groups);
-        HIPCHK(c, hipMemcpy(c->dseg_off, seg_off.data(), seg_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        HCOPY(c->dseg_off, seg_off.data(), seg_off.size() * sizeof(int64_t));
         std::vector<int32_t> ib(2 * n_groups);
         for (int i = 0; i < n_groups; ++i) { ib[2 * i] = c->item_begin[i]; ib[2 * i + 1] = c->item_count[i]; }
-        HIPCHK(c, hipMemcpy(c->ditem_begin, ib.data(), ib.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HCOPY(c->ditem_begin, ib.data(), ib.size() * sizeof(int32_t));
     }
-#undef ALLOC
-    HIPCHK(c, hipMemcpy(c->dgroups, c->hgroups.data(), n_groups * sizeof(GroupDev), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->ditems, c->hitems.data(), c->hitems.size() * sizeof(Item), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->dtiles, c->htiles.data(), c->htiles.size() * sizeof(ColTile), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->dpar_off, par_off.data(), n_groups * sizeof(int64_t), hipMemcpyHostToDevice));
+    HCOPY(c->dgroups, c->hgroups.data(), n_groups * sizeof(GroupDev));
+    HCOPY(c->ditems, c->hitems.data(), c->hitems.size() * sizeof(Item));
+    HCOPY(c->dtiles, c->htiles.data(), c->htiles.size() * sizeof(ColTile));
+    HCOPY(c->dpar_off, par_off.data(), n_groups * sizeof(int64_t));
     {
         std::vector<int64_t> ro(n_groups + 1, 0);
         for (int i = 0; i < n_groups; ++i) ro[i + 1] = ro[i] + groups[i].n_replicas;
         c->n_reps = ro[n_groups];
-        HIPCHK(c, hipMemcpy(c->drep_off, ro.data(), ro.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        HCOPY(c->drep_off, ro.data(), ro.size() * sizeof(int64_t));
     }
-    HIPCHK(c, hipMemset(c->src, 0, par * sizeof(double)));
-    HIPCHK(c, hipMemset(c->status, 0, sizeof(int32_t)));
-    HIPCHK(c, hipMemset(c->clamps, 0, n_groups * sizeof(unsigned long long)));
-    HIPCHK(c, hipMemset(c->dstep, 0, sizeof(int64_t)));
+    {
+        const hipError_t e = hipMemset(c->src, 0, par * sizeof(double));
+        if (e != hipSuccess) {
+            ra_destroy(c);
+            return fail(nullptr, RA_EDEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
+        }
+    }
+    {
+        const hipError_t e = launch_reset(c->status, c->clamps, n_groups, c->dstep, c->stream);
+        if (e != hipSuccess) {
+            ra_destroy(c);
+            return fail(nullptr, RA_EDEVICE, std::string("reset kernel: ") + hipGetErrorString(e));
+        }
+    }
+#undef ALLOC
+#undef HCOPY
     *out = c;
     return RA_OK;
 }
@@ -437,10 +456,8 @@ ra_status ra_init_chains(ra_ctx* c, const double* parent_xyz) {
     if (!c) return fail(nullptr, RA_EINVAL, "null context");
     if (!parent_xyz) return fail(c, RA_EINVAL, "parent_xyz is null");
     const int ng = (int)c->descs.size();
-    // device-side resets are kernels/memsets ordered on the context's stream
-    HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(int32_t), c->stream));
-    HIPCHK(c, hipMemsetAsync(c->clamps, 0, ng * sizeof(unsigned long long), c->stream));
-    HIPCHK(c, hipMemsetAsync(c->dstep, 0, sizeof(int64_t), c->stream));
+    // device-side resets are kernels ordered on the context's stream
+    HIPCHK(c, launch_reset(c->status, c->clamps, ng, c->dstep, c->stream));
     const bool plain = c->run.plain != 0;
     c->cur = 0;
     HIPCHK(c, launch_clone(c->dgroups, ng, c->max_group_elems, parent_xyz, c->dpar_off,
@@ -694,6 +711,8 @@ ra_status ra_rsf_cycle(ra_ctx* c, ra_ctx* parent, int64_t n_windows, int64_t par
     ra_status st = check_parent(c, parent);
     if (st != RA_OK) return st;
     if (n_windows < 0 || parent_steps < 1) return fail(c, RA_EINVAL, "n_windows < 0 or parent_steps < 1");
+    if (n_windows > (int64_t)0xFFFFFFFF || parent_steps > (int64_t)0xFFFFFFFF)
+        return fail(c, RA_EINVAL, "total steps would exceed 2^32");
     if (parent->run.sample_every != parent_steps)
         return fail(c, RA_EINVAL, "the parent context must sample every parent_steps steps");
     const int S = c->run.sample_every;
@@ -723,13 +742,10 @@ ra_status ra_rsf_cycle(ra_ctx* c, ra_ctx* parent, int64_t n_windows, int64_t par
         for (int64_t w = 0; w < n_windows; ++w) {
             st = ra_reclone(c, parent);
             if (st != RA_OK) return st;
-            if (w + 1 < n_windows) {
-                st = enqueue_forward_dual(c, S, parent, parent_steps);
-                parent->step += parent_steps;
-            } else {
-                st = enqueue_forward(c, S);
-            }
+            const bool both = w + 1 < n_windows;
+            st = both ? enqueue_forward_dual(c, S, parent, parent_steps) : enqueue_forward(c, S);
             if (st != RA_OK) return st;
+            if (both) parent->step += parent_steps;
             c->step += S;
         }
         if (two) {   // later parent work waits for the cycle

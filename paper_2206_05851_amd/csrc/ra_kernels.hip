@@ -263,6 +263,18 @@ __global__ void advance_kernel(int64_t* step, int64_t n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *step += n;
 }
 
+// Clears the status word, the per-group guard counters and the device step
+// counter: a kernel rather than memset nodes, so a caller may capture the
+// clone sequence in a graph.
+__global__ void reset_kernel(int32_t* status, unsigned long long* clamps, int n_groups, int64_t* step) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t == 0) {
+        *status = 0;
+        *step = 0;
+    }
+    for (int g = t; g < n_groups; g += (int)(gridDim.x * blockDim.x)) clamps[g] = 0ull;
+}
+
 // ---------------------------------------------------------------------------
 // Clone (RSF, Sec. II): Q_j = parent_{j+1} - parent_j in FP64, then rounded to
 // the state precision, for every replica; the parent is validated here.
@@ -603,6 +615,12 @@ hipError_t launch_forward_dual(const FwdArgs& a, const FwdArgs& b, int precision
 hipError_t launch_advance(int64_t* step, int64_t n, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, st, step, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(int32_t* status, unsigned long long* clamps, int n_groups, int64_t* step, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, st, status, clamps, n_groups, step);
     return hipGetLastError();
 }
 

@@ -47,6 +47,7 @@ struct AdjArgs {
 hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, hipStream_t st);
 hipError_t launch_forward_split(const FwdArgs& a, hipStream_t st);
 hipError_t launch_advance(int64_t* step, int64_t n, hipStream_t st);
+hipError_t launch_reset(int32_t* status, unsigned long long* clamps, int n_groups, int64_t* step, hipStream_t st);
 hipError_t launch_clone(const GroupDev* groups, int n_groups, int64_t max_elems, const double* parent,
                         const int64_t* par_off, void* state, double* tsf_acc, int32_t* status, int precision,
                         bool plain, hipStream_t st);
