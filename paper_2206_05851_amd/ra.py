@@ -109,6 +109,18 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, name, shape, dtype=torch.float64):
+    """Check a tensor's shape and dtype before its pointer crosses the C ABI,
+    which has no sizes to check against (a short buffer would be read or
+    written past its end on the device)."""
+    if t is None:
+        return None
+    if not torch.is_tensor(t) or tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+        got = (t.dtype, tuple(t.shape)) if torch.is_tensor(t) else type(t).__name__
+        raise ValueError("%s: expected %s of shape %s, got %s" % (name, dtype, tuple(shape), got))
+    return t
+
+
 def _stream_handle(stream):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -139,6 +151,7 @@ def debug_noise(counters, seed, words=True, n32=True, n64=True, stream=None):
     """Philox words and FP32/FP64 normals for device int32 counters [n,4]."""
     L = library()
     n = counters.shape[0]
+    _need(counters, "counters", (n, 4), torch.int32)
     dev = counters.device
     w = torch.empty((n, 4), dtype=torch.int32, device=dev) if words else None
     a = torch.empty((n, 3), dtype=torch.float32, device=dev) if n32 else None
@@ -205,6 +218,8 @@ class Replicas:
         if not torch.is_tensor(parents):
             flat = torch.cat([torch.as_tensor(p, dtype=torch.float64).reshape(-1) for p in parents])
             parents = flat.to(self.device)
+        n_xyz = sum(3 * g["n_beads"] for g in self.groups)
+        _need(parents.reshape(-1), "parents", (n_xyz,))
         self._parents = parents.contiguous()
         self._enter()
         self._check(self.L.ra_init_chains(self.ptr, _ptr(self._parents)))
@@ -222,6 +237,8 @@ class Replicas:
             std = self._dev((W.value, self.n_springs))
         else:
             mean, std = out
+            _need(mean, "out[0]", (W.value, self.n_springs))
+            _need(std, "out[1]", (W.value, self.n_springs))
         tm = self._dev((W.value, self.n_springs)) if tsf else None
         ts = self._dev((W.value, self.n_springs)) if tsf else None
         self._enter()
@@ -229,8 +246,14 @@ class Replicas:
         self._leave()
         return (mean, std, tm, ts) if tsf else (mean, std)
 
+    def _windows(self):
+        W = ctypes.c_int64()
+        self._check(self.L.ra_average_forces(self.ptr, None, None, None, None, ctypes.byref(W)))
+        return W.value
+
     def bell_rates(self, mean, k0, x_dagger, events=False):
         W = mean.shape[0]
+        _need(mean, "mean", (W, self.n_springs))
         rates = self._dev((W, self.n_springs))
         rsum = self._dev((W, len(self.groups)))
         ev = self._dev((W, self.n_springs), torch.uint8) if events else None
@@ -242,8 +265,13 @@ class Replicas:
 
     def backward(self, mean, grad_mean, grad_rates=None, k0=0.0, x_dagger=0.0):
         out = self._dev((len(self.groups), 3))
-        gm = grad_mean.contiguous() if grad_mean is not None else None
-        gr = grad_rates.contiguous() if grad_rates is not None else None
+        shape = (self._windows(), self.n_springs)
+        gm = _need(grad_mean, "grad_mean", shape)
+        gr = _need(grad_rates, "grad_rates", shape)
+        if gr is not None:
+            _need(mean, "mean", shape)
+        gm = gm.contiguous() if gm is not None else None
+        gr = gr.contiguous() if gr is not None else None
         self._enter()
         self._check(self.L.ra_backward(self.ptr, _ptr(mean), _ptr(gm), _ptr(gr), float(k0),
                                        float(x_dagger), _ptr(out)))
@@ -271,6 +299,7 @@ class Replicas:
     def mftu(self, rate_sum):
         """1 / (window mean of the per-chain total rate), one value per group."""
         out = self._dev((len(self.groups),))
+        _need(rate_sum, "rate_sum", (rate_sum.shape[0], len(self.groups)))
         rs = rate_sum.contiguous()
         self._enter()
         self._check(self.L.ra_mftu(self.ptr, _ptr(rs), rs.shape[0], _ptr(out)))

@@ -367,3 +367,16 @@ def test_errors_on_capacity_and_order():
     assert ei.value.code == ra.RA_EINVAL
     with pytest.raises(ra.RAError):
         rep.backward(None, None)
+    # the binding checks shapes and dtypes before a pointer reaches the C ABI
+    import torch
+    mean, _ = rep.average_forces()
+    for bad in (mean[:, :-1].contiguous(), mean.float(), mean[:1].reshape(-1)):
+        with pytest.raises(ValueError):
+            rep.bell_rates(bad, 1e-6, 0.1)
+    with pytest.raises(ValueError):
+        rep.average_forces(out=(mean[:1].clone(), mean.clone()))
+    with pytest.raises(ValueError):
+        rep.init_chains(torch.zeros(3 * 5 - 1, dtype=torch.float64, device=mean.device))
+    with pytest.raises(ValueError):
+        rep.mftu(torch.zeros(2, 3, dtype=torch.float64, device=mean.device))
+    rep.sync_status()
