@@ -108,7 +108,7 @@ typedef struct {
     uint64_t seed;              /* Philox key */
     int32_t  precision;         /* 32: FP32 state, FP64 averages; 64: all FP64 */
     int32_t  sample_every;      /* S >= 1: sample after every S-th step */
-    int32_t  max_windows;       /* capacity of the per-replica sample store */
+    int32_t  max_windows;       /* capacity of the per-replica sample store, 0..65535 */
     int32_t  tsf;               /* 1: also keep per-replica window time averages */
     int32_t  checkpoint_every;  /* K > 0 enables ra_backward (precision 32 only), keeping the
                                    state every K steps; RA_CKPT_AUTO: every step when the

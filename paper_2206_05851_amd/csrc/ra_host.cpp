@@ -101,6 +101,10 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
         why = "negative capacity";
         return RA_EINVAL;
     }
+    if (r->max_windows > 65535) {   // per-window kernels put the window on the grid's y dimension
+        why = "max_windows must be <= 65535";
+        return RA_EINVAL;
+    }
     if (r->checkpoint_every != 0 && (r->precision != 32 || r->plain)) {
         why = "the adjoint (checkpoint_every != 0) needs precision 32 and the fused path";
         return RA_EINVAL;
@@ -292,17 +296,9 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     // than the one-wave kernel with its software-pipelined noise.
     {
         bool fits = family == 4 && run->precision == 32 && !run->plain && !run->tsf;
-        int64_t items = 0;                      // wavefronts with one bead per lane
-        for (int i = 0; i < n_groups && fits; ++i) {
+        for (int i = 0; i < n_groups && fits; ++i)
             if (groups[i].n_beads > WAVE) fits = false;
-            else {
-                const int P = WAVE / groups[i].n_beads;
-                items += (groups[i].n_replicas + P - 1) / P;
-            }
-        }
-        const bool want = run->tile_policy == 3;
-        (void)items;
-        if (fits && want) {
+        if (fits && run->tile_policy == 3) {
             family = 1;
             for (int i = 0; i < n_groups; ++i) Ms[i] = 1;
         }

@@ -73,6 +73,7 @@ def _create(lib, desc_kw, run_kw):
     (dict(noise_scale=-1.0), {}, "noise_scale"),
     ({}, dict(precision=16), "precision"),
     ({}, dict(sample_every=0), "sample_every"),
+    ({}, dict(max_windows=65536), "max_windows"),
     ({}, dict(checkpoint_every=10, precision=64), "adjoint"),
     ({}, dict(checkpoint_every=10, plain=1), "adjoint"),
     ({}, dict(checkpoint_every=-1, precision=64), "adjoint"),
