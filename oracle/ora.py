@@ -58,6 +58,10 @@ def lib():
         L.rao_normals.argtypes = [ctypes.POINTER(ctypes.c_uint32), dp]
         L.rao_noise.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                 ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, dp]
+        L.rao_normals4.argtypes = [ctypes.POINTER(ctypes.c_uint32), dp]
+        L.rao_noise_mapped.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_int32, dp]
         L.rao_spring.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, dp, dp, dp, dp]
         L.rao_spring.restype = ctypes.c_int
@@ -84,6 +88,7 @@ def lib():
         L.ra_oracle_get_samples.argtypes = [P, dp, dp]
         L.ra_oracle_get_positions.argtypes = [P, dp]
         L.ra_oracle_set_tag.argtypes = [P, ctypes.c_uint32]
+        L.ra_oracle_set_noise_map.argtypes = [P, ctypes.c_int32]
         L.ra_oracle_reclone.argtypes = [P, dp]
         L.ra_oracle_rsf_cycle.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
         L.ra_oracle_block_sigma.argtypes = [P, ctypes.c_int32, dp]
@@ -126,9 +131,19 @@ def normals(words):
     return o
 
 
-def noise(seed, step, bead, replica, tag, group):
+def noise(seed, step, bead, replica, tag, group, noise_map=0):
     o = np.zeros(3)
-    lib().rao_noise(seed, step, bead, replica, tag, group, _dp(o))
+    if noise_map:
+        lib().rao_noise_mapped(seed, step, bead, replica, tag, group, noise_map, _dp(o))
+    else:
+        lib().rao_noise(seed, step, bead, replica, tag, group, _dp(o))
+    return o
+
+
+def normals4(words):
+    w = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in words])
+    o = np.zeros(4)
+    lib().rao_normals4(w, _dp(o))
     return o
 
 
@@ -202,7 +217,7 @@ def make_groups(descs):
 class Oracle:
     """Context mirroring the library's calls, on host numpy arrays."""
 
-    def __init__(self, descs, seed, sample_every, max_windows, tsf=False, tangents=False):
+    def __init__(self, descs, seed, sample_every, max_windows, tsf=False, tangents=False, noise_map=0):
         self.L = lib()
         self.descs = [dict(d) for d in descs]
         self._groups = make_groups(self.descs)
@@ -214,6 +229,8 @@ class Oracle:
             raise OracleError("ra_oracle_create failed: %d" % rc)
         self.sample_every = sample_every
         self.ranges = [(0, d["n_replicas"]) for d in descs]
+        if noise_map:
+            self._check(self.L.ra_oracle_set_noise_map(self.ptr, int(noise_map)), "set_noise_map")
 
     def _check(self, rc, what):
         if rc != 0:

@@ -61,6 +61,16 @@ void rao_normals(const uint32_t x[4], double xi[3])
     xi[2] = r1 * cos(two_pi * u3);
 }
 
+/* Box-Muller with both outputs of the second pair: xi[3] = r1 sin(2 pi u3),
+ * the normal rao_normals leaves out (independent of the other three). */
+void rao_normals4(const uint32_t x[4], double xi[4])
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    rao_normals(x, xi);
+    double r1 = sqrt(-2.0 * log(rao_uniform(x[2])));
+    xi[3] = r1 * sin(two_pi * rao_uniform(x[3]));
+}
+
 /* Counter layout: (step, bead-or-spring, replica, tag<<24 | group);
  * key = (seed low 32 bits, seed high 32 bits). Each replica gets its own
  * stream through the replica word, which plays the role of the paper's
@@ -73,6 +83,30 @@ void rao_noise(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
     uint32_t x[4];
     rao_philox4x32_10(ctr, key, x);
     rao_normals(x, xi);
+}
+
+/* The per-bead normals of one step under a noise map. Map 0: one Philox
+ * block per (step, bead), rao_noise. Map 1: the block of step n gives four
+ * normals; steps n = 4m, 4m+1, 4m+2 take the first three of their own block,
+ * and step 4m+3 takes the fourth normals of the blocks of steps 4m, 4m+1 and
+ * 4m+2 (x, y, z in that order). Every step still gets three independent
+ * standard normals, from three blocks per four steps. */
+void rao_noise_mapped(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
+                      uint32_t tag, uint32_t group, int32_t map, double xi[3])
+{
+    if (map == 0 || step % 4u != 3u) {
+        rao_noise(seed, step, bead, replica, tag, group, xi);
+        return;
+    }
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    for (uint32_t q = 0; q < 3; ++q) {
+        uint32_t ctr[4] = { step - 3u + q, bead, replica, (tag << 24) | (group & 0xFFFFFFu) };
+        uint32_t x[4];
+        double four[4];
+        rao_philox4x32_10(ctr, key, x);
+        rao_normals4(x, four);
+        xi[q] = four[3];
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -214,6 +248,7 @@ struct rao_ctx {
     int64_t* clamps;       /* per group */
     double*  src;          /* [g][i][3] conformation the replicas were last cloned from */
     uint32_t tag;          /* noise tag of this context's trajectories */
+    int32_t  noise_map;    /* 0 or 1, see rao_noise_mapped */
     int64_t  step;         /* steps taken since init */
     int64_t  n_windows;
     int      initialised;
@@ -383,6 +418,13 @@ int ra_oracle_set_tag(rao_ctx* c, uint32_t tag)
     return RAO_OK;
 }
 
+int ra_oracle_set_noise_map(rao_ctx* c, int32_t map)
+{
+    if (!c || (map != 0 && map != 1)) return fail(c, RAO_EINVAL, "noise map must be 0 or 1");
+    c->noise_map = map;
+    return RAO_OK;
+}
+
 /* RSF re-clone (Sec. II): at a force-sampling time the parent is halted and
  * every replica restarts from its current conformation. The replicas keep
  * their step count, a multiple of S, so the replicas of each window draw their
@@ -491,7 +533,7 @@ static int hi_update(rao_ctx* c, const rao_group* d, int k, uint32_t n, double* 
         double v[3];
         rao_flow_velocity(d->flow, d->rate, r + 3 * i, v);
         for (int x = 0; x < 3; ++x) step[3 * i + x] += d->dt * v[x];
-        rao_noise(c->seed, n, (uint32_t)i, (uint32_t)k, c->tag, d->stream_id, xi + 3 * i);
+        rao_noise_mapped(c->seed, n, (uint32_t)i, (uint32_t)k, c->tag, d->stream_id, c->noise_map, xi + 3 * i);
     }
     if (rao_cholesky(n3, D) != 0) {
         free(step);
@@ -570,7 +612,7 @@ static int em_step_replica(rao_ctx* c, int g, int kk, uint32_t n,
     /* position update */
     for (int i = 0; i < N; ++i) {
         double xi[3], v[3];
-        rao_noise(c->seed, n, (uint32_t)i, (uint32_t)k, c->tag, d->stream_id, xi);
+        rao_noise_mapped(c->seed, n, (uint32_t)i, (uint32_t)k, c->tag, d->stream_id, c->noise_map, xi);
         rao_flow_velocity(d->flow, d->rate, r + 3 * i, v);
         if (c->tangents) {
             for (int p = 0; p < 3; ++p) {

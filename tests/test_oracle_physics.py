@@ -98,12 +98,15 @@ def test_centre_of_mass_moves_with_flow_only():
 
 
 # ---- stochastic Hookean dynamics: exact EM moments -------------------------------
-@pytest.mark.parametrize("flow,rate", [(ora.UNIAXIAL, 0.5), (ora.SHEAR, 4.0)])
-def test_hookean_moments_match_exact_em_recursion(flow, rate):
+@pytest.mark.parametrize("flow,rate,noise_map", [(ora.UNIAXIAL, 0.5, 0), (ora.SHEAR, 4.0, 0),
+                                                (ora.UNIAXIAL, 0.5, 1), (ora.SHEAR, 4.0, 1)])
+def test_hookean_moments_match_exact_em_recursion(flow, rate, noise_map):
+    # the exact recursion holds only for independent standard normals at
+    # every (step, bead, component): both noise maps must give them
     N, R, dt, H, kT, zeta, n = 6, 4000, 1e-2, 1.0, 1.0, 1.0, 150
     parent = wl.equilibrium_parent(N, seed=3)
     o = ora.Oracle([g(N, R, dt, H=H, kT=kT, zeta=zeta, flow=flow, rate=rate)], seed=42,
-                   sample_every=50, max_windows=10)
+                   sample_every=50, max_windows=10, noise_map=noise_map)
     o.init_chains([parent])
     o.step(n)
     Q = cf.bonds_of(o.positions()[0])                  # [R, 3(N-1)]

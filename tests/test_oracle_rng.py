@@ -132,3 +132,48 @@ def test_noise_streams_differ_by_every_counter_word():
     for args in [(6, 10, 20, 30, 0, 40), (5, 11, 20, 30, 0, 40), (5, 10, 21, 30, 0, 40),
                  (5, 10, 20, 31, 0, 40), (5, 10, 20, 30, 1, 40), (5, 10, 20, 30, 0, 41)]:
         assert not np.allclose(ora.noise(*args), base)
+
+
+def _fourth_normal_py(words):
+    # r1 sin(2 pi u3) from the word map and Box-Muller written out with math
+    import math
+    u2 = ((words[2] >> 9) + 0.5) * 2.0 ** -23
+    u3 = ((words[3] >> 9) + 0.5) * 2.0 ** -23
+    return math.sqrt(-2.0 * math.log(u2)) * math.sin(2.0 * math.pi * u3)
+
+
+def test_noise_map_one_definition():
+    # map 1: steps 4m..4m+2 keep the first three normals of their own block;
+    # step 4m+3 takes the fourth normals of the blocks of steps 4m, 4m+1, 4m+2
+    seed = 0x0123456789ABCDEF
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        m = int(rng.integers(0, 2 ** 28))
+        bead, rep, grp = (int(v) for v in rng.integers(0, 1000, size=3))
+        tag = int(rng.integers(0, 2))
+        for r in range(3):
+            a = ora.noise(seed, 4 * m + r, bead, rep, tag, grp, noise_map=1)
+            assert np.array_equal(a, ora.noise(seed, 4 * m + r, bead, rep, tag, grp))
+        got = ora.noise(seed, 4 * m + 3, bead, rep, tag, grp, noise_map=1)
+        ref = [_fourth_normal_py(philox_py((4 * m + q, bead, rep, (tag << 24) | grp), key)) for q in range(3)]
+        assert np.allclose(got, ref, rtol=1e-13, atol=1e-13)
+        # the fourth normal is the one normals() leaves out
+        w = ora.philox((4 * m, bead, rep, (tag << 24) | grp), key)
+        four = ora.normals4(w)
+        assert np.array_equal(four[:3], ora.normals(w))
+        assert np.isclose(four[3], ref[0], rtol=1e-13, atol=1e-13)
+
+
+def test_fourth_normals_are_standard_and_independent_of_the_third():
+    # (r1 cos 2 pi u3, r1 sin 2 pi u3) is a Box-Muller pair: both N(0,1),
+    # uncorrelated, and their squares sum to r1^2 ~ Exp(mean 2)
+    key = (11, 22)
+    n = 40000
+    third, fourth = np.empty(n), np.empty(n)
+    for i in range(n):
+        four = ora.normals4(ora.philox((i, 7, 3, 0), key))
+        third[i], fourth[i] = four[2], four[3]
+    assert stats.kstest(fourth, "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(third, fourth)[0, 1]) < 4.5 / np.sqrt(n)
+    assert stats.kstest(third ** 2 + fourth ** 2, "expon", args=(0, 2.0)).pvalue > 1e-3
