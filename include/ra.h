@@ -122,7 +122,12 @@ typedef struct {
                                    where legal; 1000 + m: force m beads per lane */
     int32_t  waves_per_block;   /* 0 = default (4) */
     int32_t  noise_tag;         /* 0: replica noise; 1: parent trajectory (RSF cycle, Sec. II) */
-    int32_t  reserved_;         /* must be 0 */
+    int32_t  noise_map;         /* 0: one Philox block per (step, bead), three normals;
+                                   1: each block gives four normals (both of Box-Muller's
+                                   second pair): steps 4m..4m+2 use the first three of
+                                   their own block, step 4m+3 the fourth normals of those
+                                   three blocks (three blocks per four steps). Chain
+                                   model only, at most 4 beads per lane (FP32 N <= 256) */
 } ra_run_desc;
 
 /* Create a context: validates every descriptor (RA_EINVAL with nothing

@@ -159,7 +159,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <int M, bool FENE>
+template <int M, bool FENE, int NMAP>
 __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G, int item, int k_first) {
     // kernel arguments into locals (the loops must not address the argument block)
     const int S = a.S, K = a.K;
@@ -191,7 +191,15 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
         load_lane<float, M>(qn, valid, cp, G, tg);
         kc = slot_coef<float, M>(G, valid);
         s = qn;
-        em_step<float, M, FENE>(s, G, valid, kc, (uint32_t)(n_end - 1), (uint32_t)tg.j0, (uint32_t)tg.k, keys, dummy);
+        if constexpr (NMAP == 1) {
+            Carry<float, M> cy;
+            init_carry<float, M>(cy, G, (uint32_t)(n_end - 1), (uint32_t)tg.j0, (uint32_t)tg.k, keys);
+            em_step_map1<float, M, FENE>(s, cy, G, valid, kc, (uint32_t)(n_end - 1), (uint32_t)tg.j0, (uint32_t)tg.k,
+                                         keys, dummy);
+        } else {
+            em_step<float, M, FENE>(s, G, valid, kc, (uint32_t)(n_end - 1), (uint32_t)tg.j0, (uint32_t)tg.k, keys,
+                                    dummy);
+        }
         int rr = (int)(n_end % S);
         int w = (int)(n_end / S) - 1;
         for (int n = (int)n_end - 1; n >= 0; --n) {
@@ -220,10 +228,21 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
         load_lane<float, M>(s, valid, ckpt + (int64_t)sgi * state_total, G, tg);
         kc = slot_coef<float, M>(G, valid);
         float* wp = seg;
-        for (int n = s0; n < s1; ++n) {
-            seg_store<M>(wp, 0, s, lane);
-            wp += STRIDE;
-            em_step<float, M, FENE>(s, G, valid, kc, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, keys, dummy);
+        if constexpr (NMAP == 1) {
+            Carry<float, M> cy;
+            init_carry<float, M>(cy, G, (uint32_t)s0, (uint32_t)tg.j0, (uint32_t)tg.k, keys);
+            for (int n = s0; n < s1; ++n) {
+                seg_store<M>(wp, 0, s, lane);
+                wp += STRIDE;
+                em_step_map1<float, M, FENE>(s, cy, G, valid, kc, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, keys,
+                                             dummy);
+            }
+        } else {
+            for (int n = s0; n < s1; ++n) {
+                seg_store<M>(wp, 0, s, lane);
+                wp += STRIDE;
+                em_step<float, M, FENE>(s, G, valid, kc, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, keys, dummy);
+            }
         }
         // s = Q^{s1}; sweep n = s1-1 .. s0, injecting at states n+1 that were sampled.
         // rr = (n + 1) mod S, w = window of state n + 1 when rr == 0
@@ -265,7 +284,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
 
 // One kernel per beads-per-lane M, launched over the contiguous range of the
 // (M-sorted) work list that uses it, so each M gets its own register budget.
-template <int M>
+template <int M, int NMAP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M <= 2 ? 4 : 1)))
 void adjoint_kernel(AdjArgs a, int item_begin, int item_end) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -277,11 +296,12 @@ void adjoint_kernel(AdjArgs a, int item_begin, int item_end) {
         // the group's constants as a local value: read through the reference,
         // the recompute loop re-loads them from memory every step
         const GroupDev Gl = G;
-        if (Gl.spring == 1) run_adjoint<M, true>(a, Gl, item, it.k0);
-        else run_adjoint<M, false>(a, Gl, item, it.k0);
-    } else {
-        if (G.spring == 1) run_adjoint<M, true>(a, G, item, it.k0);
-        else run_adjoint<M, false>(a, G, item, it.k0);
+        if (Gl.spring == 1) run_adjoint<M, true, NMAP>(a, Gl, item, it.k0);
+        else run_adjoint<M, false, NMAP>(a, Gl, item, it.k0);
+    } else {   // noise map 1 is not compiled for wider lanes (rejected on the host)
+        static_assert(NMAP == 0, "noise map 1 is compiled for 1-4 beads per lane");
+        if (G.spring == 1) run_adjoint<M, true, 0>(a, G, item, it.k0);
+        else run_adjoint<M, false, 0>(a, G, item, it.k0);
     }
 }
 
@@ -333,22 +353,32 @@ __global__ __launch_bounds__(GR_THREADS) void grad_reduce_kernel(const int32_t* 
     if (t < 3) grad[3 * g + t] = sh[t][0];
 }
 
-hipError_t launch_adjoint(const AdjArgs& a, int M, int item_begin, int item_end, int waves_per_block,
+hipError_t launch_adjoint(const AdjArgs& a, int M, int item_begin, int item_end, int waves_per_block, int nmap,
                           hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     const int n = item_end - item_begin;
     if (n <= 0) return hipSuccess;
     const int wpb = waves_per_block;
     dim3 grid((n + wpb - 1) / wpb), block(WAVE * wpb);
+    if (nmap == 1) {
+        switch (M) {
+        case 1: hipLaunchKernelGGL((adjoint_kernel<1, 1>), grid, block, 0, st, a, item_begin, item_end); break;
+        case 2: hipLaunchKernelGGL((adjoint_kernel<2, 1>), grid, block, 0, st, a, item_begin, item_end); break;
+        case 3: hipLaunchKernelGGL((adjoint_kernel<3, 1>), grid, block, 0, st, a, item_begin, item_end); break;
+        case 4: hipLaunchKernelGGL((adjoint_kernel<4, 1>), grid, block, 0, st, a, item_begin, item_end); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (M) {
-    case 1: hipLaunchKernelGGL(adjoint_kernel<1>, grid, block, 0, st, a, item_begin, item_end); break;
-    case 2: hipLaunchKernelGGL(adjoint_kernel<2>, grid, block, 0, st, a, item_begin, item_end); break;
-    case 3: hipLaunchKernelGGL(adjoint_kernel<3>, grid, block, 0, st, a, item_begin, item_end); break;
-    case 4: hipLaunchKernelGGL(adjoint_kernel<4>, grid, block, 0, st, a, item_begin, item_end); break;
-    case 6: hipLaunchKernelGGL(adjoint_kernel<6>, grid, block, 0, st, a, item_begin, item_end); break;
-    case 8: hipLaunchKernelGGL(adjoint_kernel<8>, grid, block, 0, st, a, item_begin, item_end); break;
-    case 12: hipLaunchKernelGGL(adjoint_kernel<12>, grid, block, 0, st, a, item_begin, item_end); break;
-    case 16: hipLaunchKernelGGL(adjoint_kernel<16>, grid, block, 0, st, a, item_begin, item_end); break;
+    case 1: hipLaunchKernelGGL((adjoint_kernel<1, 0>), grid, block, 0, st, a, item_begin, item_end); break;
+    case 2: hipLaunchKernelGGL((adjoint_kernel<2, 0>), grid, block, 0, st, a, item_begin, item_end); break;
+    case 3: hipLaunchKernelGGL((adjoint_kernel<3, 0>), grid, block, 0, st, a, item_begin, item_end); break;
+    case 4: hipLaunchKernelGGL((adjoint_kernel<4, 0>), grid, block, 0, st, a, item_begin, item_end); break;
+    case 6: hipLaunchKernelGGL((adjoint_kernel<6, 0>), grid, block, 0, st, a, item_begin, item_end); break;
+    case 8: hipLaunchKernelGGL((adjoint_kernel<8, 0>), grid, block, 0, st, a, item_begin, item_end); break;
+    case 12: hipLaunchKernelGGL((adjoint_kernel<12, 0>), grid, block, 0, st, a, item_begin, item_end); break;
+    case 16: hipLaunchKernelGGL((adjoint_kernel<16, 0>), grid, block, 0, st, a, item_begin, item_end); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

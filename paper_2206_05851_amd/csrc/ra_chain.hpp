@@ -79,6 +79,75 @@ __device__ __forceinline__ void gen_noise(Noise<T, M>& e, const GroupDev& G, uin
     }
 }
 
+// Noise map 1: the block of step n gives four normals; steps 4m..4m+2 use the
+// first three of their own block, step 4m+3 the fourth normals of the blocks
+// of steps 4m, 4m+1, 4m+2 (as x, y, z). Three blocks serve four steps, and
+// every step still gets three independent standard normals. The fourth
+// normals wait in a per-slot carry until step 4m+3.
+template <typename T, int M> struct Carry {
+    T c0[M], c1[M], c2[M];
+};
+
+// Normals of step n under map 1, updating the carry (r = n mod 4 is
+// wave-uniform, so the branch is uniform and the carry slot a select).
+template <typename T, int M>
+__device__ __forceinline__ void gen_noise_map1(Noise<T, M>& e, Carry<T, M>& cy, const GroupDev& G, uint32_t n,
+                                               uint32_t bead0, uint32_t replica, const RoundKeys& keys) {
+    const uint32_t r = n & 3u;
+    if (r == 3u) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            e.x[m] = cy.c0[m];
+            e.y[m] = cy.c1[m];
+            e.z[m] = cy.c2[m];
+        }
+        return;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        T d;
+        normals4(philox10(n, bead0 + (uint32_t)m, replica, G.stream, keys), e.x[m], e.y[m], e.z[m], d);
+        cy.c0[m] = r == 0u ? d : cy.c0[m];
+        cy.c1[m] = r == 1u ? d : cy.c1[m];
+        cy.c2[m] = r == 2u ? d : cy.c2[m];
+    }
+}
+
+// Carry for a run that starts at step n: the fourth normals of the blocks of
+// steps 4m .. n-1 of n's group of four (none when n is a multiple of 4).
+template <typename T, int M>
+__device__ __forceinline__ void init_carry(Carry<T, M>& cy, const GroupDev& G, uint32_t n, uint32_t bead0,
+                                           uint32_t replica, const RoundKeys& keys) {
+    const uint32_t r = n & 3u;
+#pragma unroll
+    for (int m = 0; m < M; ++m) cy.c0[m] = cy.c1[m] = cy.c2[m] = (T)0;
+    for (uint32_t q = 0; q < r; ++q) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            T a, b, c, d;
+            normals4(philox10(n - r + q, bead0 + (uint32_t)m, replica, G.stream, keys), a, b, c, d);
+            cy.c0[m] = q == 0u ? d : cy.c0[m];
+            cy.c1[m] = q == 1u ? d : cy.c1[m];
+            cy.c2[m] = q == 2u ? d : cy.c2[m];
+        }
+    }
+}
+
+// Map 1, four steps n..n+3 with n a multiple of 4: three blocks per slot.
+template <typename T, int M>
+__device__ __forceinline__ void gen_noise4_map1(Noise<T, M> (&e)[4], const GroupDev& G, uint32_t n, uint32_t bead0,
+                                                uint32_t replica, const RoundKeys& keys) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        normals4(philox10(n, bead0 + (uint32_t)m, replica, G.stream, keys), e[0].x[m], e[0].y[m], e[0].z[m],
+                 e[3].x[m]);
+        normals4(philox10(n + 1u, bead0 + (uint32_t)m, replica, G.stream, keys), e[1].x[m], e[1].y[m], e[1].z[m],
+                 e[3].y[m]);
+        normals4(philox10(n + 2u, bead0 + (uint32_t)m, replica, G.stream, keys), e[2].x[m], e[2].y[m], e[2].z[m],
+                 e[3].z[m]);
+    }
+}
+
 // G_j = g_j Q_j of slot m (spring factor evaluated once per slot and step).
 template <typename T, int M, bool FENE>
 __device__ __forceinline__ void slot_force(const Lane<T, M>& s, const GroupDev& G, int m, T& fx, T& fy, T& fz,
@@ -212,6 +281,16 @@ __device__ __forceinline__ void em_step(Lane<T, M>& s, const GroupDev& G, const 
             normals3(philox10(n, bead0 + (uint32_t)m, replica, G.stream, keys), x, y, z);
         },
         G, valid, kc, clamps);
+}
+
+// One step at global step n under map 1 (noise from and into the carry).
+template <typename T, int M, bool FENE>
+__device__ __forceinline__ void em_step_map1(Lane<T, M>& s, Carry<T, M>& cy, const GroupDev& G,
+                                             const bool (&valid)[M], const SlotCoef<T, M>& kc, uint32_t n,
+                                             uint32_t bead0, uint32_t replica, const RoundKeys& keys, int& clamps) {
+    Noise<T, M> e;
+    gen_noise_map1<T, M>(e, cy, G, n, bead0, replica, keys);
+    physics_step<T, M, FENE>(s, e, G, valid, kc, clamps);
 }
 
 // Tension f_j = H g_j |Q_j| (Eq. 4, zero rest length) of every slot.

@@ -99,6 +99,30 @@ __device__ __forceinline__ void normals3(const Words& w, float& a, float& b, flo
     b = r0 * __builtin_amdgcn_sinf(u1);
     c = r1 * __builtin_amdgcn_cosf(u3);
 }
+// The same with the second pair's other output, d = r1 sin 2 pi u3 (noise map 1).
+__device__ __forceinline__ void normals4(const Words& w, float& a, float& b, float& c, float& d) {
+    const float m2ln2 = -1.3862943611198906f;
+    const float u0 = u01_f32(w.x), u1 = u01_f32(w.y), u2 = u01_f32(w.z), u3 = u01_f32(w.w);
+    const float r0 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+    const float r1 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
+    a = r0 * __builtin_amdgcn_cosf(u1);
+    b = r0 * __builtin_amdgcn_sinf(u1);
+    c = r1 * __builtin_amdgcn_cosf(u3);
+    d = r1 * __builtin_amdgcn_sinf(u3);
+}
+__device__ __forceinline__ void normals4(const Words& w, double& a, double& b, double& c, double& d) {
+    const double u0 = u01_f64(w.x), u1 = u01_f64(w.y), u2 = u01_f64(w.z), u3 = u01_f64(w.w);
+    const double r0 = sqrt(-2.0 * log(u0));
+    const double r1 = sqrt(-2.0 * log(u2));
+    double s1, c1, s3, c3;
+    sincospi(2.0 * u1, &s1, &c1);
+    sincospi(2.0 * u3, &s3, &c3);
+    a = r0 * c1;
+    b = r0 * s1;
+    c = r1 * c3;
+    d = r1 * s3;
+}
+
 __device__ __forceinline__ void normals3(const Words& w, double& a, double& b, double& c) {
     const double u0 = u01_f64(w.x), u1 = u01_f64(w.y), u2 = u01_f64(w.z), u3 = u01_f64(w.w);
     const double r0 = sqrt(-2.0 * log(u0));

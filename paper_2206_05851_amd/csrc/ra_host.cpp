@@ -110,7 +110,7 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
         return RA_EINVAL;
     }
     if (r->noise_tag != 0 && r->noise_tag != 1) { why = "noise_tag must be 0 or 1"; return RA_EINVAL; }
-    if (r->reserved_ != 0) { why = "reserved_ must be 0"; return RA_EINVAL; }
+    if (r->noise_map != 0 && r->noise_map != 1) { why = "noise_map must be 0 or 1"; return RA_EINVAL; }
     const int wpb = r->waves_per_block ? r->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4) { why = "waves_per_block must be 0, 1, 2 or 4"; return RA_EINVAL; }
     int n_pair = 0, n_hi = 0;
@@ -130,6 +130,10 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
     }
     if ((n_pair > 0 || n_hi > 0) && r->checkpoint_every != 0) {
         why = "the adjoint covers the free-draining Hookean and FENE chain model only";
+        return RA_EINVAL;
+    }
+    if ((n_pair > 0 || n_hi > 0) && r->noise_map != 0) {
+        why = "noise_map 1 covers the free-draining Hookean and FENE chain model only";
         return RA_EINVAL;
     }
     if ((n_pair > 0 || n_hi > 0) && r->plain) {
@@ -163,8 +167,9 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
     return RA_OK;
 }
 
-GroupDev make_group(const ra_chain_desc& d, int M, int tag) {
+GroupDev make_group(const ra_chain_desc& d, int M, int tag, int nmap) {
     GroupDev G{};
+    G.nmap = nmap;
     G.N = d.n_beads;
     G.R = d.n_replicas;
     G.M = M;
@@ -295,7 +300,7 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     // (tile_policy 3); on the 1024-replica, 50-bead workload it measured slower
     // than the one-wave kernel with its software-pipelined noise.
     {
-        bool fits = family == 4 && run->precision == 32 && !run->plain && !run->tsf;
+        bool fits = family == 4 && run->precision == 32 && !run->plain && !run->tsf && run->noise_map == 0;
         for (int i = 0; i < n_groups && fits; ++i)
             if (groups[i].n_beads > WAVE) fits = false;
         if (fits && run->tile_policy == 3) {
@@ -304,12 +309,16 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
         }
     }
     c->family = family;
+    if (run->noise_map != 0 && !run->plain && family != 4) {
+        ra_destroy(c);
+        return fail(nullptr, RA_EINVAL, "noise_map 1 needs at most 4 beads per lane (n_beads <= 256) on the fused path");
+    }
 
     // layout
     std::vector<int64_t> par_off(n_groups);
     int64_t par = 0;
     for (int i = 0; i < n_groups; ++i) {
-        GroupDev G = make_group(groups[i], Ms[i], run->noise_tag);
+        GroupDev G = make_group(groups[i], Ms[i], run->noise_tag, run->noise_map);
         if (hi) G.P = 1;   // one replica per workgroup
         const int64_t nm1 = G.N - 1;
         G.state_off = c->state_total;
@@ -499,7 +508,7 @@ static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps, hipStream_t st) {
         if (c->family == 1) HIPCHK(c, launch_forward_split(a, st));
         else if (c->family == 2) HIPCHK(c, launch_forward_pair(a, c->run.precision, c->wpb, st));
         else if (c->family == 3) HIPCHK(c, launch_forward_hi(a, c->run.precision, c->hi_nmax, st));
-        else HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, st));
+        else HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->run.noise_map, st));
         HIPCHK(c, launch_advance(c->dstep, a.n_steps, st));
     }
     return RA_OK;
@@ -518,7 +527,7 @@ static ra_status enqueue_forward_dual(ra_ctx* ca, int64_t n_a, ra_ctx* cb, int64
     if (ca->family == 2) HIPCHK(ca, launch_forward_pair_dual(a, b, ca->run.precision, ca->wpb, st));
     else if (ca->family == 3)
         HIPCHK(ca, launch_forward_hi_dual(a, b, ca->run.precision, std::max(ca->hi_nmax, cb->hi_nmax), st));
-    else HIPCHK(ca, launch_forward_dual(a, b, ca->run.precision, ca->family, ca->wpb, st));
+    else HIPCHK(ca, launch_forward_dual(a, b, ca->run.precision, ca->family, ca->wpb, ca->run.noise_map, st));
     HIPCHK(ca, launch_advance2(ca->dstep, n_a, cb->dstep, n_b, st));
     return RA_OK;
 }
@@ -654,7 +663,7 @@ ra_status ra_backward(ra_ctx* c, const double* mean, const double* grad_mean, co
         const int M = c->hgroups[c->hitems[b].g].M;
         size_t e = b;
         while (e < c->hitems.size() && c->hgroups[c->hitems[e].g].M == M) ++e;
-        HIPCHK(c, launch_adjoint(a, M, (int)b, (int)e, c->wpb, c->stream));
+        HIPCHK(c, launch_adjoint(a, M, (int)b, (int)e, c->wpb, c->run.noise_map, c->stream));
         b = e;
     }
     HIPCHK(c, launch_grad_reduce(c->ditem_begin, ng, c->partial, grad_params, c->stream));
@@ -725,6 +734,7 @@ ra_status ra_rsf_cycle(ra_ctx* c, ra_ctx* parent, int64_t n_windows, int64_t par
     // the replicas' window w (fwd_dual_kernel and its pair/HI forms), all on
     // the replicas' stream, so the two overlap on any queue mapping.
     const bool dual = n_windows > 0 && c->family == parent->family && c->wpb == parent->wpb &&
+                      c->run.noise_map == parent->run.noise_map &&
                       (c->family == 2 || c->family == 3 || c->family == 4 || c->family == 16) &&
                       S <= (1 << 30) && parent_steps <= (1 << 30);
     if (dual) {

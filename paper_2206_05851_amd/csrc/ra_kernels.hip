@@ -26,7 +26,7 @@ template <int M> struct RunAhead { static constexpr int U = M == 1 ? 4 : (M == 2
 // cut into segments between events (window end, checkpoint), so the inner
 // loop holds nothing but noise generation and the bond update (plus the
 // per-step tension sum when TSF is on).
-template <typename T, int M, bool FENE, bool UNIFORM_K, bool TSF>
+template <typename T, int M, bool FENE, bool UNIFORM_K, bool TSF, int NMAP>
 __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDev& G, int gidx, int k_first,
                                                  int64_t n0_64) {
     constexpr int U = RunAhead<M>::U;
@@ -90,7 +90,49 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
             for (int m = 0; m < M; ++m) tpart[m] += f[m];
         }
     };
+    // noise map 1: with one bead per lane the steps run in aligned groups of
+    // four (three blocks generated ahead, as in the pipeline below); a run's
+    // unaligned head and its tail, and wider lanes, take the carry step by
+    // step. The carry lives for the whole launch (built once for its first
+    // step): segments follow each other in step order, an aligned group
+    // neither needs nor changes it, and a partial group is always stepped
+    // through the carry, so it holds the current group's fourth normals.
+    [[maybe_unused]] Carry<T, M> cy;
+    if constexpr (NMAP == 1) init_carry<T, M>(cy, G, n0, bead0, rep, keys);
+    auto run_steps_map1 = [&](uint32_t n, int len) {
+        int i = 0;
+        if constexpr (M == 1) {
+            for (; i < len && ((n + (uint32_t)i) & 3u) != 0u; ++i) {
+                em_step_map1<T, M, FENE>(s, cy, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps);
+                accumulate_tsf();
+            }
+            if (i + 4 <= len) {
+                Noise<T, M> e[4];
+                gen_noise4_map1<T, M>(e, G, n + (uint32_t)i, bead0, rep, keys);
+                for (; i + 4 <= len; i += 4) {
+                    asm volatile(".p2align 6");
+                    Noise<T, M> f[4];
+                    gen_noise4_map1<T, M>(f, G, n + (uint32_t)(i + 4), bead0, rep, keys);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        physics_step<T, M, FENE>(s, e[u], G, valid, kc, clamps);
+                        accumulate_tsf();
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) e[u] = f[u];
+                }
+            }
+        }
+        for (; i < len; ++i) {   // starts aligned after the groups, so the carry is refilled before use
+            em_step_map1<T, M, FENE>(s, cy, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps);
+            accumulate_tsf();
+        }
+    };
     auto run_steps = [&](uint32_t n, int len) {   // len steps starting at global step n
+        if constexpr (NMAP == 1) {
+            run_steps_map1(n, len);
+            return;
+        }
         int i = 0;
         if constexpr (U > 1) {
             // software pipeline: the noise of block b+1 is generated in the same
@@ -173,31 +215,35 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
 // once: read through the reference, the step loop re-loads them from memory
 // every iteration (measured: one extra vector load per step). Wider lanes keep
 // the reference, as the copy would not fit their register budget.
-template <typename T, int M, bool FENE, bool UNIFORM_K, bool TSF>
+// Noise map 1 is compiled for 1-4 beads per lane only (the host rejects it
+// for wider lanes, whose register budget has no room for the carry), in
+// kernels of its own, so each map gets its own register allocation.
+template <typename T, int M, bool FENE, bool UNIFORM_K, bool TSF, int NMAP>
 __device__ __forceinline__ void run_forward(const FwdArgs& a, const GroupDev& Gm, int k_first, int64_t n0_64) {
     const int gidx = (int)(&Gm - a.groups);
     if constexpr (M <= 4) {
         const GroupDev G = Gm;
-        run_forward_impl<T, M, FENE, UNIFORM_K, TSF>(a, G, gidx, k_first, n0_64);
+        run_forward_impl<T, M, FENE, UNIFORM_K, TSF, NMAP>(a, G, gidx, k_first, n0_64);
     } else {
-        run_forward_impl<T, M, FENE, UNIFORM_K, TSF>(a, Gm, gidx, k_first, n0_64);
+        static_assert(NMAP == 0, "noise map 1 is compiled for 1-4 beads per lane");
+        run_forward_impl<T, M, FENE, UNIFORM_K, TSF, 0>(a, Gm, gidx, k_first, n0_64);
     }
 }
 
-template <typename T, int M>
+template <typename T, int M, int NMAP>
 __device__ __forceinline__ void dispatch_spring(const FwdArgs& a, const GroupDev& G, int k_first, int64_t n0) {
     const bool tsf = a.tsf != nullptr;
     if constexpr (sizeof(T) == 8) {           // FP64 correctness path: fewer variants
         if (G.spring == 1) {
-            if (tsf) run_forward<T, M, true, false, true>(a, G, k_first, n0);
-            else run_forward<T, M, true, false, false>(a, G, k_first, n0);
+            if (tsf) run_forward<T, M, true, false, true, NMAP>(a, G, k_first, n0);
+            else run_forward<T, M, true, false, false, NMAP>(a, G, k_first, n0);
         } else {
-            if (tsf) run_forward<T, M, false, false, true>(a, G, k_first, n0);
-            else run_forward<T, M, false, false, false>(a, G, k_first, n0);
+            if (tsf) run_forward<T, M, false, false, true, NMAP>(a, G, k_first, n0);
+            else run_forward<T, M, false, false, false, NMAP>(a, G, k_first, n0);
         }
     } else {
         const bool uk = G.P == 1;
-#define RA_FWD(FENE_, UK_, TSF_) run_forward<T, M, FENE_, UK_, TSF_>(a, G, k_first, n0)
+#define RA_FWD(FENE_, UK_, TSF_) run_forward<T, M, FENE_, UK_, TSF_, NMAP>(a, G, k_first, n0)
         if (G.spring == 1) {
             if (uk) { if (tsf) RA_FWD(true, true, true); else RA_FWD(true, true, false); }
             else { if (tsf) RA_FWD(true, false, true); else RA_FWD(true, false, false); }
@@ -213,7 +259,7 @@ __device__ __forceinline__ void dispatch_spring(const FwdArgs& a, const GroupDev
 // VGPRs); family 16 is held to 2 resident waves per SIMD (256 registers), which
 // it fits without spilling — left alone the scheduler hoists all 16 Philox
 // chains and falls to 1 wave, and asking for 3-4 waves makes it spill.
-template <typename T, int FAMILY>
+template <typename T, int FAMILY, int NMAP>
 __device__ __forceinline__ void fwd_item(const FwdArgs& a, int item) {
     if (item >= a.n_items) return;
     if (*(const volatile int*)a.status & 1) return;   // invalid parent: no work
@@ -222,41 +268,41 @@ __device__ __forceinline__ void fwd_item(const FwdArgs& a, int item) {
     const int64_t n0 = *a.step0;
     if constexpr (FAMILY == 4) {
         switch (G.M) {
-        case 1: dispatch_spring<T, 1>(a, G, it.k0, n0); break;
-        case 2: dispatch_spring<T, 2>(a, G, it.k0, n0); break;
-        case 3: dispatch_spring<T, 3>(a, G, it.k0, n0); break;
-        case 4: dispatch_spring<T, 4>(a, G, it.k0, n0); break;
+        case 1: dispatch_spring<T, 1, NMAP>(a, G, it.k0, n0); break;
+        case 2: dispatch_spring<T, 2, NMAP>(a, G, it.k0, n0); break;
+        case 3: dispatch_spring<T, 3, NMAP>(a, G, it.k0, n0); break;
+        case 4: dispatch_spring<T, 4, NMAP>(a, G, it.k0, n0); break;
         default: break;
         }
     } else {
         switch (G.M) {
-        case 6: dispatch_spring<T, 6>(a, G, it.k0, n0); break;
-        case 8: dispatch_spring<T, 8>(a, G, it.k0, n0); break;
-        case 12: dispatch_spring<T, 12>(a, G, it.k0, n0); break;
-        case 16: dispatch_spring<T, 16>(a, G, it.k0, n0); break;
+        case 6: dispatch_spring<T, 6, 0>(a, G, it.k0, n0); break;
+        case 8: dispatch_spring<T, 8, 0>(a, G, it.k0, n0); break;
+        case 12: dispatch_spring<T, 12, 0>(a, G, it.k0, n0); break;
+        case 16: dispatch_spring<T, 16, 0>(a, G, it.k0, n0); break;
         default: break;
         }
     }
 }
 
-template <typename T, int FAMILY, int WAVES_PER_EU>
+template <typename T, int FAMILY, int WAVES_PER_EU, int NMAP = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 void fwd_kernel(FwdArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    fwd_item<T, FAMILY>(a, (int)blockIdx.x * (int)(blockDim.x >> 6) + wave);
+    fwd_item<T, FAMILY, NMAP>(a, (int)blockIdx.x * (int)(blockDim.x >> 6) + wave);
 }
 
 // Two contexts in one launch (the RSF cycle's replicas of window w and the
 // parent's next segment): blocks [0, blocks_a) run a's work list, the rest b's.
 // One launch keeps the two concurrent whatever hardware queues the streams
 // map to, and the parent's few waves get SIMDs of their own.
-template <typename T, int FAMILY, int WAVES_PER_EU>
+template <typename T, int FAMILY, int WAVES_PER_EU, int NMAP = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 void fwd_dual_kernel(FwdArgs a, FwdArgs b, int blocks_a) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int wpb = (int)(blockDim.x >> 6);
-    if ((int)blockIdx.x < blocks_a) fwd_item<T, FAMILY>(a, (int)blockIdx.x * wpb + wave);
-    else fwd_item<T, FAMILY>(b, ((int)blockIdx.x - blocks_a) * wpb + wave);
+    if ((int)blockIdx.x < blocks_a) fwd_item<T, FAMILY, NMAP>(a, (int)blockIdx.x * wpb + wave);
+    else fwd_item<T, FAMILY, NMAP>(b, ((int)blockIdx.x - blocks_a) * wpb + wave);
 }
 
 __global__ void advance_kernel(int64_t* step, int64_t n) {
@@ -380,7 +426,14 @@ __global__ __launch_bounds__(256) void plain_step_kernel(const GroupDev* __restr
         fx -= bx; fy -= by; fz -= bz;
     }
     T ex, ey, ez;
-    normals3(philox10(n, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), ex, ey, ez);
+    if (G.nmap == 1 && (n & 3u) == 3u) {   // map 1: fourth normals of steps n-3 .. n-1
+        T a_, b_, c_;
+        normals4(philox10(n - 3u, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), a_, b_, c_, ex);
+        normals4(philox10(n - 2u, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), a_, b_, c_, ey);
+        normals4(philox10(n - 1u, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), a_, b_, c_, ez);
+    } else {
+        normals3(philox10(n, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), ex, ey, ez);
+    }
     const T x = r[3 * i], y = r[3 * i + 1], z = r[3 * i + 2];
     const T ix = fmadd(c.kx(), x, fmadd(c.kxz(), z, fmadd(c.cF(), fx, c.sigma() * ex)));
     const T iy = fmadd(c.ky(), y, fmadd(c.cF(), fy, c.sigma() * ey));
@@ -581,14 +634,17 @@ static dim3 grid1d(int64_t n, int block) {
 #define FAMILY16_WAVES 2
 #endif
 
-hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, hipStream_t st) {
+hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, int nmap,
+                          hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     const int wpb = waves_per_block;
     dim3 grid((a.n_items + wpb - 1) / wpb), block(WAVE * wpb);
     if (precision == 64) {
-        hipLaunchKernelGGL((fwd_kernel<double, 4, 1>), grid, block, 0, st, a);
+        if (nmap == 1) hipLaunchKernelGGL((fwd_kernel<double, 4, 1, 1>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((fwd_kernel<double, 4, 1>), grid, block, 0, st, a);
     } else if (family == 4) {
-        hipLaunchKernelGGL((fwd_kernel<float, 4, 1>), grid, block, 0, st, a);
+        if (nmap == 1) hipLaunchKernelGGL((fwd_kernel<float, 4, 1, 1>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((fwd_kernel<float, 4, 1>), grid, block, 0, st, a);
     } else {
         hipLaunchKernelGGL((fwd_kernel<float, 16, FAMILY16_WAVES>), grid, block, 0, st, a);
     }
@@ -596,16 +652,18 @@ hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves
 }
 
 hipError_t launch_forward_dual(const FwdArgs& a, const FwdArgs& b, int precision, int family, int waves_per_block,
-                               hipStream_t st) {
+                               int nmap, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     const int wpb = waves_per_block;
     const int ba = (a.n_items + wpb - 1) / wpb, bb = (b.n_items + wpb - 1) / wpb;
     if (ba + bb == 0) return hipSuccess;
     dim3 grid((unsigned)(ba + bb)), block(WAVE * wpb);
     if (precision == 64) {
-        hipLaunchKernelGGL((fwd_dual_kernel<double, 4, 1>), grid, block, 0, st, a, b, ba);
+        if (nmap == 1) hipLaunchKernelGGL((fwd_dual_kernel<double, 4, 1, 1>), grid, block, 0, st, a, b, ba);
+        else hipLaunchKernelGGL((fwd_dual_kernel<double, 4, 1>), grid, block, 0, st, a, b, ba);
     } else if (family == 4) {
-        hipLaunchKernelGGL((fwd_dual_kernel<float, 4, 1>), grid, block, 0, st, a, b, ba);
+        if (nmap == 1) hipLaunchKernelGGL((fwd_dual_kernel<float, 4, 1, 1>), grid, block, 0, st, a, b, ba);
+        else hipLaunchKernelGGL((fwd_dual_kernel<float, 4, 1>), grid, block, 0, st, a, b, ba);
     } else {
         hipLaunchKernelGGL((fwd_dual_kernel<float, 16, FAMILY16_WAVES>), grid, block, 0, st, a, b, ba);
     }

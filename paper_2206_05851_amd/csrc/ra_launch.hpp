@@ -44,7 +44,9 @@ struct AdjArgs {
     double* partial;           // per item [3]: d/d(rate, H, b)
 };
 
-hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, hipStream_t st);
+// nmap: noise map of the context (1 selects the kernels compiled for map 1)
+hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, int nmap,
+                          hipStream_t st);
 hipError_t launch_forward_split(const FwdArgs& a, hipStream_t st);
 hipError_t launch_advance(int64_t* step, int64_t n, hipStream_t st);
 hipError_t launch_reset(int32_t* status, unsigned long long* clamps, int n_groups, int64_t* step, hipStream_t st);
@@ -68,7 +70,7 @@ hipError_t launch_pos_to_bonds(const GroupDev* groups, int n_groups, int64_t max
                                double* out, int precision, hipStream_t st);
 hipError_t launch_debug_noise(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
                               float* n32, double* n64, hipStream_t st);
-hipError_t launch_adjoint(const AdjArgs& a, int M, int item_begin, int item_end, int waves_per_block,
+hipError_t launch_adjoint(const AdjArgs& a, int M, int item_begin, int item_end, int waves_per_block, int nmap,
                           hipStream_t st);
 hipError_t launch_lam_mu(const GroupDev* groups, int n_groups, int64_t n_windows, const double* mean,
                          const double* grad_mean, const double* grad_rates, double k0, double xd,
@@ -80,7 +82,7 @@ hipError_t launch_grad_reduce(const int32_t* item_begin, int n_groups, const dou
 hipError_t launch_forward_pair(const FwdArgs& a, int precision, int waves_per_block, hipStream_t st);
 // two contexts (same kernel family) in one launch: blocks of a first, then b
 hipError_t launch_forward_dual(const FwdArgs& a, const FwdArgs& b, int precision, int family, int waves_per_block,
-                               hipStream_t st);
+                               int nmap, hipStream_t st);
 hipError_t launch_forward_pair_dual(const FwdArgs& a, const FwdArgs& b, int precision, int waves_per_block,
                                     hipStream_t st);
 hipError_t launch_forward_hi_dual(const FwdArgs& a, const FwdArgs& b, int precision, int max_beads, hipStream_t st);

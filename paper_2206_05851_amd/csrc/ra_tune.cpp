@@ -93,6 +93,7 @@ double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int M, int wpb,
     r.max_windows = 2;
     r.tile_policy = 1000 + M;
     r.waves_per_block = wpb;
+    r.noise_map = run.noise_map;
     ra_ctx* ctx = nullptr;
     if (ra_create(&ctx, &g, 1, &r, st) != RA_OK) return -1.0;
     // straight parent along x with unit bonds (inside any FENE extension b >= 2)

@@ -14,6 +14,7 @@ struct GroupDev {
     int32_t spring;          // 0 Hookean, 1 FENE, 2 rest-length harmonic
     uint32_t stream;         // counter word: tag<<24 | stream_id (tag 0)
     int32_t flow;            // 0..3 (shear adds the x <- z coupling)
+    int32_t nmap;            // noise map: 0 one Philox block per bead-step, 1 four normals per block
     // bond-form EM increment: dQ = kdiag.*Q + kxz*Qz e_x + cF*lap(gQ) + sigma*(xi_{j+1}-xi_j)
     float kx, ky, kz, kxz;   // dt * kappa entries
     float cF;                // H * dt / zeta

@@ -50,7 +50,7 @@ class RunDesc(ctypes.Structure):
                 ("max_steps", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("tile_policy", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("noise_tag", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32)]
+                ("noise_map", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(ChainDesc) == 112 and ctypes.sizeof(RunDesc) == 56
@@ -168,7 +168,7 @@ class Replicas:
 
     def __init__(self, groups, seed, precision=32, sample_every=100, max_windows=100, tsf=False,
                  checkpoint_every=0, max_steps=0, plain=False, use_graph=False, tile_policy=0,
-                 waves_per_block=0, noise_tag=0, device=None, stream=None):
+                 waves_per_block=0, noise_tag=0, noise_map=0, device=None, stream=None):
         self.L = library()
         self.groups = [dict(g) for g in groups]
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -180,7 +180,8 @@ class Replicas:
         run = RunDesc(seed=int(seed), precision=precision, sample_every=sample_every,
                       max_windows=max_windows, tsf=int(bool(tsf)), checkpoint_every=checkpoint_every,
                       max_steps=max_steps, plain=int(bool(plain)), use_graph=int(bool(use_graph)),
-                      tile_policy=tile_policy, waves_per_block=waves_per_block, noise_tag=noise_tag)
+                      tile_policy=tile_policy, waves_per_block=waves_per_block, noise_tag=noise_tag,
+                      noise_map=noise_map)
         self._descs = arr
         self.ptr = ctypes.c_void_p()
         with torch.cuda.device(self.device):

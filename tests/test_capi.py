@@ -90,7 +90,10 @@ def _create(lib, desc_kw, run_kw):
     (dict(hi_radius=0.5, n_beads=65), {}, "n_beads"),
     (dict(hi_radius=0.5), dict(checkpoint_every=10), "adjoint"),
     (dict(hi_radius=0.5), dict(plain=1), "plain"),
-    ({}, dict(reserved_=1), "reserved_"),
+    ({}, dict(noise_map=2), "noise_map"),
+    (dict(n_beads=300), dict(noise_map=1), "noise_map"),
+    (dict(spring=2, rest_length=2.0), dict(noise_map=1), "noise_map"),
+    (dict(hi_radius=0.5), dict(noise_map=1), "noise_map"),
 ])
 def test_invalid_descriptors_rejected_on_host(lib, desc_kw, run_kw, frag):
     rc, msg = _create(lib, desc_kw, run_kw)

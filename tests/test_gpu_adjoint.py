@@ -16,7 +16,8 @@ def _gpu():
     require_gpu()
 
 
-def _grad_pair(groups, parents, seed, steps, S, K, k0=1e-6, xd=0.1, wseed=0, rate_scale=1e5, tile_policy=0):
+def _grad_pair(groups, parents, seed, steps, S, K, k0=1e-6, xd=0.1, wseed=0, rate_scale=1e5, tile_policy=0,
+               noise_map=0):
     import torch
     W = steps // S
     nspr = sum(g["n_beads"] - 1 for g in groups)
@@ -24,13 +25,13 @@ def _grad_pair(groups, parents, seed, steps, S, K, k0=1e-6, xd=0.1, wseed=0, rat
     gm = rng.normal(size=(W, nspr))
     gr = rng.normal(size=(W, nspr)) * rate_scale
     rep = run_gpu(groups, parents, seed, steps, S, checkpoint_every=K, max_steps=steps,
-                  tile_policy=tile_policy)
+                  tile_policy=tile_policy, noise_map=noise_map)
     assert rep.checkpoint_interval() == (1 if K == -1 else K)
     mean, _ = rep.average_forces()
     g_gpu = rep.backward(mean, torch.from_numpy(gm).cuda(), torch.from_numpy(gr).cuda(), k0, xd)
     g_gpu = g_gpu.cpu().numpy()
     rep.sync_status()
-    o = run_oracle(groups, parents, seed, steps, S, tangents=True)
+    o = run_oracle(groups, parents, seed, steps, S, tangents=True, noise_map=noise_map)
     g_ref = o.backward(gm, gr, k0, xd)
     return g_gpu, g_ref
 
@@ -55,6 +56,18 @@ def test_adjoint_matches_oracle_tangents_200_steps(spring, flow, N, policy):
     _check(g_gpu, g_ref, 1e-4)
     if spring == wl.HOOKEAN:
         assert g_gpu[0, 2] == 0.0
+
+
+@pytest.mark.parametrize("N,K", [(50, 50), (50, 7), (50, -1), (130, 25)])
+def test_adjoint_under_noise_map_one(N, K):
+    # noise map 1: the segment recompute rebuilds the fourth-normal carry at
+    # each segment start (K = 7 and 25 start segments off the 4-step grid);
+    # N = 130 runs 3 beads per lane
+    g = wl.group(N, 64, 1e-4, wl.FENE, 1.3, 40.0, wl.UNIAXIAL, 0.8, stream_id=2)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.3, 40.0, seed=N + 1)
+    announce("adjoint noise map 1 N=%d K=%d" % (N, K))
+    g_gpu, g_ref = _grad_pair([g], [parent], 23, 200, 50, K, noise_map=1)
+    _check(g_gpu, g_ref, 1e-4)
 
 
 def test_adjoint_batch_and_guard():

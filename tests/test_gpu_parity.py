@@ -174,6 +174,72 @@ def test_noise_producer_split_is_bitwise_equal_to_one_wave(N, R, steps, chunks):
     assert rel_err(out[3][0], o.samples()[0]) < TOL32
 
 
+@pytest.mark.parametrize("precision,tol", [(32, TOL32), (64, TOL64)])
+def test_noise_map_one_parity_tiles_and_plain(precision, tol):
+    # noise map 1 against the oracle's map 1. S = 25 puts window ends off the
+    # 4-step grid and the step calls (37, 13, 150) start off it, so the fused
+    # loop's unaligned heads, carry rebuilds and tails all run; every tile M =
+    # 1..4 must give the same bits, and the plain path the oracle's values
+    from paper_2206_05851_amd import ra
+    N, R, seed = 50, 40, 17
+    g = wl.group(N, R, 1e-4, wl.FENE, 1.0, 60.0, wl.UNIAXIAL, 0.5, stream_id=6)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 60.0, seed=61)
+    o = run_oracle([g], [parent], seed, 200, 25, noise_map=1)
+    ref = None
+    for M in (1, 2, 3, 4):
+        announce("noise map 1 precision=%d M=%d" % (precision, M))
+        rep = ra.Replicas([g], seed, precision=precision, sample_every=25, max_windows=8, noise_map=1,
+                          tile_policy=1000 + M)
+        rep.init_chains([parent])
+        for c in (37, 13, 150):
+            rep.step(c)
+        smp = rep.samples()[0].cpu().numpy()
+        rep.sync_status()
+        assert rep.tile_info()[0] == [M]
+        if ref is None:
+            ref = smp
+            assert rel_err(smp, o.samples()[0]) < tol
+        else:
+            assert np.array_equal(smp, ref), M
+    announce("noise map 0 differs; plain path under map 1")
+    rep0 = run_gpu([g], [parent], seed, 200, 25, precision=precision)
+    assert not np.array_equal(rep0.samples()[0].cpu().numpy(), ref)
+    rep0.sync_status()
+    repp = run_gpu([g], [parent], seed, 200, 25, precision=precision, plain=True, noise_map=1)
+    assert rel_err(repp.samples()[0].cpu().numpy(), o.samples()[0]) < tol
+    repp.sync_status()
+
+
+def test_noise_map_one_tsf_graph_and_batch():
+    # TSF (per-step tensions) and graph replay under map 1, in a batch of
+    # uneven chains (M = 1 and packed replicas), each group against the oracle
+    gs = [wl.group(50, 30, 1e-4, wl.FENE, 1.0, 80.0, wl.SHEAR, 20.0, stream_id=1),
+          wl.group(20, 45, 1e-4, wl.HOOKEAN, 1.0, 0.0, wl.PLANAR, 0.4, stream_id=2),
+          wl.group(200, 6, 1e-4, wl.FENE, 1.0, 120.0, wl.UNIAXIAL, 0.02, stream_id=3)]
+    ps = [wl.equilibrium_parent(g["n_beads"], g["spring"], g["H"], g["b"], seed=70 + i) for i, g in enumerate(gs)]
+    o = run_oracle(gs, ps, 29, 150, 30, tsf=True, noise_map=1)
+    announce("noise map 1 batch, TSF, eager")
+    rep = run_gpu(gs, ps, 29, 0, 30, max_windows=5, tsf=True, noise_map=1)
+    for c in (61, 89):
+        rep.step(c)
+    smp, tsf = rep.samples(tsf=True)
+    rep.sync_status()
+    osmp = o.samples()
+    otsf = o.samples(tsf=True)[1]
+    for k in range(3):
+        assert rel_err(smp[k].cpu().numpy(), osmp[k]) < TOL32
+        assert rel_err(tsf[k].cpu().numpy(), otsf[k]) < TOL32
+    announce("noise map 1 batch, graph replay")
+    repg = run_gpu(gs, ps, 29, 0, 30, max_windows=5, tsf=True, noise_map=1, use_graph=True)
+    for c in (61, 89):
+        repg.step(c)
+    smpg, tsfg = repg.samples(tsf=True)
+    repg.sync_status()
+    for k in range(3):
+        assert np.array_equal(smpg[k].cpu().numpy(), smp[k].cpu().numpy())
+        assert np.array_equal(tsfg[k].cpu().numpy(), tsf[k].cpu().numpy())
+
+
 def test_batch_is_bitwise_invariant():
     gs = [wl.group(20, 40, 1e-4, wl.FENE, 1.0, 50.0, wl.PLANAR, 0.5, stream_id=4),
           wl.group(63, 17, 2e-4, wl.HOOKEAN, 2.0, 0.0, wl.UNIAXIAL, 0.01, stream_id=9),
