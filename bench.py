@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--tile-policy", type=int, default=0,
                     help="ra_run_desc.tile_policy for the headline workload (0 = cost model)")
     ap.add_argument("--noise-map", type=int, default=1, choices=(0, 1),
-                    help="ra_run_desc.noise_map of the headline, plain and adjoint workloads "
+                    help="ra_run_desc.noise_map of the headline, plain, adjoint and batched workloads "
                          "(1: four normals per Philox block)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -337,7 +337,8 @@ def main():
         bg, bp, brun = wl.batched512()
         bpar = torch.from_numpy(np.concatenate([np.ascontiguousarray(p).reshape(-1) for p in bp])).to(dev)
         bat = ra.Replicas(bg, brun["seed"], precision=32, sample_every=brun["sample_every"],
-                          max_windows=brun["steps"] // brun["sample_every"], use_graph=True, device=dev)
+                          max_windows=brun["steps"] // brun["sample_every"], use_graph=True, device=dev,
+                          noise_map=args.noise_map)
 
         def bat_step():
             bat.init_chains(bpar)
@@ -353,7 +354,7 @@ def main():
         # length timed alone on 256 replicas) instead of the cost model
         bat = ra.Replicas(bg, brun["seed"], precision=32, sample_every=brun["sample_every"],
                           max_windows=brun["steps"] // brun["sample_every"], use_graph=True, device=dev,
-                          tile_policy=1)
+                          tile_policy=1, noise_map=args.noise_map)
         bat_step()
         ttun = min(time_once(bat_step) for _ in range(2))
         bat.sync_status()
