@@ -114,7 +114,7 @@ def time_once(fn):
     return time.perf_counter() - t0
 
 
-def rsf_cycle_bench(workload, desc, dev, name):
+def rsf_cycle_bench(workload, desc, dev, name, noise_map=0):
     """One RSF cycle (parent context on its own stream, re-clone per window)
     with the estimators built on it, timed after a warm-up cycle."""
     import numpy as np
@@ -124,8 +124,9 @@ def rsf_cycle_bench(workload, desc, dev, name):
     rS, rP, rW = rrun["sample_every"], rrun["parent_steps"], rrun["n_windows"]
     pstream = torch.cuda.Stream()
     rpar = ra.Replicas([dict(x, n_replicas=1) for x in rg], rrun["seed"], sample_every=rP, max_windows=rW,
-                       tsf=True, noise_tag=1, stream=pstream, use_graph=True, device=dev)
-    rrep = ra.Replicas(rg, rrun["seed"], sample_every=rS, max_windows=rW, use_graph=True, device=dev)
+                       tsf=True, noise_tag=1, stream=pstream, use_graph=True, device=dev, noise_map=noise_map)
+    rrep = ra.Replicas(rg, rrun["seed"], sample_every=rS, max_windows=rW, use_graph=True, device=dev,
+                       noise_map=noise_map)
     mftu = {}
     rpd = torch.from_numpy(np.concatenate([np.ravel(x) for x in rp])).to(dev)
 
@@ -149,7 +150,8 @@ def rsf_cycle_bench(workload, desc, dev, name):
     work = rg[0]["n_replicas"] * rg[0]["n_beads"] * rS * rW
     res = {"workload": name + ": " + desc, "value": work / t,
            "unit": "replica·bead·steps/s (whole cycle incl. parent)", "ms_per_cycle": 1e3 * t,
-           "us_per_window": 1e6 * t / rW, "mftu": {k: float(v[0]) for k, v in mftu.items()}}
+           "us_per_window": 1e6 * t / rW, "mftu": {k: float(v[0]) for k, v in mftu.items()},
+           "noise_map": noise_map}
     rpar.close()
     rrep.close()
     log("%s: %.2f ms per cycle (%.1f us per window)" % (name, 1e3 * t, 1e6 * t / rW))
@@ -169,7 +171,7 @@ def main():
     ap.add_argument("--tile-policy", type=int, default=0,
                     help="ra_run_desc.tile_policy for the headline workload (0 = cost model)")
     ap.add_argument("--noise-map", type=int, default=1, choices=(0, 1),
-                    help="ra_run_desc.noise_map of the headline, plain, adjoint and batched workloads "
+                    help="ra_run_desc.noise_map of the headline, plain, adjoint, batched and rsf50 workloads "
                          "(1: four normals per Philox block)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -401,7 +403,9 @@ def main():
                                   "every step), shear 30, dt=1e-5, parent + N_R=50 replicas re-cloned every "
                                   "750 steps, 4 windows, ISF/TSF/RSF, sigma(N_R), MFTU")):
         if rname in extras:
-            out[rname] = rsf_cycle_bench(getattr(wl, rname)(), rdesc, dev, rname)
+            # noise map 1 covers the chain model only (not the pair and HI models)
+            out[rname] = rsf_cycle_bench(getattr(wl, rname)(), rdesc, dev, rname,
+                                         args.noise_map if rname == "rsf50" else 0)
 
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB

@@ -15,23 +15,25 @@ def _gpu():
     require_gpu()
 
 
-def _gpu_pair(groups, parents, seed, S, P, W, precision=32, two_streams=False, use_graph=False):
+def _gpu_pair(groups, parents, seed, S, P, W, precision=32, two_streams=False, use_graph=False, noise_map=0):
     import torch
     from paper_2206_05851_amd import ra
     pstream = torch.cuda.Stream() if two_streams else None
     par = ra.Replicas([dict(g, n_replicas=1) for g in groups], seed, precision=precision, sample_every=P,
-                      max_windows=W, tsf=True, noise_tag=1, stream=pstream, use_graph=use_graph)
+                      max_windows=W, tsf=True, noise_tag=1, stream=pstream, use_graph=use_graph,
+                      noise_map=noise_map)
     par.init_chains(parents)
-    rep = ra.Replicas(groups, seed, precision=precision, sample_every=S, max_windows=W, use_graph=use_graph)
+    rep = ra.Replicas(groups, seed, precision=precision, sample_every=S, max_windows=W, use_graph=use_graph,
+                      noise_map=noise_map)
     return par, rep
 
 
-def _oracle_pair(groups, parents, seed, S, P, W, ranges=None):
+def _oracle_pair(groups, parents, seed, S, P, W, ranges=None, noise_map=0):
     from oracle import ora
-    par = ora.Oracle([dict(g, n_replicas=1) for g in groups], seed, P, W, tsf=True)
+    par = ora.Oracle([dict(g, n_replicas=1) for g in groups], seed, P, W, tsf=True, noise_map=noise_map)
     par.set_tag(ora.TAG_PARENT)
     par.init_chains(parents)
-    rep = ora.Oracle(groups, seed, S, W)
+    rep = ora.Oracle(groups, seed, S, W, noise_map=noise_map)
     for g, r in (ranges or {}).items():
         rep.set_replicas(g, *r)
     return par, rep
@@ -46,7 +48,7 @@ def _run_both(groups, parents, seed, S, P, W, **kw):
     torch.cuda.synchronize()
     gp.sync_status()
     gr.sync_status()
-    op, orr = _oracle_pair(groups, parents, seed, S, P, W)
+    op, orr = _oracle_pair(groups, parents, seed, S, P, W, noise_map=kw.get("noise_map", 0))
     orr.rsf_cycle(op, W, P)
     oisf, _, otsf, _ = op.average_forces(tsf=True)
     orsf, orstd = orr.average_forces()
@@ -54,15 +56,16 @@ def _run_both(groups, parents, seed, S, P, W, **kw):
            (op, orr, oisf, otsf, orsf, orstd)
 
 
-@pytest.mark.parametrize("two_streams", [False, True])
-def test_rsf_cycle_matches_oracle(two_streams):
+@pytest.mark.parametrize("two_streams,noise_map", [(False, 0), (True, 0), (False, 1), (True, 1)])
+def test_rsf_cycle_matches_oracle(two_streams, noise_map):
     gs = [wl.group(24, 48, 1e-4, wl.FENE, 1.0, 60.0, wl.SHEAR, wl.wi_to_rate(40.0, 24), stream_id=3),
           wl.group(10, 20, 1e-3, wl.HOOKEAN, 1.0, 0.0, wl.UNIAXIAL, wl.wi_to_rate(0.4, 10), stream_id=9)]
     ps = [wl.equilibrium_parent(24, wl.FENE, 1.0, 60.0, seed=5), wl.equilibrium_parent(10, seed=6)]
     S, P, W = 40, 30, 5
-    announce("rsf cycle two_streams=%s" % two_streams)
+    announce("rsf cycle two_streams=%s noise_map=%d" % (two_streams, noise_map))
     (gp, gr, isf, tsf, rsf, rstd), (op, orr, oisf, otsf, orsf, orstd) = _run_both(gs, ps, 11, S, P, W,
-                                                                                   two_streams=two_streams)
+                                                                                   two_streams=two_streams,
+                                                                                   noise_map=noise_map)
     e = [rel_err(isf, oisf, 1e-3), rel_err(tsf, otsf, 1e-3), rel_err(rsf, orsf, 1e-3), rel_err(rstd, orstd, 1e-3)]
     announce("isf %.2e tsf %.2e rsf %.2e std %.2e" % tuple(e))
     assert max(e) < 1e-4
