@@ -210,6 +210,30 @@ def test_noise_map_one_parity_tiles_and_plain(precision, tol):
     repp.sync_status()
 
 
+@pytest.mark.parametrize("M", [1, 3])
+def test_noise_map_one_tiny_calls_equal_one_call(M):
+    # calls of 1-3 steps start every launch inside a group of four, so each
+    # builds its carry from the blocks of the group's earlier steps; windows of
+    # 5 steps end off the grid too. Bit-equal to one call, and to the oracle.
+    from paper_2206_05851_amd import ra
+    N = 40
+    g = wl.group(N, 24, 1e-4, wl.FENE, 1.0, 60.0, wl.PLANAR, 0.7, stream_id=8)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 60.0, seed=81)
+    chunks = [1, 2, 3, 1, 1, 3, 2, 2, 1, 3, 1, 2, 3, 3, 2, 1, 1, 2, 3, 3]   # 40 steps
+    out = []
+    for calls in (chunks, [sum(chunks)]):
+        announce("noise map 1 M=%d, %d calls" % (M, len(calls)))
+        rep = ra.Replicas([g], 37, sample_every=5, max_windows=8, noise_map=1, tile_policy=1000 + M)
+        rep.init_chains([parent])
+        for c in calls:
+            rep.step(c)
+        out.append((rep.samples()[0].cpu().numpy(), rep.bonds()[0].cpu().numpy()))
+        rep.sync_status()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    o = run_oracle([g], [parent], 37, 40, 5, noise_map=1)
+    assert rel_err(out[0][0], o.samples()[0]) < TOL32
+
+
 def test_noise_map_one_tsf_graph_and_batch():
     # TSF (per-step tensions) and graph replay under map 1, in a batch of
     # uneven chains (M = 1 and packed replicas), each group against the oracle
