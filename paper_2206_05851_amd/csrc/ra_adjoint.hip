@@ -98,8 +98,12 @@ __device__ __forceinline__ void inject(const Lane<float, M>& q, const bool (&val
 }
 
 // Reverse step through Phi at the state q = Q^n; lambda holds lambda^{n+1}.
+// kc.cF is 0 on slots that are not a spring of an active replica: their
+// lambda starts at 0, gets no injection, and with a zero coefficient on the
+// neighbour term stays 0 without a per-step select (their Q is 0, so they add
+// nothing to the theta sums either).
 template <int M, bool FENE>
-__device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const bool (&valid)[M], const GroupDev& G,
+__device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const SlotCoef<float, M>& kc, const GroupDev& G,
                                              float (&lx)[M], float (&ly)[M], float (&lz)[M], float& gr,
                                              float& gH, float& gb) {
     const float kx = G.kx, ky = G.ky, kz = G.kz, kxz = G.kxz, cF = G.cF;
@@ -135,21 +139,26 @@ __device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const bool
         // theta terms with lambda^{n+1}
         gr += fmadd(lx[m], fmadd(px, Qx, pxz * Qz), fmadd(ly[m], py * Qy, lz[m] * pz * Qz));
         const float muQ = fmadd(ux[m], Qx, fmadd(uy[m], Qy, uz[m] * Qz));
-        const float wH = (FENE && smooth) ? dtz * g * fmadd(g, s, 1.0f) : dtz * g;
-        const float wb = (FENE && smooth) ? -cF * g * g * (s * inv_b) : 0.0f;
+        // off the guard s and 2/Q0^2 enter dG/dQ and dG/dtheta; on it (and
+        // for Hookean springs) both are 0 and only g remains
+        const float se = (FENE && smooth) ? s : 0.0f;
+        const float e2 = (FENE && smooth) ? 2.0f * G.inv_q0sq : 0.0f;
+        const float wH = dtz * g * fmadd(g, se, 1.0f);
+        const float wb = -cF * g * g * (se * inv_b);
         gH = fmadd(wH, muQ, gH);
         gb = fmadd(wb, muQ, gb);
         // lambda^n = lambda + (dt kappa)^T lambda + cF J mu
-        const float ex = (FENE && smooth) ? 2.0f * g * g * G.inv_q0sq * muQ : 0.0f;
+        const float ex = g * g * e2 * muQ;
         const float jx = fmadd(g, ux[m], ex * Qx);
         const float jy = fmadd(g, uy[m], ex * Qy);
         const float jz = fmadd(g, uz[m], ex * Qz);
-        const float nx = lx[m] + fmadd(kx, lx[m], cF * jx);
-        const float ny = ly[m] + fmadd(ky, ly[m], cF * jy);
-        const float nz = lz[m] + fmadd(kz, lz[m], fmadd(kxz, lx[m], cF * jz));
-        lx[m] = valid[m] ? nx : 0.0f;
-        ly[m] = valid[m] ? ny : 0.0f;
-        lz[m] = valid[m] ? nz : 0.0f;
+        const float cFm = kc.cF[m];
+        const float nx = lx[m] + fmadd(kx, lx[m], cFm * jx);
+        const float ny = ly[m] + fmadd(ky, ly[m], cFm * jy);
+        const float nz = lz[m] + fmadd(kz, lz[m], fmadd(kxz, lx[m], cFm * jz));
+        lx[m] = nx;
+        ly[m] = ny;
+        lz[m] = nz;
     }
 }
 
@@ -214,7 +223,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
                 --w;
             }
             float pr = 0.0f, pH = 0.0f, pb = 0.0f;
-            reverse_step<M, FENE>(q, valid, G, lx, ly, lz, pr, pH, pb);
+            reverse_step<M, FENE>(q, kc, G, lx, ly, lz, pr, pH, pb);
             gr += (double)pr;
             gH += (double)pH;
             gb += (double)pb;
@@ -262,7 +271,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
                 gb += db;
                 --w;
             }
-            reverse_step<M, FENE>(q, valid, G, lx, ly, lz, pr, pH, pb);
+            reverse_step<M, FENE>(q, kc, G, lx, ly, lz, pr, pH, pb);
             s = q;
             rr = rr == 0 ? S - 1 : rr - 1;
         }
