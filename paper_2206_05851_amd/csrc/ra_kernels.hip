@@ -123,7 +123,10 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
                 }
             }
         }
-        for (; i < len; ++i) {   // starts aligned after the groups, so the carry is refilled before use
+        // the rest: with one bead per lane a tail of at most three steps that
+        // starts aligned (the carry is refilled before it is read); wider lanes
+        // step through the carry from the start
+        for (; i < len; ++i) {
             em_step_map1<T, M, FENE>(s, cy, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps);
             accumulate_tsf();
         }
