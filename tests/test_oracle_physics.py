@@ -5,7 +5,7 @@ than the oracle: bond-space closed forms, potentials, Newton solutions and
 textbook equilibrium results."""
 import numpy as np
 import pytest
-from scipy import integrate, optimize
+from scipy import optimize
 
 import closed_forms as cf
 from oracle import ora
