@@ -196,6 +196,44 @@ def test_rouse_equilibrium_tension_is_maxwell():
     assert np.all(std > 0)
 
 
+def test_replica_std_is_unbiased_maxwell_spread():
+    # Pins the replica standard deviation (denominator R - 1) of the RSF and TSF
+    # estimates. Hookean dumbbells (one spring) with H = kT = zeta = 1: the bond
+    # relaxes at rate 2H/zeta and its EM-stationary variance per component is
+    # v = (kT/H) / (1 - H dt/zeta). Windows of S dt = 5 time units leave every
+    # replica of a window independent of its clone source and of the previous
+    # window (correlation e^-10), so each window's replica variance over R = 3
+    # replicas is an unbiased estimate of the Maxwell variance v H^2 (3 - 8/pi).
+    # A denominator R would give 2/3 of it; the band below is 4.5 standard errors.
+    R, G, dt, S, W = 3, 400, 0.01, 500, 10
+    groups = [g(2, R, dt, stream_id=i) for i in range(G)]
+    parents = [wl.equilibrium_parent(2, seed=900 + i) for i in range(G)]
+    o = ora.Oracle(groups, seed=11, sample_every=S, max_windows=W, tsf=True)
+    o.init_chains(parents)
+    o.step(S * W)
+    mean, std, tmean, tstd = o.average_forces(tsf=True)
+    v = 1.0 / (1.0 - dt)
+    mu_exact, var_exact = np.sqrt(8.0 * v / np.pi), v * (3.0 - 8.0 / np.pi)
+    s2 = std[1:] ** 2                                   # first window still remembers the parent
+    se = s2.std() / np.sqrt(s2.size)
+    assert abs(s2.mean() - var_exact) < 4.5 * se, (s2.mean(), var_exact, se)
+    assert abs(s2.mean() - (R - 1) / R * var_exact) > 10 * se
+    assert abs(mean[1:].mean() - mu_exact) < 4.5 * mean[1:].std() / np.sqrt(mean[1:].size)
+    # the same outputs against numpy's ddof=1 statistics of the oracle's samples
+    smp, tsmp = o.samples(tsf=True)
+    per = np.stack([x[:, :, 0] for x in smp], axis=1)   # [W][G][R]
+    tper = np.stack([x[:, :, 0] for x in tsmp], axis=1)
+    assert np.allclose(std, per.std(axis=2, ddof=1), rtol=1e-12, atol=0)
+    assert np.allclose(mean, per.mean(axis=2), rtol=1e-13, atol=0)
+    assert np.allclose(tstd, tper.std(axis=2, ddof=1), rtol=1e-12, atol=0)
+    assert np.allclose(tmean, tper.mean(axis=2), rtol=1e-13, atol=0)
+    # R = 1: the spread is defined as 0
+    one = ora.Oracle([g(2, 1, dt)], seed=11, sample_every=S, max_windows=1)
+    one.init_chains([parents[0]])
+    one.step(S)
+    assert one.average_forces()[1][0, 0] == 0.0
+
+
 def _mean_tension_gaussian(m, cov3, H, n=400000, seed=0):
     """E[H |Q|] for Q ~ Normal(m, cov3), by numpy Monte Carlo (independent RNG)."""
     rng = np.random.default_rng(seed)
