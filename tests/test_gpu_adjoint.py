@@ -1,11 +1,12 @@
 """GPU adjoint (ra_backward, reverse mode over checkpointed segments) against
-the oracle's forward-mode pathwise tangents on the same seeds, and against
-central finite differences with common random numbers at the full
+the oracle's forward-mode pathwise tangents on the same seeds (up to the
+differentiation workload's tile and horizon), and against central finite
+differences of the FP64 oracle with common random numbers at the full
 differentiation workload (N=100, 4096 replicas, 2000 steps)."""
 import numpy as np
 import pytest
 
-from gpu_util import announce, require_gpu, run_gpu, run_oracle
+from gpu_util import announce, cpu_threads, oracle_mean_parallel, require_gpu, run_gpu, run_oracle
 from paper_2206_05851_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -138,18 +139,40 @@ def test_autograd_function_uses_adjoint():
     _check(params.grad.numpy(), ref, 1e-4)
 
 
-def test_adjoint_full_size_against_fd_with_crn():
-    # Full differentiation workload; FD on the FP64 GPU path with the same
-    # counters (common random numbers), relative step 1e-4, against the FP32
-    # reverse-mode gradient.
+@pytest.mark.parametrize("noise_map", [0, 1])
+def test_adjoint_c4_tile_matches_oracle_tangents(noise_map):
+    # The differentiation workload's shape (N = 100, b = 100, uniaxial Wi = 4,
+    # dt = 1e-4, 2000 steps, checkpoints every 100 steps, 2 beads per lane) on
+    # its first 64 replicas: the counters carry the global replica index, so
+    # these are replicas 0..63 of the full run. Objective with both terms
+    # (replica-averaged tension profile and Bell rates).
+    groups, parents, run = wl.adjoint100(n_replicas=64)
+    steps, S, K = run["steps"], run["sample_every"], run["checkpoint_every"]
+    announce("C4 tile adjoint vs oracle tangents: N=100 R=64 2000 steps K=100 noise map %d" % noise_map)
+    g_gpu, g_ref = _grad_pair(groups, parents, run["seed"], steps, S, K, run["k0"], run["x_dagger"], wseed=4,
+                              noise_map=noise_map)
+    rep = run_gpu(groups, parents, run["seed"], 0, S, max_windows=steps // S, checkpoint_every=K,
+                  max_steps=steps, noise_map=noise_map)
+    assert rep.tile_info()[0][0] == 2
+    rep.close()
+    _check(g_gpu, g_ref, 1e-3)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_full_size_against_oracle_fd_with_crn():
+    # Full differentiation workload (4096 replicas, noise map 1 as in the
+    # benchmark): the FP32 reverse-mode gradient of J = sum gm * mean against
+    # central finite differences of the FP64 oracle with the same counters
+    # (common random numbers), relative step 1e-4. The oracle runs its
+    # replicas on host threads.
     import torch
     groups, parents, run = wl.adjoint100()
     steps, S, K = run["steps"], run["sample_every"], run["checkpoint_every"]
     W = steps // S
     rng = np.random.default_rng(3)
     gm = rng.normal(size=(W, 99))
-    announce("C4 full size adjoint: N=100 R=4096 2000 steps")
-    rep = run_gpu(groups, parents, run["seed"], steps, S, checkpoint_every=K, max_steps=steps)
+    announce("C4 full size adjoint: N=100 R=4096 2000 steps, noise map 1")
+    rep = run_gpu(groups, parents, run["seed"], steps, S, checkpoint_every=K, max_steps=steps, noise_map=1)
     mean, _ = rep.average_forces()
     grad = rep.backward(mean, torch.from_numpy(gm).cuda(), None).cpu().numpy()[0]
     rep.sync_status()
@@ -157,16 +180,13 @@ def test_adjoint_full_size_against_fd_with_crn():
 
     def J(over):
         g = dict(groups[0], **over)
-        r = run_gpu([g], parents, run["seed"], steps, S, precision=64)
-        m, _ = r.average_forces()
-        val = float((m.cpu().numpy() * gm).sum())
-        r.sync_status()
-        r.close()
-        return val
+        m = oracle_mean_parallel([g], parents, run["seed"], steps, S, noise_map=1)
+        return float((m * gm).sum())
 
     h = 1e-4
     for p, key in enumerate(("rate", "H", "b")):
         th = groups[0][key]
+        announce("oracle FD d/d%s on %d host threads" % (key, cpu_threads()))
         fd = (J({key: th * (1 + h)}) - J({key: th * (1 - h)})) / (2 * h * th)
-        announce("d/d%s adjoint %.6e fd %.6e" % (key, grad[p], fd))
+        announce("d/d%s adjoint %.6e oracle fd %.6e" % (key, grad[p], fd))
         assert abs(grad[p] - fd) <= 1e-3 * max(abs(fd), 1e-3 * np.max(np.abs(grad))), key
