@@ -239,7 +239,7 @@ def main():
     traffic = (FWD_TRAFFIC["bytes"] if family == 4 and args.tile_policy == 0
                and args.noise_map == FWD_TRAFFIC.get("noise_map", 0)
                and fwd_sources_digest() == FWD_TRAFFIC["sha256"] else None)
-    kernel_name = {1: "fwd_split_kernel", 4: "fwd_kernel<float,4,1,%d>" % args.noise_map,
+    kernel_name = {4: "fwd_kernel<float,4,1,%d>" % args.noise_map,
                    16: "fwd_kernel<float,16,2,0>"}[family]
 
     out = {

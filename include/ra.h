@@ -117,9 +117,8 @@ typedef struct {
     int32_t  max_steps;         /* steps since ra_init_chains the checkpoints must hold */
     int32_t  plain;             /* 1: plain path, one launch per step, state in HBM */
     int32_t  use_graph;         /* 1: capture ra_step's launch sequence in a hipGraph */
-    int32_t  tile_policy;       /* 0 cost model; 1 autotune by timing; 2 cost model
-                                   without the noise-producer split; 3 force the split
-                                   where legal; 1000 + m: force m beads per lane */
+    int32_t  tile_policy;       /* 0 cost model; 1 autotune by timing; 1000 + m: force
+                                   m beads per lane where legal (m <= 16) */
     int32_t  waves_per_block;   /* 0 = default (4) */
     int32_t  noise_tag;         /* 0: replica noise; 1: parent trajectory (RSF cycle, Sec. II) */
     int32_t  noise_map;         /* 0: one Philox block per (step, bead), three normals;
@@ -252,8 +251,7 @@ RA_API ra_status ra_get_bonds(ra_ctx* ctx, double* out);
 RA_API ra_status ra_checkpoint_interval(ra_ctx* ctx, int32_t* steps);
 
 /* Tile chosen per group (host int32[n_groups] each): beads per lane and
- * replicas per wavefront; kernel_family (host int32[1], may be NULL): 1 = one
- * bead per lane with a noise-producer wavefront per work item, 2 = the
+ * replicas per wavefront; kernel_family (host int32[1], may be NULL): 2 = the
  * pair-interaction kernel (one bead per lane; LJ and rest-length springs),
  * 3 = hydrodynamic-interaction kernel (one workgroup per replica), 4 = 1-4
  * beads per lane, 16 = 6-16 beads per lane, 0 = plain path. */

@@ -92,6 +92,12 @@ bool is_pair_group(const ra_chain_desc& d) {
     return !is_hi_group(d) && (d.spring == RA_HARMONIC || d.lj_eps > 0.0);
 }
 
+}  // namespace
+
+namespace ra {
+
+void set_global_error(const std::string& msg) { g_err = msg; }
+
 ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std::string& why) {
     char buf[256];
     if (!g || n < 1 || !r) { why = "null descriptor or n_groups < 1"; return RA_EINVAL; }
@@ -110,6 +116,10 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
         return RA_EINVAL;
     }
     if (r->noise_tag != 0 && r->noise_tag != 1) { why = "noise_tag must be 0 or 1"; return RA_EINVAL; }
+    if (r->tile_policy != 0 && r->tile_policy != 1 && !(r->tile_policy > 1000 && r->tile_policy <= 1016)) {
+        why = "tile_policy must be 0 (cost model), 1 (autotune) or 1000 + m (m beads per lane)";
+        return RA_EINVAL;
+    }
     if (r->noise_map != 0 && r->noise_map != 1) { why = "noise_map must be 0 or 1"; return RA_EINVAL; }
     const int wpb = r->waves_per_block ? r->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4) { why = "waves_per_block must be 0, 1, 2 or 4"; return RA_EINVAL; }
@@ -202,6 +212,10 @@ GroupDev make_group(const ra_chain_desc& d, int M, int tag, int nmap) {
     return G;
 }
 
+}  // namespace ra
+
+namespace {
+
 template <typename T>
 ra_status dalloc(ra_ctx* c, T** p, size_t count) {
     *p = nullptr;
@@ -290,22 +304,12 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
         Ms[i] = (pair || hi) ? 1 : choose_beads_per_lane(groups[i].n_beads, groups[i].n_replicas, family, forced);
     }
     if (run->tile_policy == 1 && !run->plain && !pair && !hi) {
-        ra_status st = autotune_tiles(c->descs, *run, family, c->wpb, c->stream, Ms, why);
+        int wpb = run->waves_per_block;   // 0: the tuner chooses the workgroup size too
+        ra_status st = autotune_tiles(c->descs, *run, family, wpb, c->stream, Ms, why);
+        c->wpb = wpb;
         if (st != RA_OK) {
             ra_destroy(c);
             return fail(nullptr, st, "autotune: " + why);
-        }
-    }
-    // Noise-producer split (one bead per lane, no TSF, FP32): only on request
-    // (tile_policy 3); on the 1024-replica, 50-bead workload it measured slower
-    // than the one-wave kernel with its software-pipelined noise.
-    {
-        bool fits = family == 4 && run->precision == 32 && !run->plain && !run->tsf && run->noise_map == 0;
-        for (int i = 0; i < n_groups && fits; ++i)
-            if (groups[i].n_beads > WAVE) fits = false;
-        if (fits && run->tile_policy == 3) {
-            family = 1;
-            for (int i = 0; i < n_groups; ++i) Ms[i] = 1;
         }
     }
     c->family = family;
@@ -505,8 +509,7 @@ static ra_status enqueue_forward(ra_ctx* c, int64_t n_steps, hipStream_t st) {
     const int64_t chunk = (int64_t)1 << 30;
     for (int64_t done = 0; done < n_steps; done += chunk) {
         a.n_steps = std::min(chunk, n_steps - done);
-        if (c->family == 1) HIPCHK(c, launch_forward_split(a, st));
-        else if (c->family == 2) HIPCHK(c, launch_forward_pair(a, c->run.precision, c->wpb, st));
+        if (c->family == 2) HIPCHK(c, launch_forward_pair(a, c->run.precision, c->wpb, st));
         else if (c->family == 3) HIPCHK(c, launch_forward_hi(a, c->run.precision, c->hi_nmax, st));
         else HIPCHK(c, launch_forward(a, c->run.precision, c->family, c->wpb, c->run.noise_map, st));
         HIPCHK(c, launch_advance(c->dstep, a.n_steps, st));

@@ -4,9 +4,20 @@
 #include <stdint.h>
 #include <algorithm>
 
+#include <string>
+
+#include "ra.h"
 #include "ra_types.hpp"
 
 namespace ra {
+
+// Host-side helpers shared by the entry points (ra_host.cpp).
+// Validates descriptors and run options as ra_create does (RA_EINVAL + text).
+ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std::string& why);
+// Per-group device constants for beads-per-lane M, counter tag and noise map.
+GroupDev make_group(const ra_chain_desc& d, int M, int tag, int nmap);
+// Text returned by ra_last_error(NULL) on this thread.
+void set_global_error(const std::string& msg);
 
 struct FwdArgs {
     const GroupDev* groups;
@@ -47,7 +58,6 @@ struct AdjArgs {
 // nmap: noise map of the context (1 selects the kernels compiled for map 1)
 hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, int nmap,
                           hipStream_t st);
-hipError_t launch_forward_split(const FwdArgs& a, hipStream_t st);
 hipError_t launch_advance(int64_t* step, int64_t n, hipStream_t st);
 hipError_t launch_reset(int32_t* status, unsigned long long* clamps, int n_groups, int64_t* step, hipStream_t st);
 hipError_t launch_clone(const GroupDev* groups, int n_groups, int64_t max_elems, const double* parent,

@@ -1,14 +1,14 @@
-// ra_tune.cpp — cost-model and timing autotuner for the per-group tile.
+// ra_tune.cpp — cost-model and timing autotuner for the per-group tile and
+// the launch's wavefronts per workgroup.
 #include "ra_tune.hpp"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <fstream>
 #include <map>
 #include <mutex>
-#include <sstream>
-#include <fstream>
 #include <tuple>
 
 namespace ra {
@@ -40,37 +40,54 @@ int choose_beads_per_lane(int n_beads, int n_replicas, int family, int forced) {
 
 namespace {
 
-using Key = std::tuple<int, int, int, int, int>;   // N, spring, precision, family, wpb
+// One tuning result: the fastest M for a chain length and spring law under a
+// precision, kernel family, wavefronts per workgroup and noise map, and its
+// time per replica for 96 steps (to compare workgroup sizes across a batch).
+using Key = std::tuple<int, int, int, int, int, int>;   // N, spring, precision, family, wpb, noise_map
+struct Entry {
+    int M;
+    double ms_per_replica;
+};
 constexpr int TUNE_WAVES_PER_SIMD = 4;             // timing runs fill every SIMD this many times
-std::mutex g_mu;
-std::map<Key, int> g_cache;
-bool g_loaded = false;
 
-void load_cache_file() {
-    if (g_loaded) return;
-    g_loaded = true;
-    const char* path = std::getenv("RA_AUTOTUNE_CACHE");
-    if (!path) return;
+// The process keeps one table of results per cache file (the empty path when
+// RA_AUTOTUNE_CACHE is unset): the library's only process-wide state. Tuning
+// results depend on the device model and the library build, not on a
+// context, so contexts with the same groups share them.
+std::mutex g_mu;
+std::map<std::string, std::map<Key, Entry>> g_tables;
+
+std::map<Key, Entry>& table_for(const std::string& path) {
+    auto it = g_tables.find(path);
+    if (it != g_tables.end()) return it->second;
+    std::map<Key, Entry>& t = g_tables[path];
+    if (path.empty()) return t;
     std::ifstream f(path);
-    if (!f) return;
-    // one entry per line: {"N": .., "spring": .., "precision": .., "family": .., "wpb": .., "M": ..}
+    // one entry per line: {"N": .., "spring": .., "precision": .., "family": .., "wpb": ..,
+    //                      "noise_map": .., "M": .., "ms_per_replica": ..}
     std::string line;
-    while (std::getline(f, line)) {
-        int v[6];
+    while (f && std::getline(f, line)) {
+        int v[7];
+        double ms = 0.0;
         if (std::sscanf(line.c_str(),
-                        " {\"N\": %d, \"spring\": %d, \"precision\": %d, \"family\": %d, \"wpb\": %d, \"M\": %d}",
-                        &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 6)
-            g_cache[Key{v[0], v[1], v[2], v[3], v[4]}] = v[5];
+                        " {\"N\": %d, \"spring\": %d, \"precision\": %d, \"family\": %d, \"wpb\": %d, "
+                        "\"noise_map\": %d, \"M\": %d, \"ms_per_replica\": %lf}",
+                        &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &ms) == 8)
+            t[Key{v[0], v[1], v[2], v[3], v[4], v[5]}] = Entry{v[6], ms};
     }
+    return t;
 }
 
-void append_cache_file(const Key& k, int M) {
-    const char* path = std::getenv("RA_AUTOTUNE_CACHE");
-    if (!path) return;
+void append_cache_file(const std::string& path, const Key& k, const Entry& e) {
+    if (path.empty()) return;
     std::ofstream f(path, std::ios::app);
-    f << "{\"N\": " << std::get<0>(k) << ", \"spring\": " << std::get<1>(k) << ", \"precision\": "
-      << std::get<2>(k) << ", \"family\": " << std::get<3>(k) << ", \"wpb\": " << std::get<4>(k)
-      << ", \"M\": " << M << "}\n";
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "{\"N\": %d, \"spring\": %d, \"precision\": %d, \"family\": %d, \"wpb\": %d, "
+                  "\"noise_map\": %d, \"M\": %d, \"ms_per_replica\": %.9g}\n",
+                  std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                  std::get<5>(k), e.M, e.ms_per_replica);
+    f << buf;
 }
 
 // Time 96 fused steps of one group with a forced tile M and enough replicas
@@ -96,9 +113,13 @@ double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int M, int wpb,
     r.noise_map = run.noise_map;
     ra_ctx* ctx = nullptr;
     if (ra_create(&ctx, &g, 1, &r, st) != RA_OK) return -1.0;
-    // straight parent along x with unit bonds (inside any FENE extension b >= 2)
+    // straight parent along x; its bonds stay inside the FENE extension
+    // (half of Q0 = sqrt(b kT/H), at most 0.5), so the timed kernel does the
+    // work of a valid chain
+    double bond = 0.5;
+    if (d.spring == RA_FENE) bond = std::min(0.5, 0.5 * std::sqrt(d.b * d.kT / d.H));
     std::vector<double> parent(3 * (size_t)d.n_beads, 0.0);
-    for (int i = 0; i < d.n_beads; ++i) parent[3 * i] = 0.5 * i;
+    for (int i = 0; i < d.n_beads; ++i) parent[3 * i] = bond * i;
     double* dp = nullptr;
     double ms = -1.0;
     hipEvent_t e0, e1;
@@ -121,7 +142,9 @@ double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int M, int wpb,
         }
         (void)hipEventDestroy(e0);
     }
-    // a timing probe: failures above leave ms < 0 and the candidate unused
+    // a timing probe: failures above leave ms < 0 and the candidate unused;
+    // an invalid parent would time a kernel that skips its work
+    if (ms >= 0 && ra_sync_status(ctx) != RA_OK) ms = -1.0;
     (void)hipStreamSynchronize(st);
     if (dp) (void)hipFree(dp);
     ra_destroy(ctx);
@@ -131,26 +154,45 @@ double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int M, int wpb,
 }  // namespace
 
 ra_status autotune_tiles(const std::vector<ra_chain_desc>& descs, const ra_run_desc& run, int family,
-                         int waves_per_block, hipStream_t stream, std::vector<int>& Ms, std::string& why) {
+                         int& waves_per_block, hipStream_t stream, std::vector<int>& Ms, std::string& why) {
     std::lock_guard<std::mutex> lk(g_mu);
-    load_cache_file();
-    for (size_t i = 0; i < descs.size(); ++i) {
-        const ra_chain_desc& d = descs[i];
-        const Key k{d.n_beads, d.spring, run.precision, family, waves_per_block};
-        auto it = g_cache.find(k);
-        if (it != g_cache.end()) { Ms[i] = it->second; continue; }
-        double best_ms = -1.0;
-        int best = Ms[i];
-        for (int M : family_beads_per_lane(family)) {
-            if (!legal(d.n_beads, M)) continue;
-            const double ms = time_tile(d, run, M, waves_per_block, stream);   // per replica
-            if (ms < 0) { why = "timing run failed"; return RA_EDEVICE; }
-            if (best_ms < 0 || ms < best_ms) { best_ms = ms; best = M; }
+    const char* env = std::getenv("RA_AUTOTUNE_CACHE");
+    const std::string path = env ? env : "";
+    std::map<Key, Entry>& table = table_for(path);
+    // candidate workgroup sizes: the caller's, or all three when it left the choice open
+    std::vector<int> wpbs = waves_per_block ? std::vector<int>{waves_per_block} : std::vector<int>{1, 2, 4};
+    double best_total = -1.0;
+    std::vector<int> best_Ms = Ms;
+    int best_wpb = waves_per_block ? waves_per_block : 4;
+    for (int wpb : wpbs) {
+        std::vector<int> Mw(descs.size());
+        double total = 0.0;   // predicted batch time: sum over groups of R x time per replica
+        for (size_t i = 0; i < descs.size(); ++i) {
+            const ra_chain_desc& d = descs[i];
+            const Key k{d.n_beads, d.spring, run.precision, family, wpb, run.noise_map};
+            auto it = table.find(k);
+            if (it == table.end()) {
+                Entry best{Ms[i], -1.0};
+                for (int M : family_beads_per_lane(family)) {
+                    if (!legal(d.n_beads, M)) continue;
+                    const double ms = time_tile(d, run, M, wpb, stream);
+                    if (ms < 0) { why = "timing run failed"; return RA_EDEVICE; }
+                    if (best.ms_per_replica < 0 || ms < best.ms_per_replica) best = Entry{M, ms};
+                }
+                it = table.emplace(k, best).first;
+                append_cache_file(path, k, best);
+            }
+            Mw[i] = it->second.M;
+            total += it->second.ms_per_replica * d.n_replicas;
         }
-        Ms[i] = best;
-        g_cache[k] = best;
-        append_cache_file(k, best);
+        if (best_total < 0 || total < best_total) {
+            best_total = total;
+            best_Ms = Mw;
+            best_wpb = wpb;
+        }
     }
+    Ms = best_Ms;
+    waves_per_block = best_wpb;
     return RA_OK;
 }
 

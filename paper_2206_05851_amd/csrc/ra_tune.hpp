@@ -19,9 +19,13 @@ const std::vector<int>& family_beads_per_lane(int family);
 int choose_beads_per_lane(int n_beads, int n_replicas, int family, int forced);
 
 // Times every legal M for each distinct (N, spring) of the batch with a short
-// run of the fused kernel on 256 replicas and keeps the fastest. Results are cached in
-// memory and, if RA_AUTOTUNE_CACHE names a file, in that JSON file.
+// run of the fused kernel that fills every SIMD four times and keeps the
+// fastest per replica. With waves_per_block = 0 on entry it also tries 1, 2
+// and 4 wavefronts per workgroup and returns the size whose tiles give the
+// least predicted batch time (sum over groups of R x time per replica).
+// Results are kept per process and, if RA_AUTOTUNE_CACHE names a file, in that
+// JSON-lines file (read when a context first uses it).
 ra_status autotune_tiles(const std::vector<ra_chain_desc>& descs, const ra_run_desc& run, int family,
-                         int waves_per_block, hipStream_t stream, std::vector<int>& Ms, std::string& why);
+                         int& waves_per_block, hipStream_t stream, std::vector<int>& Ms, std::string& why);
 
 }  // namespace ra

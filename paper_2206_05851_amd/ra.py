@@ -374,8 +374,8 @@ class Replicas:
         return list(M), list(P)
 
     def kernel_family(self):
-        """1 = noise-producer split, 2 = pair kernel, 3 = HI kernel, 4 / 16 = one-wave
-        families, 0 = plain path."""
+        """2 = pair kernel, 3 = HI kernel, 4 / 16 = one-wave families (1-4 and 6-16
+        beads per lane), 0 = plain path."""
         G = len(self.groups)
         M = (ctypes.c_int32 * G)()
         P = (ctypes.c_int32 * G)()

@@ -124,3 +124,10 @@ def test_mixed_model_classes_rejected_on_host(lib):
         p = ctypes.c_void_p()
         assert lib.ra_create(ctypes.byref(p), arr, 2, ctypes.byref(run), None) == -1
         assert "only" in lib.ra_last_error(None).decode()
+
+
+def test_tile_policy_values_checked(lib):
+    for bad in (2, 3, 1000, 1017, -1):
+        rc, msg = _create(lib, {}, dict(tile_policy=bad))
+        assert rc == -1 and "tile_policy" in msg, bad
+

@@ -45,10 +45,10 @@ def _check(g_gpu, g_ref, rtol):
 
 
 @pytest.mark.parametrize("spring,flow,N,policy", [(wl.FENE, wl.UNIAXIAL, 12, 0), (wl.FENE, wl.SHEAR, 33, 0),
-                                                  (wl.FENE, wl.SHEAR, 33, 2), (wl.HOOKEAN, wl.PLANAR, 10, 2),
+                                                  (wl.FENE, wl.SHEAR, 33, 1002), (wl.HOOKEAN, wl.PLANAR, 10, 1003),
                                                   (wl.FENE, wl.PLANAR, 150, 0)])
 def test_adjoint_matches_oracle_tangents_200_steps(spring, flow, N, policy):
-    # policy 0 picks the noise-producer forward for N <= 64, policy 2 the one-wave one
+    # policy 0 is the cost model's tile; 1000 + m forces m beads per lane
     b = 40.0 if spring == wl.FENE else 0.0
     g = wl.group(N, 64, 1e-4, spring, 1.3, b, flow, 30.0 if flow == wl.SHEAR else 0.8)
     parent = wl.equilibrium_parent(N, spring, 1.3, b, seed=N)

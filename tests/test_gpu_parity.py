@@ -134,12 +134,11 @@ def test_tile_choice_is_bitwise_invariant():
     g = wl.group(N, R, 1e-4, wl.FENE, 1.0, 80.0, wl.SHEAR, 20.0)
     parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 80.0, seed=9)
     ref = None
-    for M in (1, 2, 3, 4, "split"):
+    for M in (1, 2, 3, 4):
         announce("tile M=%s" % M)
-        policy = 3 if M == "split" else 1000 + M
-        rep = run_gpu([g], [parent], 5, 150, 50, tile_policy=policy)
-        assert rep.kernel_family() == (1 if M == "split" else 4)
-        assert rep.tile_info()[0] == [1 if M == "split" else M]
+        rep = run_gpu([g], [parent], 5, 150, 50, tile_policy=1000 + M)
+        assert rep.kernel_family() == 4
+        assert rep.tile_info()[0] == [M]
         smp = rep.samples()[0].cpu().numpy()
         rep.sync_status()
         if ref is None:
@@ -148,30 +147,6 @@ def test_tile_choice_is_bitwise_invariant():
             assert rel_err(smp, o.samples()[0]) < TOL32
         else:
             assert np.array_equal(smp, ref), M
-
-
-@pytest.mark.parametrize("N,R,steps,chunks", [(50, 64, 300, (300,)), (20, 45, 150, (37, 13, 100)),
-                                               (64, 9, 77, (77,)), (2, 70, 120, (120,))])
-def test_noise_producer_split_is_bitwise_equal_to_one_wave(N, R, steps, chunks):
-    # packed replicas (N=20, P=3; N=2, P=32), a partial last block, step counts
-    # off the 16-step chunk grid, several ra_step calls, and checkpoints
-    g = wl.group(N, R, 1e-4, wl.FENE, 1.0, 60.0, wl.UNIAXIAL, 0.3, stream_id=3)
-    parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 60.0, seed=N)
-    out = {}
-    for policy in (2, 3):
-        announce("split check N=%d policy=%d" % (N, policy))
-        rep = run_gpu([g], [parent], 31, 0, 25, max_windows=steps // 25, tile_policy=policy,
-                      checkpoint_every=10, max_steps=steps)
-        assert rep.kernel_family() == (4 if policy == 2 else 1)
-        for c in chunks:
-            rep.step(c)
-        out[policy] = (rep.samples()[0].cpu().numpy(), rep.bonds()[0].cpu().numpy(), rep.guard_counts())
-        rep.sync_status()
-    assert np.array_equal(out[2][0], out[3][0])
-    assert np.array_equal(out[2][1], out[3][1])
-    assert out[2][2] == out[3][2]
-    o = run_oracle([g], [parent], 31, steps, 25)
-    assert rel_err(out[3][0], o.samples()[0]) < TOL32
 
 
 @pytest.mark.parametrize("precision,tol", [(32, TOL32), (64, TOL64)])
