@@ -1,31 +1,40 @@
 """Benchmark: replica-averaged Brownian dynamics on one MI355X.
 
-Headline workload (one "step" = the whole hot path once):
-  FENE chain, N = 50 beads, b = 100, uniaxial elongation at Wi = 2,
-  dt = 1e-4, 1024 replicas cloned from one equilibrium parent,
-  10^4 Euler-Maruyama steps, tension sampled every 100 steps (100 windows),
-  FP32 state, FP64 replica mean/std, Bell rates k0 = 1e-6, x = 0.1.
-  = ra_init_chains + ra_step(10^4) + ra_average_forces + ra_bell_rates,
+Headline workload (one "step" = the whole hot path once), the largest
+single-GPU configuration:
+  large1000: FENE chain, N = 1000 beads, b = 400, start-up uniaxial elongation
+  at Wi = 10, dt = 5e-5, 8192 replicas cloned from one equilibrium parent,
+  2 x 10^4 Euler-Maruyama steps, replica-averaged (RSF) and time-averaged
+  (TSF) tension profiles over windows of 500 steps (40 windows), FP32 state,
+  FP64 averages, Bell rates k0 = 1e-6, x = 0.1 with one event draw per spring
+  and window
+  = ra_init_chains + ra_step(2 x 10^4) + ra_average_forces (RSF and TSF)
+    + ra_bell_rates (rates, rate sums, events),
   inputs (parent conformation) resident in HBM before the timed region.
-  Noise map 1 (--noise-map, default 1): each Philox block gives four normals,
-  three blocks serve four bead-steps; the oracle baseline draws the same.
 
-value = replica*bead*steps per second (1024 * 50 * 10^4 per step / time).
+value = replica*bead*steps per second (8192 * 1000 * 2 x 10^4 per step / time).
 
-Also reported, each measured once after warm-up: the plain unbatched GPU path
-on the same workload (one launch per EM step, state in HBM; speedup), the
-adjoint (N = 100, 4096 replicas, 2000 steps, checkpoints every 100), the
-batched run (512 uneven FENE chains, one graph-captured persistent launch),
-the 1000-bead transient (8192 replicas, 2e4 steps, RSF + TSF) and the RSF
-sampling cycle (a parent trajectory re-cloned into 1000 replicas every 750
-steps, 20 windows, with ISF/TSF/RSF, sigma(N_R) and MFTU) on the FENE chain,
-on the paper's collapsed polymer (rest-length springs + LJ) and on the full
-model with hydrodynamic interaction (parent + 50 replicas, 4 windows).
-The roofline object is for the fused forward kernel; its time is taken with
-HIP events on the stream the kernel runs on. cpu_baseline is the FP64 oracle
-on a bounded sample of the same workload, on the host's cores.
+The roofline object is for the fused forward kernel of the headline: its
+duration is taken with HIP events on the stream it is launched on, and its
+algorithmic work is the VALU lane-slots per replica*bead*step (below) times
+the replica*bead*steps of one launch. cpu_baseline is the FP64 oracle on a
+bounded sample of the same workload (replica ranges, all steps) on the host's
+cores, one thread and all threads, and the GPU's samples are compared with it.
+
+Also reported, each measured after warm-up: the plain unbatched GPU path on
+the headline (one launch per EM step, state in HBM; a 2000-step prefix,
+extrapolated) and on fene50; fene50 itself (N = 50, 1024 replicas, 10^4 steps);
+the adjoint (N = 100, 4096 replicas, 2000 steps, checkpoints every 100); the
+batched run (512 uneven FENE chains, one graph-captured persistent launch,
+cost-model and autotuned tiles); the RSF sampling cycle (a parent trajectory
+re-cloned into 1000 replicas every 750 steps, 20 windows, with ISF/TSF/RSF,
+sigma(N_R) and MFTU) on the FENE chain, on the paper's collapsed polymer
+(rest-length springs + LJ) and on the full model with hydrodynamic interaction.
+The roofline fraction of each chain workload under the same slot count is
+listed in roofline_fractions.
 """
 import argparse
+import concurrent.futures
 import json
 import os
 import sys
@@ -38,31 +47,36 @@ if ROOT not in sys.path:
 METRIC = "replica·bead·steps/s and adjoint steps/s vs plain GPU path at 1e-4 rel err"
 
 # Peak VALU issue rate of one MI355X in lane-slots: 256 CUs x 4 SIMDs x 16 lanes
-# x 2.4 GHz = 39.3 T lane-slots/s. One lane-slot is one lane of one full-rate
-# VALU instruction (a wave64 instruction occupies a SIMD for 4 cycles); it is
-# the published 157.3 TFLOP/s FP32 vector peak divided by 2 flops per FMA and
-# by 2 for the packed FP32 forms, which integer work cannot use.
+# x 2.4 GHz = 39.3 T lane-slots/s. One lane-slot is one lane of one VALU
+# instruction issue (a wave64 instruction occupies its SIMD's VALU for 4
+# cycles); it is the published 157.3 TFLOP/s FP32 vector peak divided by 2
+# flops per FMA and by 2 for the packed FP32 forms, which integer work cannot use.
 VALU_PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
-# Algorithmic lane-slots per replica*bead*step of the FENE forward step, at the
-# issue cost of the gfx950 instruction that each operation needs (a
-# transcendental occupies 2 slots, everything else 1):
-#   Philox4x32-10: 10 rounds x (2 products 32x32->64 + 2 three-input XORs) = 40
-#   uniform maps: 4 words x (exponent splice + subtract)                      =  8
-#   Box-Muller: 2 log + 2 sqrt + 3 sin/cos (2 slots each) + 5 scalings        = 19
-#   FENE bond update (spring law, flow, neighbour exchange, EM combine)      = 32
-VALU_SLOTS_PER_BEAD_STEP_FENE = 40 + 8 + 19 + 32
+# Algorithmic lane-slots per replica*bead*step of the FENE forward step: the
+# gfx950 VALU instructions the step needs, one slot each, the same count for
+# every tile layout. Transcendentals (v_log, v_sqrt, v_sin, v_cos, v_rcp) are
+# not counted: they execute on the transcendental unit beside the VALU (on
+# large1000 the kernel issues 1.05x more VALU instructions than 4-cycle slots
+# exist in its active cycles; without the transcendentals, 0.95x).
+#   Philox4x32-10: 10 rounds x (2 v_mad_u64_u32 + 2 v_bitop3_b32)           = 40
+#   uniform maps: 4 words x (v_alignbit_b32 + subtract)                        =  8
+#   Box-Muller, 3 normals: 2 log scalings + 3 radius products                  =  5
+#     (beside them on the transcendental unit: 2 log, 2 sqrt, 3 sin/cos)
+#   FENE bond update: |Q|^2 (3), s, 1 - s, guard compare, g Q (3), neighbour
+#     Laplacian by DPP (9), noise difference by DPP (3), flow + EM increment
+#     (8), add (3)                                                            = 31
+#     (beside them: the reciprocal 1/(1 - s))
 # With noise map 1 a Philox block gives four normals and serves 4/3 bead-steps:
 #   Philox 40 x 3/4 = 30; uniform maps 8 x 3/4 = 6; Box-Muller with both outputs
-#   of the second pair, 2 log + 2 sqrt + 4 sin/cos (2 slots each) + 6 scalings
-#   = 22 per block, x 3/4 = 16.5; FENE bond update 32
-VALU_SLOTS_PER_BEAD_STEP_FENE_MAP1 = 30 + 6 + 16.5 + 32
-# HBM bytes per launch of the forward kernel on the headline workload, read with
-# rocprofv3 counters (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, both factors from
-# a 1 GiB device copy). Valid only for the kernel sources they were taken on:
-# the digest of those sources is recorded with the figure, and bench.py reports
-# null when the sources have changed since.
-FWD_TRAFFIC = {"sha256": "59e3a42a4fdb70ba6f5abdc9b5a3c9c26073053b867d8cb3bc54d0182f0d7ae7", "noise_map": 1,
-               "bytes": (429.625 * 2.0 + 20592.0) * 1024}
+#   of the second pair (2 log scalings + 4 radius products) x 3/4 = 4.5;
+#   FENE bond update 31.
+SLOTS_PER_BEAD_STEP = {0: 40 + 8 + 5 + 31, 1: 30 + 6 + 4.5 + 31}
+# HBM bytes per launch of the headline's forward kernel, read with rocprofv3
+# counters (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, both factors from a 1 GiB
+# device copy in the same runs). Valid only for the kernel sources they were
+# taken on: the digest of those sources is recorded with the figure, and
+# traffic is reported as null when the sources have changed since.
+FWD_TRAFFIC = {"sha256": None, "bytes": None}
 FWD_SOURCES = ("ra_kernels.hip", "ra_chain.hpp", "ra_device.hpp", "ra_types.hpp", "ra_launch.hpp",
                "ra_host.cpp", "ra_tune.cpp", "ra_tune.hpp")
 
@@ -87,24 +101,6 @@ def cpu_cores():
         return os.cpu_count()
 
 
-def cpu_baseline(groups, parents, run, n_replicas, noise_map=0):
-    """FP64 oracle on replicas [0, n_replicas) of the headline workload, all
-    steps, plus the replica averages and Bell rates (single thread)."""
-    from oracle import ora
-    g = dict(groups[0])
-    t0 = time.perf_counter()
-    o = ora.Oracle([g], run["seed"], run["sample_every"], run["steps"] // run["sample_every"],
-                   noise_map=noise_map)
-    o.set_replicas(0, 0, n_replicas)
-    o.init_chains(parents)
-    o.step(run["steps"])
-    mean, std = o.average_forces()
-    o.bell_rates(mean, run["k0"], run["x_dagger"])
-    dt = time.perf_counter() - t0
-    work = n_replicas * g["n_beads"] * run["steps"]
-    return work / dt, dt, o.samples()[0]
-
-
 def time_once(fn):
     import torch
     torch.cuda.synchronize()
@@ -114,6 +110,88 @@ def time_once(fn):
     return time.perf_counter() - t0
 
 
+class EventTimer:
+    """HIP events around one call on a given stream; mean duration in ms."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.pairs = []
+
+    def run(self, fn):
+        import torch
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        r = fn()
+        e1.record(self.stream)
+        self.pairs.append((e0, e1))
+        return r
+
+    def mean_ms(self):
+        import numpy as np
+        return float(np.mean([a.elapsed_time(b) for a, b in self.pairs]))
+
+
+def roofline_frac(slots, work, seconds):
+    return slots * work / seconds / VALU_PEAK_LANE_SLOTS
+
+
+# ---------------------------------------------------------------------------
+# FP64 oracle baseline (host cores) on replica ranges of a one-group workload
+# ---------------------------------------------------------------------------
+def oracle_range(groups, parents, run, k_begin, k_end, noise_map=0):
+    """The whole pass (clone, all steps, RSF/TSF averages, Bell rates and
+    events) of the oracle on replicas [k_begin, k_end); returns seconds and the
+    per-replica samples (and TSF samples)."""
+    from oracle import ora
+    tsf = bool(run.get("tsf", False))
+    t0 = time.perf_counter()
+    o = ora.Oracle(groups, run["seed"], run["sample_every"], run["steps"] // run["sample_every"], tsf=tsf,
+                   noise_map=noise_map)
+    o.set_replicas(0, k_begin, k_end)
+    o.init_chains(parents)
+    o.step(run["steps"])
+    mean = o.average_forces(tsf=tsf)[0]
+    o.bell_rates(mean, run["k0"], run["x_dagger"], events=tsf)
+    secs = time.perf_counter() - t0
+    smp = o.samples(tsf=tsf)
+    o.close()
+    if tsf:
+        return secs, smp[0][0], smp[1][0]
+    return secs, smp[0], None
+
+
+def cpu_baseline(groups, parents, run, single_replicas, per_thread, threads, noise_map=0):
+    import numpy as np
+    N, T = groups[0]["n_beads"], run["steps"]
+    log("cpu baseline: oracle, 1 thread, replicas 0..%d x %d steps" % (single_replicas - 1, T))
+    t1, _, _ = oracle_range(groups, parents, run, 0, single_replicas, noise_map)
+    log("cpu baseline: oracle, %d threads x %d replicas x %d steps" % (threads, per_thread, T))
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda i: oracle_range(groups, parents, run, i * per_thread, (i + 1) * per_thread,
+                                                   noise_map), range(threads)))
+    tall = time.perf_counter() - t0
+    n_all = threads * per_thread
+    smp = np.concatenate([p[1] for p in parts], axis=1)
+    tsmp = np.concatenate([p[2] for p in parts], axis=1) if parts[0][2] is not None else None
+    return {"single": (single_replicas * N * T / t1, t1), "all": (n_all * N * T / tall, tall, n_all),
+            "samples": smp, "tsf_samples": tsmp}
+
+
+def accuracy(got, ref, first_windows):
+    """Max relative errors: every sample, and the replica-mean profile of the
+    compared replicas, over all windows and over the first windows."""
+    import numpy as np
+    rel = np.abs(got - ref) / np.abs(ref)
+    prof = np.abs(got.mean(axis=1) - ref.mean(axis=1)) / np.abs(ref.mean(axis=1))
+    return {"samples": float(rel.max()), "samples_first": float(rel[:first_windows].max()),
+            "profile": float(prof.max()), "profile_first": float(prof[:first_windows].max())}
+
+
+# ---------------------------------------------------------------------------
+# Extras
+# ---------------------------------------------------------------------------
 def rsf_cycle_bench(workload, desc, dev, name, noise_map=0):
     """One RSF cycle (parent context on its own stream, re-clone per window)
     with the estimators built on it, timed after a warm-up cycle."""
@@ -152,27 +230,224 @@ def rsf_cycle_bench(workload, desc, dev, name, noise_map=0):
            "unit": "replica·bead·steps/s (whole cycle incl. parent)", "ms_per_cycle": 1e3 * t,
            "us_per_window": 1e6 * t / rW, "mftu": {k: float(v[0]) for k, v in mftu.items()},
            "noise_map": noise_map}
+    # MFTU by sampling unfolding events over the cycle's rate profiles (1024
+    # trials, up to 2^20 windows each), beside 1/<sum k> above
+    isf, _, tsf, _ = rpar.average_forces(tsf=True)
+    rsf, _ = rrep.average_forces()
+    ev = {}
+    t_ev = 0.0
+    for key, prof in (("isf", isf), ("tsf", tsf), ("rsf", rsf)):
+        rates, _ = rpar.bell_rates(prof, rrun["k0"], rrun["x_dagger"])
+        t0 = time.perf_counter()
+        m, f = rpar.mftu_events(rates, 1024, 1 << 20)
+        torch.cuda.synchronize()
+        t_ev += time.perf_counter() - t0
+        ev[key] = {"mftu": float(m[0]), "censored": float((f[:, 0] < 0).float().mean().item())}
+    res["mftu_events"] = dict(ev, trials=1024, max_windows=1 << 20, ms=1e3 * t_ev)
     rpar.close()
     rrep.close()
     log("%s: %.2f ms per cycle (%.1f us per window)" % (name, 1e3 * t, 1e6 * t / rW))
     return res
 
 
+def sigma_sweep_bench(dev, noise_map):
+    """sigma(N_R) of the RSF estimate against the evolution time S (the
+    analogue of Figs. 2 and 5): the rsf50 chain's RSF cycle at several S
+    (parent steps P = S), 20 windows each, sigma over blocks of N_R replicas
+    for the middle spring (window mean) and over all springs; beside them the
+    spread over windows of the parent's ISF and TSF of the middle spring."""
+    import numpy as np
+    import torch
+    from paper_2206_05851_amd import ra
+    from paper_2206_05851_amd import workloads as wl
+    rg, rp, rrun = wl.rsf50()
+    rpd = torch.from_numpy(np.concatenate([np.ravel(x) for x in rp])).to(dev)
+    W, mid = rrun["n_windows"], rg[0]["n_beads"] // 2 - 1
+    rows = []
+    t0 = time.perf_counter()
+    for S in (75, 250, 750, 2500):
+        par = ra.Replicas([dict(x, n_replicas=1) for x in rg], rrun["seed"], sample_every=S, max_windows=W,
+                          tsf=True, noise_tag=1, device=dev, noise_map=noise_map)
+        rep = ra.Replicas(rg, rrun["seed"], sample_every=S, max_windows=W, device=dev, noise_map=noise_map)
+        par.init_chains(rpd)
+        rep.init_chains(rpd)
+        rep.rsf_cycle(par, W, S)
+        isf, _, tsf, _ = [x.cpu().numpy() for x in par.average_forces(tsf=True)]
+        row = {"S_steps": S, "S_time": S * rg[0]["dt"],
+               "isf_spread_mid": float(isf[:, mid].std(ddof=1)), "tsf_spread_mid": float(tsf[:, mid].std(ddof=1))}
+        for b in (10, 20, 40):
+            sig = rep.block_sigma(b).cpu().numpy()
+            row["sigma_NR%d_mid" % b] = float(sig[:, mid].mean())
+            row["sigma_NR%d_all" % b] = float(sig.mean())
+        par.sync_status()
+        rep.sync_status()
+        par.close()
+        rep.close()
+        rows.append(row)
+    log("sigma sweep: %d evolution times in %.2f s" % (len(rows), time.perf_counter() - t0))
+    return {"workload": "rsf50 chain (FENE N=50 b=100, shear Wi=50), RSF cycles at S = 75, 250, 750, 2500 steps "
+                        "(dt = 1e-4), parent steps P = S, 1000 replicas, 20 windows; sigma over blocks of N_R = "
+                        "10, 20, 40", "noise_map": noise_map, "rows": rows}
+
+
+def fene50_bench(dev, noise_map, passes=10):
+    """fene50 (N = 50, 1024 replicas, 10^4 steps) fused, and its plain path."""
+    import numpy as np
+    import torch
+    from paper_2206_05851_amd import ra
+    from paper_2206_05851_amd import workloads as wl
+    groups, parents, run = wl.fene50()
+    g = groups[0]
+    R, N, T, S = g["n_replicas"], g["n_beads"], run["steps"], run["sample_every"]
+    W = T // S
+    parent = torch.from_numpy(np.ascontiguousarray(parents[0]).reshape(-1)).to(dev)
+    rep = ra.Replicas(groups, run["seed"], sample_every=S, max_windows=W, device=dev, noise_map=noise_map)
+    timer = EventTimer(torch.cuda.current_stream())
+    mean = torch.empty((W, N - 1), dtype=torch.float64, device=dev)
+    std = torch.empty_like(mean)
+
+    def one(record):
+        rep.init_chains(parent)
+        if record:
+            timer.run(lambda: rep.step(T))
+        else:
+            rep.step(T)
+        rep.average_forces(out=(mean, std))
+        rep.bell_rates(mean, run["k0"], run["x_dagger"])
+
+    for _ in range(2):
+        one(False)
+    t = min(time_once(lambda: one(True)) for _ in range(passes))
+    rep.sync_status()
+    work = R * N * T
+    kms = timer.mean_ms()
+    out = {"workload": "fene50: FENE N=50 b=100, uniaxial Wi=2, dt=1e-4, R=1024, 10^4 steps, sample every 100, "
+                       "Bell rates", "value": work / t, "ms_per_step": 1e3 * t, "kernel_ms": kms,
+           "noise_map": noise_map,
+           "roofline_frac": roofline_frac(SLOTS_PER_BEAD_STEP[noise_map], work, kms * 1e-3)}
+    # plain unbatched path, same workload and counters
+    plain = ra.Replicas(groups, run["seed"], sample_every=S, max_windows=W, plain=True, device=dev,
+                        noise_map=noise_map)
+    pm = torch.empty_like(mean)
+    ps = torch.empty_like(mean)
+
+    def plain_pass():
+        plain.init_chains(parent)
+        plain.step(T)
+        plain.average_forces(out=(pm, ps))
+        plain.bell_rates(pm, run["k0"], run["x_dagger"])
+
+    plain_pass()
+    tp = min(time_once(plain_pass) for _ in range(2))
+    plain.sync_status()
+    out["plain_path"] = {"value": work / tp, "ms_per_step": 1e3 * tp, "speedup_fused_over_plain": tp / t,
+                         "max_rel_diff_profile_vs_fused": torch.max(torch.abs(pm - mean) / mean).item()}
+    plain.close()
+    rep.close()
+    log("fene50: %.3f ms per pass (kernel %.3f ms), plain %.2f ms" % (1e3 * t, kms, 1e3 * tp))
+    return out
+
+
+def adjoint_bench(dev, noise_map):
+    import numpy as np
+    import torch
+    from paper_2206_05851_amd import ra
+    from paper_2206_05851_amd import workloads as wl
+    ag, ap_, arun = wl.adjoint100()
+    ga = ag[0]
+    apar = torch.from_numpy(np.ascontiguousarray(ap_[0]).reshape(-1)).to(dev)
+    W = arun["steps"] // arun["sample_every"]
+    gm = torch.ones((W, ga["n_beads"] - 1), dtype=torch.float64, device=dev)
+    awork = ga["n_replicas"] * ga["n_beads"] * arun["steps"]
+    res = {}
+    for label, K in (("every_100", arun["checkpoint_every"]), ("auto_interval", ra.CKPT_AUTO)):
+        adj = ra.Replicas(ag, arun["seed"], sample_every=arun["sample_every"], max_windows=W,
+                          checkpoint_every=K, max_steps=arun["steps"], device=dev, noise_map=noise_map)
+
+        def fwd():
+            adj.init_chains(apar)
+            adj.step(arun["steps"])
+
+        def bwd():
+            m, _ = adj.average_forces()
+            return adj.backward(m, gm, None)
+
+        fwd()
+        bwd()
+        tf = min(time_once(fwd) for _ in range(2))
+        tb = min(time_once(bwd) for _ in range(2))
+        adj.sync_status()
+        res[label] = {"checkpoint_every": adj.checkpoint_interval(), "value": awork / tb,
+                      "forward_value": awork / tf, "backward_ms": 1e3 * tb, "forward_ms": 1e3 * tf,
+                      "backward_over_forward": tb / tf}
+        adj.close()
+        log("adjoint %s: fwd %.2f ms bwd %.2f ms" % (label, 1e3 * tf, 1e3 * tb))
+    out = {"workload": "adjoint100: FENE N=100 b=100, uniaxial Wi=4, R=4096, dt=1e-4, 2000 steps, "
+                       "gradient of the profile w.r.t. (rate, H, b)",
+           "value": res["every_100"]["value"], "unit": "replica·bead·steps/s (backward incl. recompute)",
+           "noise_map": noise_map,
+           "forward_roofline_frac": roofline_frac(SLOTS_PER_BEAD_STEP[noise_map], awork,
+                                                  res["every_100"]["forward_ms"] * 1e-3)}
+    out.update(res)
+    return out
+
+
+def batched_bench(dev, noise_map):
+    import numpy as np
+    import torch
+    from paper_2206_05851_amd import ra
+    from paper_2206_05851_amd import workloads as wl
+    bg, bp, brun = wl.batched512()
+    bpar = torch.from_numpy(np.concatenate([np.ascontiguousarray(p).reshape(-1) for p in bp])).to(dev)
+    bwork = sum(x["n_replicas"] * x["n_beads"] for x in bg) * brun["steps"]
+    res = {}
+    for label, policy in (("cost_model", 0), ("autotuned", 1)):
+        t_tune = time.perf_counter()
+        bat = ra.Replicas(bg, brun["seed"], sample_every=brun["sample_every"],
+                          max_windows=brun["steps"] // brun["sample_every"], use_graph=True, device=dev,
+                          tile_policy=policy, noise_map=noise_map)
+        t_tune = time.perf_counter() - t_tune
+        timer = EventTimer(torch.cuda.current_stream())
+
+        def one():
+            bat.init_chains(bpar)
+            timer.run(lambda: bat.step(brun["steps"]))
+            m, s = bat.average_forces()
+            bat.bell_rates(m, brun["k0"], brun["x_dagger"])
+
+        one()
+        timer.pairs.clear()
+        t = min(time_once(one) for _ in range(3))
+        bat.sync_status()
+        kms = timer.mean_ms()
+        res[label] = {"ms_per_step": 1e3 * t, "kernel_ms": kms, "create_s": t_tune,
+                      "roofline_frac": roofline_frac(SLOTS_PER_BEAD_STEP[noise_map], bwork, kms * 1e-3)}
+        bat.close()
+        log("batched (%s): %.2f ms per pass, kernel %.2f ms" % (label, 1e3 * t, kms))
+    best = min(res.values(), key=lambda r: r["ms_per_step"])
+    out = {"workload": "batched512: 512 FENE chains N~U{20..200}, b~U[50,200], planar Wi~U[0.5,5] / shear "
+                       "Wi~U[1,50], R~U{16..256}, 5000 steps, one graph-captured persistent launch",
+           "value": bwork / (best["ms_per_step"] * 1e-3), "noise_map": noise_map}
+    out.update(res)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="plain,adjoint,batched,large1000,rsf50,collapsed50,hi50",
-                    help="comma-separated extra workloads to measure once")
-    ap.add_argument("--cpu-replicas", type=int, default=384)
-    ap.add_argument("--tile-policy", type=int, default=0,
-                    help="ra_run_desc.tile_policy for the headline workload (0 = cost model)")
+    ap.add_argument("--extras", default="plain,fene50,adjoint,batched,rsf50,sigma_sweep,collapsed50,hi50",
+                    help="comma-separated extra workloads to measure")
+    ap.add_argument("--cpu-single-replicas", type=int, default=2,
+                    help="oracle replicas on one thread (all 2 x 10^4 steps)")
+    ap.add_argument("--cpu-replicas-per-thread", type=int, default=2,
+                    help="oracle replicas per thread on all threads")
     ap.add_argument("--noise-map", type=int, default=1, choices=(0, 1),
-                    help="ra_run_desc.noise_map of the headline, plain, adjoint, batched and rsf50 workloads "
-                         "(1: four normals per Philox block)")
+                    help="ra_run_desc.noise_map of fene50, its plain path, the adjoint, batched and rsf50 "
+                         "(the headline's 16 beads per lane run noise map 0)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -189,33 +464,25 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    groups, parents, run = wl.fene50()
+    groups, parents, run = wl.large1000()
     g = groups[0]
     R, N, T, S = g["n_replicas"], g["n_beads"], run["steps"], run["sample_every"]
     W = T // S
     parent = torch.from_numpy(np.ascontiguousarray(parents[0]).reshape(-1)).to(dev)
-    rep = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W, device=dev,
-                      tile_policy=args.tile_policy, noise_map=args.noise_map)
-    slots = VALU_SLOTS_PER_BEAD_STEP_FENE_MAP1 if args.noise_map else VALU_SLOTS_PER_BEAD_STEP_FENE
-    mean = torch.empty((W, N - 1), dtype=torch.float64, device=dev)
-    std = torch.empty_like(mean)
-    stream = torch.cuda.current_stream()
-    ev = []
+    rep = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W, tsf=True, device=dev)
+    outs = [torch.empty((W, N - 1), dtype=torch.float64, device=dev) for _ in range(4)]
+    timer = EventTimer(torch.cuda.current_stream())
 
     def one_step(record):
         rep.init_chains(parent)
         if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        rep.step(T)
-        if record:
-            e1.record(stream)
-            ev.append((e0, e1))
-        rep.average_forces(out=(mean, std))
-        return rep.bell_rates(mean, run["k0"], run["x_dagger"])
+            timer.run(lambda: rep.step(T))
+        else:
+            rep.step(T)
+        m, s, tm, ts = rep.average_forces(tsf=True)
+        return rep.bell_rates(m, run["k0"], run["x_dagger"], events=True)
 
-    log("warmup %d" % args.warmup)
+    log("headline large1000: warmup %d" % args.warmup)
     for _ in range(args.warmup):
         one_step(False)
     rep.sync_status()
@@ -223,174 +490,111 @@ def main():
     log("timing %d steps" % args.steps)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        rates, rsum = one_step(True)
+        one_step(True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     rep.sync_status()
+    del outs
     work_per_step = R * N * T
     value = work_per_step * args.steps / elapsed
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    kernel_ms = timer.mean_ms()
+    slots = SLOTS_PER_BEAD_STEP[0]
     achieved = slots * work_per_step / (kernel_ms * 1e-3)
-    log("fused: %.3f ms/step, kernel %.3f ms, %.3e replica-bead-steps/s" %
-        (1e3 * elapsed / args.steps, kernel_ms, value))
-    gpu_samples = rep.samples()[0]
+    log("large1000: %.1f ms/step, kernel %.1f ms, %.3e replica-bead-steps/s, frac %.3f" %
+        (1e3 * elapsed / args.steps, kernel_ms, value, achieved / VALU_PEAK_LANE_SLOTS))
     tiles = rep.tile_info()
     family = rep.kernel_family()
-    traffic = (FWD_TRAFFIC["bytes"] if family == 4 and args.tile_policy == 0
-               and args.noise_map == FWD_TRAFFIC.get("noise_map", 0)
-               and fwd_sources_digest() == FWD_TRAFFIC["sha256"] else None)
-    kernel_name = {4: "fwd_kernel<float,4,1,%d>" % args.noise_map,
-                   16: "fwd_kernel<float,16,2,0>"}[family]
-
+    traffic = (FWD_TRAFFIC["bytes"] if FWD_TRAFFIC["sha256"] and fwd_sources_digest() == FWD_TRAFFIC["sha256"]
+               else None)
     out = {
         "metric": METRIC, "value": value, "unit": "replica·bead·steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded FENE equilibrium parent; Philox noise, noise map %d)" % args.noise_map,
-        "config": {"workload": "fene50: FENE N=50 b=100, uniaxial Wi=2 (rate=%.6g), dt=1e-4, "
-                               "R=1024, 10^4 steps, sample every 100, FP64 averages, Bell rates"
+        "data": "synthetic (seeded FENE equilibrium parent; Philox noise, noise map 0)",
+        "config": {"workload": "large1000: FENE N=1000 b=400, start-up uniaxial Wi=10 (rate=%.6g), dt=5e-5, "
+                               "R=8192, 2x10^4 steps, RSF+TSF windows of 500, FP64 averages, Bell rates + events"
                                % g["rate"],
                    "global_batch": R, "seq_len": N, "parallelism": "none (1 GPU)",
                    "beads_per_lane": tiles[0][0], "replicas_per_wave": tiles[1][0],
-                   "kernel_family": family, "noise_map": args.noise_map},
+                   "kernel_family": family, "noise_map": 0},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_SLOTS / 1e12,
                      "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK_LANE_SLOTS,
-                     "traffic": traffic, "kernel": kernel_name, "kernel_ms": kernel_ms,
-                     "lane_slots_per_replica_bead_step": slots},
+                     "traffic": traffic, "kernel": "fwd_kernel<float,16,2,0>", "kernel_ms": kernel_ms,
+                     "lane_slots_per_replica_bead_step": slots,
+                     "replica_bead_steps_per_launch": work_per_step},
     }
+    fracs = {"large1000": out["roofline"]["frac"]}
+
+    n_cmp = 0
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = max(1, min(16, cpu_cores()))
+        cpu = cpu_baseline(groups, parents, run, args.cpu_single_replicas, args.cpu_replicas_per_thread, threads)
+        r1, t1 = cpu["single"]
+        ra_, ta, n_cmp = cpu["all"]
+        out["cpu_baseline"] = {
+            "value": ra_, "unit": "replica·bead·steps/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle, replicas 0..%d of 8192 (%d per thread on %d threads), all 2x10^4 steps, "
+                      "RSF+TSF averages, Bell rates and events (%.1f s); rate per replica*bead*step, which "
+                      "extrapolates linearly to the full workload (replicas are independent)"
+                      % (n_cmp - 1, args.cpu_replicas_per_thread, threads, ta),
+            "single_thread": {"value": r1, "replicas": args.cpu_single_replicas, "seconds": t1},
+            "host_cores": cpu_cores()}
+        log("cpu: %.3e (1 thread), %.3e (%d threads) replica-bead-steps/s" % (r1, ra_, threads))
+        smp, tsmp = rep.samples(tsf=True)
+        got = smp[0][:, :n_cmp].cpu().numpy()
+        tgot = tsmp[0][:, :n_cmp].cpu().numpy()
+        del smp, tsmp
+        acc = accuracy(got, cpu["samples"], 1)
+        tacc = accuracy(tgot, cpu["tsf_samples"], 1)
+        out["accuracy_vs_oracle"] = {"replicas": n_cmp, "rsf": acc, "tsf": tacc,
+                                     "note": "max relative error over all 40 windows; *_first: first window "
+                                             "(500 steps); profile = replica mean of the compared replicas"}
+        log("GPU vs oracle: samples %.2e (first window %.2e), profile %.2e; TSF samples %.2e"
+            % (acc["samples"], acc["samples_first"], acc["profile"], tacc["samples"]))
 
     extras = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
     if "plain" in extras:
-        # plain unbatched path, same workload and counters
-        plain = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W,
-                            plain=True, device=dev, noise_map=args.noise_map)
-        pm = torch.empty_like(mean)
-        ps = torch.empty_like(mean)
+        # plain unbatched path on the headline: a 2000-step prefix (4 windows),
+        # timed after a warm-up, extrapolated to the 2x10^4 steps
+        Tp = 2000
+        plain = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=Tp // S, tsf=True,
+                            plain=True, device=dev)
 
-        def plain_step():
+        def plain_pass():
             plain.init_chains(parent)
-            plain.step(T)
-            plain.average_forces(out=(pm, ps))
-            plain.bell_rates(pm, run["k0"], run["x_dagger"])
+            plain.step(Tp)
+            m, s, tm, ts = plain.average_forces(tsf=True)
+            plain.bell_rates(m, run["k0"], run["x_dagger"], events=True)
 
-        plain_step()
-        tp = min(time_once(plain_step) for _ in range(2))
+        plain_pass()
+        tp = time_once(plain_pass)
         plain.sync_status()
-        diff = torch.max(torch.abs(pm - mean) / mean).item()
-        out["plain_path"] = {"value": work_per_step / tp, "ms_per_step": 1e3 * tp,
-                             "speedup_fused_over_plain": (work_per_step / (elapsed / args.steps)) /
-                             (work_per_step / tp),
-                             "max_rel_diff_profile_vs_fused": diff}
+        pv = R * N * Tp / tp
+        out["plain_path"] = {"workload": "large1000, plain path (one launch per EM step and group, bead "
+                                         "positions in HBM), first 2000 steps (4 windows), extrapolated",
+                             "value": pv, "ms_per_step_extrapolated": 1e3 * tp * T / Tp,
+                             "speedup_fused_over_plain": value / pv}
+        if cpu is not None:
+            psmp, ptsmp = plain.samples(tsf=True)
+            pacc = accuracy(psmp[0][:, :n_cmp].cpu().numpy(), cpu["samples"][:Tp // S], 1)
+            ptacc = accuracy(ptsmp[0][:, :n_cmp].cpu().numpy(), cpu["tsf_samples"][:Tp // S], 1)
+            fused = accuracy(got[:Tp // S], cpu["samples"][:Tp // S], 1)
+            out["plain_path"]["accuracy_vs_oracle"] = {"rsf": pacc, "tsf": ptacc, "fused_rsf_same_windows": fused}
+            del psmp, ptsmp
         plain.close()
-        log("plain: %.3f ms/step" % (1e3 * tp))
+        log("plain large1000: %.1f ms for %d steps (x%.0f extrapolated)" % (1e3 * tp, Tp, T / Tp))
+    rep.close()
 
+    if "fene50" in extras:
+        out["fene50"] = fene50_bench(dev, args.noise_map)
+        fracs["fene50"] = out["fene50"]["roofline_frac"]
     if "adjoint" in extras:
-        ag, ap_, arun = wl.adjoint100()
-        ga = ag[0]
-        apar = torch.from_numpy(np.ascontiguousarray(ap_[0]).reshape(-1)).to(dev)
-        adj = ra.Replicas(ag, arun["seed"], precision=32, sample_every=arun["sample_every"],
-                          max_windows=arun["steps"] // arun["sample_every"],
-                          checkpoint_every=arun["checkpoint_every"], max_steps=arun["steps"], device=dev,
-                          noise_map=args.noise_map)
-        gm = torch.ones((arun["steps"] // arun["sample_every"], ga["n_beads"] - 1),
-                        dtype=torch.float64, device=dev)
-
-        def adj_fwd():
-            adj.init_chains(apar)
-            adj.step(arun["steps"])
-
-        def adj_bwd():
-            m, _ = adj.average_forces()
-            return adj.backward(m, gm, None)
-
-        adj_fwd()
-        adj_bwd()
-        tf = time_once(adj_fwd)
-        tb = time_once(adj_bwd)
-        adj.sync_status()
-        adj.close()
-        # the same gradient with the library's automatic checkpoint interval:
-        # the 2001 states (9.8 GB) fit in HBM, so every state is kept and the
-        # backward recomputes nothing
-        adj = ra.Replicas(ag, arun["seed"], precision=32, sample_every=arun["sample_every"],
-                          max_windows=arun["steps"] // arun["sample_every"],
-                          checkpoint_every=ra.CKPT_AUTO, max_steps=arun["steps"], device=dev,
-                          noise_map=args.noise_map)
-        adj_fwd()
-        adj_bwd()
-        tf1 = time_once(adj_fwd)
-        tb1 = time_once(adj_bwd)
-        k_auto = adj.checkpoint_interval()
-        adj.sync_status()
-        adj.close()
-        awork = ga["n_replicas"] * ga["n_beads"] * arun["steps"]
-        out["adjoint"] = {"workload": "adjoint100: FENE N=100 b=100, uniaxial Wi=4, R=4096, dt=1e-4, "
-                                      "2000 steps, checkpoints every 100",
-                          "value": awork / tb, "unit": "replica·bead·steps/s (backward incl. recompute)",
-                          "forward_value": awork / tf, "backward_ms": 1e3 * tb, "forward_ms": 1e3 * tf,
-                          "auto_interval": {"checkpoint_every": k_auto, "value": awork / tb1,
-                                            "forward_value": awork / tf1, "backward_ms": 1e3 * tb1,
-                                            "forward_ms": 1e3 * tf1}}
-        log("adjoint: fwd %.2f ms bwd %.2f ms; automatic interval %d: fwd %.2f ms bwd %.2f ms"
-            % (1e3 * tf, 1e3 * tb, k_auto, 1e3 * tf1, 1e3 * tb1))
-
+        out["adjoint"] = adjoint_bench(dev, args.noise_map)
+        fracs["adjoint100_forward"] = out["adjoint"]["forward_roofline_frac"]
     if "batched" in extras:
-        # batched uneven chains, one graph-captured persistent launch per call
-        bg, bp, brun = wl.batched512()
-        bpar = torch.from_numpy(np.concatenate([np.ascontiguousarray(p).reshape(-1) for p in bp])).to(dev)
-        bat = ra.Replicas(bg, brun["seed"], precision=32, sample_every=brun["sample_every"],
-                          max_windows=brun["steps"] // brun["sample_every"], use_graph=True, device=dev,
-                          noise_map=args.noise_map)
-
-        def bat_step():
-            bat.init_chains(bpar)
-            bat.step(brun["steps"])
-            m, s = bat.average_forces()
-            bat.bell_rates(m, brun["k0"], brun["x_dagger"])
-
-        bat_step()
-        tbat = min(time_once(bat_step) for _ in range(2))
-        bat.sync_status()
-        bat.close()
-        # the same batch with tiles chosen by the timing autotuner (each chain
-        # length timed alone on 256 replicas) instead of the cost model
-        bat = ra.Replicas(bg, brun["seed"], precision=32, sample_every=brun["sample_every"],
-                          max_windows=brun["steps"] // brun["sample_every"], use_graph=True, device=dev,
-                          tile_policy=1, noise_map=args.noise_map)
-        bat_step()
-        ttun = min(time_once(bat_step) for _ in range(2))
-        bat.sync_status()
-        bat.close()
-        bwork = sum(x["n_replicas"] * x["n_beads"] for x in bg) * brun["steps"]
-        out["batched"] = {"workload": "batched512: 512 FENE chains N~U{20..200}, b~U[50,200], planar "
-                                      "Wi~U[0.5,5] / shear Wi~U[1,50], R~U{16..256}, 5000 steps",
-                          "value": bwork / tbat, "ms_per_step": 1e3 * tbat, "graph": True,
-                          "tiles": "cost model", "autotuned_tiles_ms_per_step": 1e3 * ttun}
-        log("batched: %.2f ms (cost-model tiles), %.2f ms (autotuned tiles)" % (1e3 * tbat, 1e3 * ttun))
-
-    if "large1000" in extras:
-        # 1000-bead transient with TSF
-        lg, lp, lrun = wl.large1000()
-        lpar = torch.from_numpy(np.ascontiguousarray(lp[0]).reshape(-1)).to(dev)
-        big = ra.Replicas(lg, lrun["seed"], precision=32, sample_every=lrun["sample_every"],
-                          max_windows=lrun["steps"] // lrun["sample_every"], tsf=True, device=dev)
-
-        def big_step():
-            big.init_chains(lpar)
-            big.step(lrun["steps"])
-            m, s, tm, ts = big.average_forces(tsf=True)
-            big.bell_rates(m, lrun["k0"], lrun["x_dagger"], events=True)
-
-        big_step()
-        tbig = time_once(big_step)
-        big.sync_status()
-        lwork = lg[0]["n_replicas"] * lg[0]["n_beads"] * lrun["steps"]
-        out["large1000"] = {"workload": "large1000: FENE N=1000 b=400, start-up uniaxial Wi=10, R=8192, "
-                                        "dt=5e-5, 2e4 steps, RSF+TSF windows of 500, Bell events",
-                            "value": lwork / tbig, "ms_per_step": 1e3 * tbig}
-        big.close()
-        log("large1000: %.1f ms" % (1e3 * tbig))
-
+        out["batched"] = batched_bench(dev, args.noise_map)
+        fracs["batched512"] = out["batched"]["cost_model"]["roofline_frac"]
     for rname, rdesc in (("rsf50", "RSF cycle, FENE N=50 b=100, shear Wi=50, parent + 1000 replicas "
                                    "re-cloned every 750 steps, S=750, 20 windows, ISF/TSF/RSF, "
                                    "sigma(N_R=10,20,40,50), Bell rates and MFTU"),
@@ -406,6 +610,9 @@ def main():
             # noise map 1 covers the chain model only (not the pair and HI models)
             out[rname] = rsf_cycle_bench(getattr(wl, rname)(), rdesc, dev, rname,
                                          args.noise_map if rname == "rsf50" else 0)
+    if "sigma_sweep" in extras:
+        out["sigma_sweep"] = sigma_sweep_bench(dev, args.noise_map)
+    out["roofline_fractions"] = {"slots_per_replica_bead_step": SLOTS_PER_BEAD_STEP, "frac": fracs}
 
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
@@ -416,29 +623,6 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    if not args.no_cpu_baseline:
-        nr = args.cpu_replicas
-        log("cpu baseline: oracle on %d replicas x %d steps" % (nr, T))
-        rate, secs, ref = cpu_baseline(groups, parents, run, nr, args.noise_map)
-        got = gpu_samples[:, :nr].cpu().numpy()
-        rel = np.abs(got - ref) / np.abs(ref)
-        err = float(np.max(rel))
-        # the accuracy gate: replica-averaged forces over windows of at most
-        # 200 steps (and the profile of the same replicas over the whole run)
-        prof = np.abs(got.mean(axis=1) - ref.mean(axis=1)) / np.abs(ref.mean(axis=1))
-        out["max_rel_err_vs_oracle_profile_first_200_steps"] = float(np.max(prof[:200 // S]))
-        out["max_rel_err_vs_oracle_profile"] = float(np.max(prof))
-        out["max_rel_err_vs_oracle_samples_first_200_steps"] = float(np.max(rel[:200 // S]))
-        out["cpu_baseline"] = {"value": rate, "unit": "replica·bead·steps/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": "FP64 oracle, replicas 0..%d of 1024, all 10^4 steps, averages and "
-                                         "Bell rates, single thread (%.1f s; host has %d cores)"
-                                         % (nr - 1, secs, cpu_cores())}
-        out["max_rel_err_vs_oracle"] = err   # every sample of every window of the 10^4 steps
-        log("cpu: %.3e replica-bead-steps/s, GPU vs oracle max rel err %.2e (samples), %.2e (profile)"
-            % (rate, err, out["max_rel_err_vs_oracle_profile"]))
-
-    rep.close()
     print(json.dumps(out), flush=True)
 
 

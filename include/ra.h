@@ -218,6 +218,24 @@ RA_API ra_status ra_block_sigma(ra_ctx* ctx, int32_t block, double* sigma);
  * FP64 [n_groups]; n_windows >= 1. */
 RA_API ra_status ra_mftu(ra_ctx* ctx, const double* rate_sum, int64_t n_windows, double* mftu);
 
+/* MFTU by sampling unfolding events (Sec. III, Table 1), for n_trials
+ * independent trials per group: window v = 0, 1, ... of a trial carries the
+ * rates of sampled window v mod n_windows (the rate profile repeats), and
+ * spring j of group g unfolds in window v when the tag-2 uniform of counter
+ * (v, j, trial, 2<<24 | stream_id) is below 1 - exp(-rates[v mod W][j] S dt_g)
+ * (trial 0 over the sampled windows draws exactly ra_bell_rates's events). A
+ * trial's first-passage time is the end of its first window with any
+ * unfolding, (v + 1) S dt_g; a trial with none in max_windows windows is
+ * censored at max_windows S dt_g. mftu[g] = (sum of all trials' times) /
+ * (number of trials with an event), the censored maximum-likelihood mean of an
+ * exponential waiting time (+Inf when no trial has an event); for a constant
+ * total rate K it estimates S dt / (1 - exp(-K S dt)) = 1/K + S dt/2 + ...
+ * rates: device FP64 [n_windows][sum_g(N_g-1)] from ra_bell_rates;
+ * first_window: device int64 [n_trials][n_groups] (first window or -1);
+ * mftu: device FP64 [n_groups]. 1 <= n_trials <= 65535, 1 <= max_windows < 2^32. */
+RA_API ra_status ra_mftu_events(ra_ctx* ctx, const double* rates, int64_t n_windows, int32_t n_trials,
+                                int64_t max_windows, int64_t* first_window, double* mftu);
+
 /* Replica fidelity (Sec. IV, Eq. 5) and radius of gyration, from the current
  * state of every replica, in the centre-of-mass frame:
  *   dbar[q][a]   = (1/N) sum_i |rhat_a^i(q) - rhat_a^i(source)|,

@@ -93,6 +93,8 @@ def lib():
         L.ra_oracle_rsf_cycle.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64]
         L.ra_oracle_block_sigma.argtypes = [P, ctypes.c_int32, dp]
         L.ra_oracle_mftu.argtypes = [P, dp, ctypes.c_int64, dp]
+        L.ra_oracle_mftu_events.argtypes = [P, dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int64), dp]
         L.ra_oracle_conformation.argtypes = [P, dp, dp, dp, dp]
         L.ra_oracle_clamps.argtypes = [P, ctypes.c_int32]
         L.ra_oracle_clamps.restype = ctypes.c_int64
@@ -343,6 +345,17 @@ class Oracle:
         out = np.zeros(len(self.descs))
         self._check(self.L.ra_oracle_mftu(self.ptr, _dp(rs), rs.shape[0], _dp(out)), "mftu")
         return out
+
+    def mftu_events(self, rates, n_trials, max_windows):
+        """(mftu [G], first window [n_trials][G]) by event sampling over the
+        rate windows repeated in order."""
+        r = np.ascontiguousarray(rates, dtype=np.float64)
+        out = np.zeros(len(self.descs))
+        first = np.zeros((n_trials, len(self.descs)), dtype=np.int64)
+        self._check(self.L.ra_oracle_mftu_events(self.ptr, _dp(r), r.shape[0], int(n_trials), int(max_windows),
+                                                 first.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                                 _dp(out)), "mftu_events")
+        return out, first
 
     def conformation(self, per_bead=False):
         """(dbar [Rsim][3], rg2 [Rsim][3], src_rg2 [G][3][, d_bead [Rsim][N][3] per group])."""

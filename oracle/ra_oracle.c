@@ -840,6 +840,53 @@ int ra_oracle_block_sigma(const rao_ctx* c, int32_t block, double* sigma)
  * the per-chain total rate K_w = sum_j k_j held over each window, and K
  * stationary over the run, the first event time is exponential with mean
  * 1 / <K>, <K> the average of K_w over the windows. */
+/* MFTU by sampling unfolding events (Sec. III, Table 1), trial by trial:
+ * window v = 0, 1, ... of a trial carries the rates of sampled window
+ * v mod n_windows; each spring unfolds in window v with probability
+ * 1 - exp(-k S dt), decided by the tag-2 uniform of counter (v, spring,
+ * trial, group). The trial's first-passage time is the end of the first
+ * window with any unfolding, (v + 1) S dt; a trial without one in max_windows
+ * windows contributes max_windows S dt and no event. mftu = total time of all
+ * trials / number of trials with an event (the maximum-likelihood mean of an
+ * exponential waiting time under censoring), +Inf if no trial has one. */
+int ra_oracle_mftu_events(const rao_ctx* c, const double* rates, int64_t n_windows, int32_t n_trials,
+                          int64_t max_windows, int64_t* first_window, double* mftu)
+{
+    if (!c || !rates || !mftu || n_windows < 1 || n_trials < 1 || max_windows < 1 ||
+        max_windows > (int64_t)0xFFFFFFFF)
+        return RAO_EINVAL;
+    uint32_t key[2] = { (uint32_t)c->seed, (uint32_t)(c->seed >> 32) };
+    for (int g = 0; g < c->n_groups; ++g) {
+        const rao_group* d = &c->groups[g];
+        const double window_time = c->sample_every * d->dt;
+        double total = 0.0;
+        int64_t n_events = 0;
+        for (int32_t t = 0; t < n_trials; ++t) {
+            int64_t first = -1;
+            for (int64_t v = 0; v < max_windows && first < 0; ++v) {
+                int64_t w = v % n_windows;
+                for (int j = 0; j + 1 < d->n_beads; ++j) {
+                    double k = rates[w * c->n_spr + c->spr_off[g] + j];
+                    uint32_t ctr[4] = { (uint32_t)v, (uint32_t)j, (uint32_t)t,
+                                        ((uint32_t)RAO_TAG_EVENT << 24) | d->stream_id };
+                    uint32_t x[4];
+                    rao_philox4x32_10(ctr, key, x);
+                    if (rao_uniform(x[0]) < -expm1(-k * window_time)) first = v;
+                }
+            }
+            if (first_window) first_window[(int64_t)t * c->n_groups + g] = first;
+            if (first >= 0) {
+                total += (double)(first + 1) * window_time;
+                n_events += 1;
+            } else {
+                total += (double)max_windows * window_time;
+            }
+        }
+        mftu[g] = n_events > 0 ? total / (double)n_events : INFINITY;
+    }
+    return RAO_OK;
+}
+
 int ra_oracle_mftu(const rao_ctx* c, const double* rate_sum, int64_t n_windows, double* mftu)
 {
     if (!c || !rate_sum || !mftu || n_windows < 1) return RAO_EINVAL;

@@ -129,6 +129,8 @@ int  ra_oracle_rsf_cycle(rao_ctx* rep, rao_ctx* par, int64_t n_windows, int64_t 
 int  ra_oracle_block_sigma(const rao_ctx* c, int32_t block, double* sigma);
 /* mftu[g] = 1 / (mean over windows of rate_sum[w][g]) */
 int  ra_oracle_mftu(const rao_ctx* c, const double* rate_sum, int64_t n_windows, double* mftu);
+int  ra_oracle_mftu_events(const rao_ctx* c, const double* rates, int64_t n_windows, int32_t n_trials,
+                           int64_t max_windows, int64_t* first_window, double* mftu);
 /* Eq. 5 fidelity dbar[k][3], per-bead d_bead[k][i][3], squared radius of
  * gyration components rg2[k][3] and src_rg2[g][3] of the clone source */
 int  ra_oracle_conformation(const rao_ctx* c, double* dbar, double* d_bead, double* rg2,

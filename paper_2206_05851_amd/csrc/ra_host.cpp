@@ -800,6 +800,20 @@ ra_status ra_mftu(ra_ctx* c, const double* rate_sum, int64_t n_windows, double* 
     return RA_OK;
 }
 
+ra_status ra_mftu_events(ra_ctx* c, const double* rates, int64_t n_windows, int32_t n_trials, int64_t max_windows,
+                         int64_t* first_window, double* mftu) {
+    if (!c) return fail(nullptr, RA_EINVAL, "null context");
+    if (!rates || !first_window || !mftu) return fail(c, RA_EINVAL, "null argument");
+    if (n_windows < 1 || n_trials < 1 || n_trials > 65535 || max_windows < 1 || max_windows > (int64_t)0xFFFFFFFF)
+        return fail(c, RA_EINVAL, "need n_windows >= 1, 1 <= n_trials <= 65535, 1 <= max_windows < 2^32");
+    const int ng = (int)c->hgroups.size();
+    if (ng > 65535) return fail(c, RA_EINVAL, "more than 65535 groups");
+    HIPCHK(c, launch_mftu_events(c->dgroups, ng, rates, n_windows, c->spr_total, n_trials, max_windows,
+                                 c->run.sample_every, (uint32_t)c->run.seed, (uint32_t)(c->run.seed >> 32),
+                                 first_window, mftu, c->stream));
+    return RA_OK;
+}
+
 ra_status ra_conformation(ra_ctx* c, double* dbar, double* d_bead, double* rg2, double* src_rg2) {
     if (!c) return fail(nullptr, RA_EINVAL, "null context");
     if (c->run.plain) return fail(c, RA_EINVAL, "ra_conformation needs the fused path");

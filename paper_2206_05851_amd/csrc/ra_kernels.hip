@@ -57,27 +57,30 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
     int to_smp = S - (int)(n0 % (uint32_t)S);                              // steps to the next window end
     int to_ck = K > 0 ? (int)((K - (int)(n0 % (uint32_t)K)) % K) : INT32_MAX;  // steps to the next checkpoint
     // TSF: per-step tensions are summed in registers over at most TSF_FLUSH
-    // steps (relative error below 64 ulp) and folded into the FP64 window sums
-    // kept in global memory, so no FP64 accumulator stays live in the loop
-    constexpr int TSF_FLUSH = 64;
+    // steps and folded into the FP64 window sum in global memory only when a
+    // window is longer than that or continues in a later launch; a window that
+    // starts and ends within this launch and TSF_FLUSH steps is averaged from
+    // its register sum alone. Tensions are nonnegative, so a register sum of
+    // at most 512 terms carries a relative error below 511 ulp (3e-5).
+    constexpr int TSF_FLUSH = 512;
     T tpart[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) tpart[m] = (T)0;
+    // the window sum in global memory holds part of the current window: true
+    // when the launch starts inside a window, and after every mid-window fold
+    bool acc_live = (n0_64 % S) != 0;
     auto flush_tsf = [&](bool window_end) {
         if constexpr (TSF) {
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 if (valid[m]) {
-                    const double acc = tacc_g[m] + (double)tpart[m];
-                    if (window_end) {
-                        tsf_w[m] = (T)(acc / (double)S);
-                        tacc_g[m] = 0.0;
-                    } else {
-                        tacc_g[m] = acc;
-                    }
+                    const double acc = (acc_live ? tacc_g[m] : 0.0) + (double)tpart[m];
+                    if (window_end) tsf_w[m] = (T)(acc / (double)S);
+                    else tacc_g[m] = acc;
                 }
                 tpart[m] = (T)0;
             }
+            acc_live = !window_end;
         }
     };
     int clamps = 0;

@@ -5,11 +5,13 @@
 //   - the centre-of-mass-frame conformation each replica set was cloned from;
 //   - the spread sigma(N_R) of the RSF estimate over blocks of N_R replicas
 //     (Figs. 2 and 5);
-//   - the mean first-passage time to any event of a chain (MFTU, Sec. III);
+//   - the mean first-passage time to any event of a chain (MFTU, Sec. III),
+//     from the mean total rate and by sampling unfolding events;
 //   - replica fidelity D-bar (Eq. 5) and radius-of-gyration components
 //     (R_Gz, Sec. IV).
 // None of these is on the per-step path; they run once per window or per
 // analysis call, with fixed summation orders so results are reproducible.
+#include "ra_device.hpp"
 #include "ra_launch.hpp"
 
 namespace ra {
@@ -290,6 +292,63 @@ __global__ __launch_bounds__(64) void mftu_kernel(const double* __restrict__ rat
     if (threadIdx.x == 0) mftu[g] = 1.0 / (acc / (double)n_windows);
 }
 
+// MFTU by sampling unfolding events, one wavefront per (trial, group): the
+// lanes cover the chain's springs; window v carries the rates of sampled
+// window v mod n_windows and spring j unfolds there when the tag-2 uniform of
+// counter (v, j, trial, 2<<24 | stream) is below 1 - exp(-k S dt) (trial 0 over
+// the sampled windows draws exactly ra_bell_rates's events). The wave stops at
+// the first window with any unfolding (a wave vote) or after max_windows.
+__global__ __launch_bounds__(64) void first_event_kernel(const GroupDev* __restrict__ groups,
+                                                         const double* __restrict__ rates, int64_t n_windows,
+                                                         int64_t spr_total, int64_t max_windows, int S,
+                                                         uint32_t key0, uint32_t key1,
+                                                         int64_t* __restrict__ first_window, int n_groups) {
+    const int trial = blockIdx.x;
+    const int g = blockIdx.y;
+    const GroupDev& G = groups[g];
+    const int lane = threadIdx.x;
+    const int nm1 = G.N - 1;
+    const double window_time = (double)S * G.dt;
+    const uint32_t ctr3 = (2u << 24) | (G.stream & 0xFFFFFFu);
+    const RoundKeys keys = round_keys<false>(key0, key1);
+    int64_t first = -1;
+    int64_t w = 0;
+    for (int64_t v = 0; v < max_windows; ++v) {
+        bool hit = false;
+        for (int j = lane; j < nm1; j += WAVE) {
+            const double k = rates[w * spr_total + G.spr_off + j];
+            const Words u = philox10((uint32_t)v, (uint32_t)j, (uint32_t)trial, ctr3, keys);
+            hit |= u01_f64(u.x) < -expm1(-k * window_time);
+        }
+        if (__builtin_amdgcn_ballot_w64(hit) != 0) {
+            first = v;
+            break;
+        }
+        if (++w == n_windows) w = 0;
+    }
+    if (lane == 0) first_window[(int64_t)trial * n_groups + g] = first;
+}
+
+// The censored maximum-likelihood mean of the first-passage times: all
+// trials' times (first-passage or censoring) over the number of events; one
+// wavefront per group, trials summed in fixed order.
+__global__ __launch_bounds__(64) void mftu_events_kernel(const GroupDev* __restrict__ groups,
+                                                         const int64_t* __restrict__ first_window, int n_trials,
+                                                         int64_t max_windows, int S, int n_groups,
+                                                         double* __restrict__ mftu) {
+    const int g = blockIdx.x;
+    const double window_time = (double)S * groups[g].dt;
+    double total = 0.0, events = 0.0;
+    for (int t = threadIdx.x; t < n_trials; t += WAVE) {
+        const int64_t f = first_window[(int64_t)t * n_groups + g];
+        total += (double)(f >= 0 ? f + 1 : max_windows) * window_time;
+        events += f >= 0 ? 1.0 : 0.0;
+    }
+    total = wave_sum_d(total);
+    events = wave_sum_d(events);
+    if (threadIdx.x == 0) mftu[g] = events > 0.0 ? total / events : __builtin_inf();
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
@@ -353,6 +412,17 @@ hipError_t launch_block_sigma(const GroupDev* groups, const ColTile* tiles, int 
     else
         hipLaunchKernelGGL(block_sigma_kernel<float>, grid, blk, 0, st, groups, tiles, (const float*)smp, smp_total,
                            spr_total, block, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_mftu_events(const GroupDev* groups, int n_groups, const double* rates, int64_t n_windows,
+                              int64_t spr_total, int n_trials, int64_t max_windows, int S, uint32_t key0,
+                              uint32_t key1, int64_t* first_window, double* mftu, hipStream_t st) {
+    (void)hipGetLastError();   // report only this launch's own error
+    hipLaunchKernelGGL(first_event_kernel, dim3((unsigned)n_trials, (unsigned)n_groups), dim3(64), 0, st, groups,
+                       rates, n_windows, spr_total, max_windows, S, key0, key1, first_window, n_groups);
+    hipLaunchKernelGGL(mftu_events_kernel, dim3((unsigned)n_groups), dim3(64), 0, st, groups, first_window, n_trials,
+                       max_windows, S, n_groups, mftu);
     return hipGetLastError();
 }
 

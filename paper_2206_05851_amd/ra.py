@@ -21,7 +21,8 @@ _NAMES = {RA_EINVAL: "RA_EINVAL", RA_ENOMEM: "RA_ENOMEM", RA_EDEVICE: "RA_EDEVIC
 
 # Every symbol include/ra.h declares.
 EXPORTS = ["ra_create", "ra_init_chains", "ra_step", "ra_average_forces", "ra_bell_rates",
-           "ra_backward", "ra_reclone", "ra_rsf_cycle", "ra_block_sigma", "ra_mftu", "ra_conformation",
+           "ra_backward", "ra_reclone", "ra_rsf_cycle", "ra_block_sigma", "ra_mftu", "ra_mftu_events",
+           "ra_conformation",
            "ra_sync_status", "ra_guard_counts", "ra_get_samples", "ra_get_bonds",
            "ra_checkpoint_interval", "ra_tile_info", "ra_debug_noise", "ra_last_error", "ra_destroy"]
 
@@ -79,6 +80,7 @@ def library():
         "ra_rsf_cycle": [P, P, i64, i64],
         "ra_block_sigma": [P, i32, P],
         "ra_mftu": [P, P, i64, P],
+        "ra_mftu_events": [P, P, i64, i32, i64, P, P],
         "ra_conformation": [P, P, P, P, P],
         "ra_sync_status": [P],
         "ra_guard_counts": [P, ctypes.POINTER(i64)],
@@ -306,6 +308,20 @@ class Replicas:
         self._check(self.L.ra_mftu(self.ptr, _ptr(rs), rs.shape[0], _ptr(out)))
         self._leave()
         return out
+
+    def mftu_events(self, rates, n_trials, max_windows):
+        """(mftu [G], first window [n_trials, G] (int64, -1 = censored)) by
+        sampling unfolding events over the rate windows repeated in order."""
+        W = rates.shape[0]
+        _need(rates, "rates", (W, self.n_springs))
+        out = self._dev((len(self.groups),))
+        first = self._dev((int(n_trials), len(self.groups)), torch.int64)
+        r = rates.contiguous()
+        self._enter()
+        self._check(self.L.ra_mftu_events(self.ptr, _ptr(r), W, int(n_trials), int(max_windows), _ptr(first),
+                                          _ptr(out)))
+        self._leave()
+        return out, first
 
     def conformation(self, per_bead=False):
         """(dbar [sum R][3], rg2 [sum R][3], src_rg2 [G][3][, d_bead [sum R N][3]]) (Eq. 5)."""

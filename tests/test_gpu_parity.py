@@ -445,3 +445,48 @@ def test_errors_on_capacity_and_order():
     with pytest.raises(ValueError):
         rep.mftu(torch.zeros(2, 3, dtype=torch.float64, device=mean.device))
     rep.sync_status()
+
+
+def test_autotuner_tiles_bit_equal_and_cache_round_trip(tmp_path, monkeypatch):
+    # tile_policy 1 times the legal tiles (and workgroup sizes) per chain
+    # length; whatever it picks, the results are the cost model's bits. Its
+    # results persist in the RA_AUTOTUNE_CACHE file: a copy of that file gives
+    # the same tiles without timing (nothing is appended), and an entry written
+    # by hand is obeyed.
+    import shutil
+    from paper_2206_05851_amd import ra
+    gs = [wl.group(20, 40, 1e-4, wl.FENE, 1.0, 60.0, wl.SHEAR, 20.0, stream_id=1),
+          wl.group(50, 30, 1e-4, wl.FENE, 1.0, 100.0, wl.UNIAXIAL, 0.3, stream_id=2),
+          wl.group(130, 20, 1e-4, wl.HOOKEAN, 1.0, 0.0, wl.PLANAR, 0.2, stream_id=3)]
+    ps = [wl.equilibrium_parent(20, wl.FENE, 1.0, 60.0, seed=1), wl.equilibrium_parent(50, wl.FENE, 1.0, 100.0, seed=2),
+          wl.equilibrium_parent(130, seed=3)]
+    a = tmp_path / "a.jsonl"
+    monkeypatch.setenv("RA_AUTOTUNE_CACHE", str(a))
+    announce("autotuner: tuning 3 chain lengths")
+    tuned = run_gpu(gs, ps, 5, 150, 50, tile_policy=1)
+    cost = run_gpu(gs, ps, 5, 150, 50, tile_policy=0)
+    for x, y in zip(tuned.samples(), cost.samples()):
+        assert torch_equal(x, y)
+    tiles = tuned.tile_info()
+    tuned.sync_status()
+    lines = a.read_text().splitlines()
+    assert len(lines) == 9                        # 3 lengths x 3 workgroup sizes
+    b = tmp_path / "b.jsonl"
+    shutil.copy(a, b)
+    monkeypatch.setenv("RA_AUTOTUNE_CACHE", str(b))
+    again = ra.Replicas(gs, 5, sample_every=50, max_windows=3, tile_policy=1)
+    assert again.tile_info() == tiles
+    assert b.read_text() == a.read_text()
+    again.close()
+    c = tmp_path / "c.jsonl"
+    c.write_text("".join('{"N": 50, "spring": 1, "precision": 32, "family": 4, "wpb": %d, "noise_map": 0, '
+                         '"M": 4, "ms_per_replica": 1e-9}\n' % w for w in (1, 2, 4)))
+    monkeypatch.setenv("RA_AUTOTUNE_CACHE", str(c))
+    forced = ra.Replicas(gs, 5, sample_every=50, max_windows=3, tile_policy=1)
+    assert forced.tile_info()[0][1] == 4
+    forced.close()
+
+
+def torch_equal(x, y):
+    import torch
+    return bool(torch.equal(x, y))

@@ -116,6 +116,32 @@ def test_block_sigma_definition_and_oracle():
         assert rel_err(sig, orr.block_sigma(nr), 1e-3) < 1e-4
 
 
+def test_mftu_events_matches_oracle():
+    # first windows bit-exact (the event decisions are FP64 on both sides from
+    # the same counters) and the censored mean; two groups, one of them longer
+    # than a wavefront of springs; a short cap so some trials are censored
+    import torch
+    from oracle import ora
+    from paper_2206_05851_amd import ra
+    gs = [wl.group(12, 4, 1e-2, stream_id=3), wl.group(90, 4, 1e-2, stream_id=8)]
+    S, W = 10, 6
+    rng = np.random.default_rng(5)
+    mean = rng.uniform(0.0, 20.0, size=(W, 11 + 89))
+    o = ora.Oracle(gs, 21, S, W)
+    rates, _ = o.bell_rates(mean, k0=2e-3, x_dagger=0.1)
+    announce("MFTU by event sampling: 500 trials, caps 40 and 4000")
+    rep = ra.Replicas(gs, 21, sample_every=S, max_windows=W)
+    for cap in (40, 4000):
+        m_ref, f_ref = o.mftu_events(rates, 500, cap)
+        m, f = rep.mftu_events(torch.from_numpy(rates).cuda(), 500, cap)
+        f = f.cpu().numpy()
+        assert np.array_equal(f, f_ref)
+        assert np.allclose(m.cpu().numpy(), m_ref, rtol=1e-13, atol=0)
+        if cap == 40:
+            assert np.any(f < 0) and np.any(f >= 0)
+    rep.close()
+
+
 def test_conformation_after_cycle_matches_oracle():
     gs = [wl.group(40, 16, 1e-4, wl.FENE, 1.0, 100.0, wl.SHEAR, wl.wi_to_rate(50.0, 40), stream_id=1),
           wl.group(7, 9, 1e-3, wl.HOOKEAN, 1.0, 0.0, wl.QUIESCENT, 0.0, stream_id=2)]

@@ -183,6 +183,64 @@ def test_mftu_is_inverse_mean_total_rate():
     assert m[0] <= np.mean(1.0 / rsum[:, 0])
 
 
+def test_mftu_events_trial_zero_uses_the_bell_event_draws():
+    # trial 0 over the sampled windows draws exactly the uniforms of
+    # bell_rates' events, so its first window is the first row with an event
+    N, W, S, dt = 12, 30, 10, 1e-2
+    o = ora.Oracle([wl.group(N, 1, dt, stream_id=5)], 3, S, W)
+    rng = np.random.default_rng(1)
+    mean = rng.uniform(5.0, 25.0, size=(W, N - 1))
+    rates, rsum, ev = o.bell_rates(mean, k0=0.02, x_dagger=0.1, events=True)
+    rows = np.nonzero(ev.any(axis=1))[0]
+    assert rows.size > 0
+    _, first = o.mftu_events(rates, 1, W)
+    assert first[0, 0] == rows[0]
+    # no event at all within the cap: censored
+    _, first = o.mftu_events(np.zeros_like(rates), 3, 50)
+    assert np.all(first == -1)
+    m, _ = o.mftu_events(np.zeros_like(rates), 3, 50)
+    assert np.isinf(m[0])
+
+
+def test_mftu_events_geometric_first_passage():
+    # Piecewise-constant rates held per window: window v of a trial unfolds
+    # some spring with probability p_v = 1 - exp(-K_v S dt) (K_v the summed
+    # rate, springs independent), so the first window is distributed as
+    # P(v) = prod_{i<v} (1 - p_i) p_v over the repeated rate profile. Its mean
+    # and the censored fraction are checked against that law by brute force.
+    N, S, dt = 6, 10, 1e-2
+    o = ora.Oracle([wl.group(N, 1, dt, stream_id=2)], 7, S, 3)
+    dtw = S * dt
+    rates = np.array([[0.5, 0.2, 0.1, 0.05, 0.15], [2.0, 0.0, 0.0, 0.0, 0.0], [0.1, 0.1, 0.1, 0.1, 0.1]])
+    K = rates.sum(axis=1)
+    p = -np.expm1(-K * dtw)
+    T, cap = 20000, 400
+    m, first = o.mftu_events(rates, T, cap)
+    v = first[:, 0]
+    surv, pmf = 1.0, np.zeros(cap)
+    for i in range(cap):
+        pmf[i] = surv * p[i % 3]
+        surv *= 1.0 - p[i % 3]
+    assert surv < 1e-12 and np.all(v >= 0)
+    ev = np.sum((np.arange(cap) + 1) * pmf)
+    got = (v + 1).astype(float)
+    assert abs(got.mean() - ev) < 4.5 * got.std() / np.sqrt(T)
+    assert abs(m[0] - ev * dtw) < 4.5 * dtw * got.std() / np.sqrt(T)
+    for i in range(3):                              # the first windows' frequencies
+        assert abs(np.mean(v == i) - pmf[i]) < 4.5 * np.sqrt(pmf[i] * (1 - pmf[i]) / T)
+    # constant rate: the estimator tends to S dt / p, i.e. 1/K + S dt / 2 for K S dt << 1
+    one = rates[2:3]
+    m1, f1 = o.mftu_events(one, T, 5000)
+    p1 = p[2]
+    assert abs(m1[0] - dtw / p1) < 4.5 * dtw * np.sqrt(1 - p1) / p1 / np.sqrt(T)
+    # censoring at 5 windows: the survivors are (1 - p)^5 of the trials and the
+    # censored mean (total time / events) is still an estimate of S dt / p
+    m5, f5 = o.mftu_events(one, T, 5)
+    cens = np.mean(f5[:, 0] < 0)
+    assert abs(cens - (1 - p1) ** 5) < 4.5 * np.sqrt(cens * (1 - cens) / T)
+    assert abs(m5[0] / (dtw / p1) - 1.0) < 0.1
+
+
 def test_conformation_hand_values():
     # Eq. 5 on a 3-bead example: source on the x axis, replica displaced.
     src = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [2.0, 0.0, 0.0]])
