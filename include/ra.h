@@ -284,6 +284,32 @@ RA_API ra_status ra_debug_noise(const uint32_t* counters, int64_t n, uint64_t se
                                 uint32_t* words, float* normals32, double* normals64,
                                 void* hip_stream);
 
+/* Allocation-free run, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): for one chain group (Hookean or FENE, no LJ, no HI) it does what
+ * ra_create + ra_init_chains + ra_step(n_steps) + ra_average_forces do, with
+ * the same kernels and bit-identical mean and std, but keeps its descriptors,
+ * counters, bond state and per-replica samples in a static device array of
+ * RA_STATIC_SCRATCH_MAX bytes instead of allocating. It calls no allocating
+ * routine (the array's device address is looked up once per device, on the
+ * first call there, with hipGetSymbolAddress).
+ *   group, run: host structs as for ra_create; run must select the fused path
+ *     without TSF, checkpoints, graph capture, autotuning (tile_policy 0 or
+ *     1000 + m) or the parent noise tag; run->max_windows is ignored.
+ *   parent_xyz: device FP64 [N][3]; n_steps: a positive multiple of
+ *     sample_every (W = n_steps / sample_every windows, W <= 65535).
+ *   mean, std: device FP64 [W][N-1] (either may be NULL, not both).
+ *   Scratch needed: R (N-1) (3 + W) values of the state precision plus ~2 KB;
+ *     RA_EINVAL (text in ra_last_error(NULL)) if it exceeds the limit.
+ *   Errors found on the device (an invalid parent, a non-finite tension)
+ *     set every element of mean and std to NaN.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (each call rewrites what it reads): calls that overlap on
+ * one device, from several streams or host threads, race. */
+#define RA_STATIC_SCRATCH_MAX (64ll << 20)
+RA_API ra_status ra_run_static(const ra_chain_desc* group, const ra_run_desc* run, const double* parent_xyz,
+                               int64_t n_steps, double* mean, double* std, void* hip_stream);
+
 RA_API const char* ra_last_error(const ra_ctx* ctx);
 RA_API void ra_destroy(ra_ctx* ctx);
 

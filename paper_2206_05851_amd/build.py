@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libra.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["ra_kernels.hip", "ra_adjoint.hip", "ra_rsf.hip", "ra_pair.hip", "ra_hi.hip", "ra_host.cpp", "ra_tune.cpp"]
+SOURCES = ["ra_kernels.hip", "ra_adjoint.hip", "ra_rsf.hip", "ra_pair.hip", "ra_hi.hip", "ra_static.hip", "ra_host.cpp", "ra_tune.cpp"]
 ARCH = os.environ.get("RA_OFFLOAD_ARCH", "gfx950")
 
 

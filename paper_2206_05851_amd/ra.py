@@ -24,7 +24,8 @@ EXPORTS = ["ra_create", "ra_init_chains", "ra_step", "ra_average_forces", "ra_be
            "ra_backward", "ra_reclone", "ra_rsf_cycle", "ra_block_sigma", "ra_mftu", "ra_mftu_events",
            "ra_conformation",
            "ra_sync_status", "ra_guard_counts", "ra_get_samples", "ra_get_bonds",
-           "ra_checkpoint_interval", "ra_tile_info", "ra_debug_noise", "ra_last_error", "ra_destroy"]
+           "ra_checkpoint_interval", "ra_tile_info", "ra_debug_noise", "ra_run_static", "ra_last_error",
+           "ra_destroy"]
 
 
 class RAError(RuntimeError):
@@ -89,6 +90,7 @@ def library():
         "ra_checkpoint_interval": [P, ctypes.POINTER(i32)],
         "ra_tile_info": [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "ra_debug_noise": [P, i64, u64, P, P, P, P],
+        "ra_run_static": [ctypes.POINTER(ChainDesc), ctypes.POINTER(RunDesc), P, i64, P, P, P],
         "ra_destroy": [P],
     }
     for name, args in sig.items():
@@ -163,6 +165,34 @@ def debug_noise(counters, seed, words=True, n32=True, n64=True, stream=None):
     if rc != RA_OK:
         raise RAError(rc, L.ra_last_error(None).decode())
     return w, a, b
+
+
+def run_static(group, seed, n_steps, sample_every, parent, precision=32, noise_map=0, tile_policy=0,
+                waves_per_block=0, stream=None, out=None):
+    """ra_run_static: clone, n_steps steps and replica averages of one chain
+    group with the library's static scratch array (no device allocation in
+    the library). parent: device FP64 tensor of N*3 values. Returns (mean,
+    std), device FP64 [W, N-1] (out=(mean, std) reuses caller buffers)."""
+    L = library()
+    W = n_steps // sample_every
+    nm1 = int(group["n_beads"]) - 1
+    _need(parent.reshape(-1), "parent", (3 * int(group["n_beads"]),))
+    if out is None:
+        mean = torch.empty((W, nm1), dtype=torch.float64, device=parent.device)
+        std = torch.empty((W, nm1), dtype=torch.float64, device=parent.device)
+    else:
+        mean, std = out
+        _need(mean, "out[0]", (W, nm1))
+        _need(std, "out[1]", (W, nm1))
+    desc = make_desc(group, 0)
+    run = RunDesc(seed=int(seed), precision=precision, sample_every=sample_every, max_windows=W,
+                  tile_policy=tile_policy, waves_per_block=waves_per_block, noise_map=noise_map)
+    par = parent.contiguous()
+    rc = L.ra_run_static(ctypes.byref(desc), ctypes.byref(run), _ptr(par), int(n_steps), _ptr(mean), _ptr(std),
+                         _stream_handle(stream))
+    if rc != RA_OK:
+        raise RAError(rc, L.ra_last_error(None).decode())
+    return mean, std
 
 
 class Replicas:

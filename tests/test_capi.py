@@ -131,3 +131,40 @@ def test_tile_policy_values_checked(lib):
         rc, msg = _create(lib, {}, dict(tile_policy=bad))
         assert rc == -1 and "tile_policy" in msg, bad
 
+
+def test_static_run_rejections_on_host(lib):
+    # every case fails in host validation, before the device is touched; the
+    # dummy parent pointer is never dereferenced (skipped where a GPU exists,
+    # so no case can reach a kernel)
+    import torch
+    from paper_2206_05851_amd import ra
+    if torch.cuda.is_available():
+        pytest.skip("host-only check")
+
+    def call(desc_kw, run_kw, n_steps, parent=ctypes.c_void_p(0x1000), outs=True):
+        d = ra.make_desc(dict(dict(n_beads=50, n_replicas=64, dt=1e-4, spring=1, b=100.0), **desc_kw), 0)
+        run = ra.RunDesc(**dict(dict(seed=0, precision=32, sample_every=10, max_windows=4), **run_kw))
+        out = ctypes.c_void_p(0x2000) if outs else None
+        rc = lib.ra_run_static(ctypes.byref(d), ctypes.byref(run), parent, n_steps, out, out, None)
+        return rc, lib.ra_last_error(None).decode()
+
+    cases = [
+        (dict(n_replicas=8192, n_beads=1000), {}, 1000, "scratch"),
+        ({}, {}, 15, "multiple"),
+        ({}, {}, 0, "multiple"),
+        ({}, dict(tsf=1), 10, "TSF"),
+        ({}, dict(checkpoint_every=10, max_steps=10), 10, "checkpoints"),
+        ({}, dict(plain=1), 10, "fused"),
+        ({}, dict(tile_policy=1), 10, "autotuning"),
+        (dict(spring=2, rest_length=2.0), {}, 10, "chain model"),
+        (dict(hi_radius=0.5), {}, 10, "chain model"),
+        (dict(n_beads=300), dict(noise_map=1), 10, "noise_map"),
+        (dict(n_beads=1), {}, 10, "n_beads"),
+    ]
+    for desc_kw, run_kw, n, frag in cases:
+        rc, msg = call(desc_kw, run_kw, n)
+        assert rc == -1 and frag in msg, (desc_kw, run_kw, n, msg)
+    rc, msg = call({}, {}, 10, parent=None)
+    assert rc == -1 and "null" in msg
+    rc, msg = call({}, {}, 10, outs=False)
+    assert rc == -1 and "output" in msg

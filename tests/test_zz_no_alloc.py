@@ -1,0 +1,88 @@
+"""The allocation-free entry point ra_run_static (static scratch array) against
+the context path it stands in for (ra_create + ra_init_chains + ra_step +
+ra_average_forces): the same kernels, so the same bits. Two calls in a row on
+one device share the array; the second is smaller, so any state left from the
+first would show."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, require_gpu, run_gpu
+from paper_2206_05851_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _context(group, parent, seed, steps, S, precision=32, noise_map=0):
+    rep = run_gpu([group], [parent], seed, steps, S, precision=precision, noise_map=noise_map)
+    mean, std = rep.average_forces()
+    rep.sync_status()
+    out = (mean.cpu().numpy(), std.cpu().numpy())
+    rep.close()
+    return out
+
+
+def _static(group, parent, seed, steps, S, precision=32, noise_map=0):
+    import torch
+    from paper_2206_05851_amd import ra
+    p = torch.from_numpy(np.ascontiguousarray(parent).reshape(-1)).cuda()
+    mean, std = ra.run_static(group, seed, steps, S, p, precision=precision, noise_map=noise_map)
+    torch.cuda.synchronize()
+    return mean.cpu().numpy(), std.cpu().numpy()
+
+
+@pytest.mark.parametrize("noise_map", [0, 1])
+def test_static_run_equals_context_path_two_calls(noise_map):
+    big = wl.group(50, 1024, 1e-4, wl.FENE, 1.0, 100.0, wl.UNIAXIAL, wl.wi_to_rate(2.0, 50), stream_id=0)
+    pbig = wl.equilibrium_parent(50, wl.FENE, 1.0, 100.0, seed=101)
+    small = wl.group(20, 96, 1e-4, wl.FENE, 1.0, 60.0, wl.SHEAR, 20.0, stream_id=3)
+    psmall = wl.equilibrium_parent(20, wl.FENE, 1.0, 60.0, seed=7)
+    announce("static run, noise map %d: call 1 N=50 R=1024 400 steps" % noise_map)
+    s1 = _static(big, pbig, 1, 400, 100, noise_map=noise_map)
+    announce("static run, noise map %d: call 2 N=20 R=96 150 steps" % noise_map)
+    s2 = _static(small, psmall, 9, 150, 50, noise_map=noise_map)
+    c1 = _context(big, pbig, 1, 400, 100, noise_map=noise_map)
+    c2 = _context(small, psmall, 9, 150, 50, noise_map=noise_map)
+    for a, b in ((s1, c1), (s2, c2)):
+        assert np.all(np.isfinite(a[0])) and np.all(a[1] > 0)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_static_run_fp64_wide_lanes_and_errors():
+    import torch
+    from paper_2206_05851_amd import ra
+    # FP64 chain, then a 1000-bead FP32 chain (16 beads per lane), then the
+    # first again: every call matches the context path
+    h = wl.group(10, 64, 1e-3, wl.HOOKEAN, 1.0, 0.0, wl.UNIAXIAL, wl.wi_to_rate(0.3, 10))
+    ph = wl.equilibrium_parent(10, seed=100)
+    w = wl.group(1000, 16, 5e-5, wl.FENE, 1.0, 400.0, wl.UNIAXIAL, wl.wi_to_rate(10.0, 1000))
+    pw = wl.equilibrium_parent(1000, wl.FENE, 1.0, 400.0, seed=103)
+    announce("static run: FP64 N=10, FP32 N=1000, FP64 N=10")
+    a = _static(h, ph, 0, 300, 100, precision=64)
+    b = _static(w, pw, 4, 1000, 500)
+    c = _static(h, ph, 0, 300, 100, precision=64)
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    ca = _context(h, ph, 0, 300, 100, precision=64)
+    cb = _context(w, pw, 4, 1000, 500)
+    assert np.array_equal(a[0], ca[0]) and np.array_equal(a[1], ca[1])
+    assert np.array_equal(b[0], cb[0]) and np.array_equal(b[1], cb[1])
+    # host-side rejections: scratch too small, steps off the window grid, TSF
+    p = torch.from_numpy(pw.reshape(-1)).cuda()
+    with pytest.raises(ra.RAError, match="scratch"):
+        ra.run_static(dict(w, n_replicas=8192), 4, 1000, 500, p)
+    with pytest.raises(ra.RAError, match="multiple"):
+        ra.run_static(w, 4, 1001, 500, p)
+    # an invalid parent (a FENE bond beyond Q0) is found on the device: no
+    # steps run and every output is NaN
+    bad = ph.copy()
+    bad[5:] += 30.0
+    fb = wl.group(10, 64, 1e-3, wl.FENE, 1.0, 100.0, wl.UNIAXIAL, 0.1)
+    m, s = _static(fb, bad, 0, 200, 100)
+    assert np.all(np.isnan(m)) and np.all(np.isnan(s))
+    # and the next call is clean again
+    m2, s2 = _static(h, ph, 0, 300, 100, precision=64)
+    assert np.array_equal(m2, ca[0]) and np.array_equal(s2, ca[1])
