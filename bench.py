@@ -447,7 +447,8 @@ def main():
                     help="oracle replicas per thread on all threads")
     ap.add_argument("--noise-map", type=int, default=1, choices=(0, 1),
                     help="ra_run_desc.noise_map of fene50, its plain path, the adjoint, batched and rsf50 "
-                         "(the headline's 16 beads per lane run noise map 0)")
+                         "(1: four normals per Philox block, three blocks per four bead-steps; the headline's "
+                         "16 beads per lane run noise map 0)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -469,7 +470,9 @@ def main():
     R, N, T, S = g["n_replicas"], g["n_beads"], run["steps"], run["sample_every"]
     W = T // S
     parent = torch.from_numpy(np.ascontiguousarray(parents[0]).reshape(-1)).to(dev)
-    rep = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W, tsf=True, device=dev)
+    head_map = 0   # noise map 1 is compiled for at most 4 beads per lane
+    rep = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W, tsf=True, device=dev,
+                      noise_map=head_map)
     outs = [torch.empty((W, N - 1), dtype=torch.float64, device=dev) for _ in range(4)]
     timer = EventTimer(torch.cuda.current_stream())
 
@@ -498,28 +501,28 @@ def main():
     work_per_step = R * N * T
     value = work_per_step * args.steps / elapsed
     kernel_ms = timer.mean_ms()
-    slots = SLOTS_PER_BEAD_STEP[0]
+    slots = SLOTS_PER_BEAD_STEP[head_map]
     achieved = slots * work_per_step / (kernel_ms * 1e-3)
     log("large1000: %.1f ms/step, kernel %.1f ms, %.3e replica-bead-steps/s, frac %.3f" %
         (1e3 * elapsed / args.steps, kernel_ms, value, achieved / VALU_PEAK_LANE_SLOTS))
     tiles = rep.tile_info()
     family = rep.kernel_family()
     traffic = (FWD_TRAFFIC["bytes"] if FWD_TRAFFIC["sha256"] and fwd_sources_digest() == FWD_TRAFFIC["sha256"]
-               else None)
+               and FWD_TRAFFIC.get("noise_map") == head_map else None)
     out = {
         "metric": METRIC, "value": value, "unit": "replica·bead·steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded FENE equilibrium parent; Philox noise, noise map 0)",
+        "data": "synthetic (seeded FENE equilibrium parent; Philox noise, noise map %d)" % head_map,
         "config": {"workload": "large1000: FENE N=1000 b=400, start-up uniaxial Wi=10 (rate=%.6g), dt=5e-5, "
                                "R=8192, 2x10^4 steps, RSF+TSF windows of 500, FP64 averages, Bell rates + events"
                                % g["rate"],
                    "global_batch": R, "seq_len": N, "parallelism": "none (1 GPU)",
                    "beads_per_lane": tiles[0][0], "replicas_per_wave": tiles[1][0],
-                   "kernel_family": family, "noise_map": 0},
+                   "kernel_family": family, "noise_map": head_map},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_SLOTS / 1e12,
                      "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK_LANE_SLOTS,
-                     "traffic": traffic, "kernel": "fwd_kernel<float,16,2,0>", "kernel_ms": kernel_ms,
+                     "traffic": traffic, "kernel": "fwd_kernel<float,16,2,%d>" % head_map, "kernel_ms": kernel_ms,
                      "lane_slots_per_replica_bead_step": slots,
                      "replica_bead_steps_per_launch": work_per_step},
     }
@@ -529,7 +532,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         threads = max(1, min(16, cpu_cores()))
-        cpu = cpu_baseline(groups, parents, run, args.cpu_single_replicas, args.cpu_replicas_per_thread, threads)
+        cpu = cpu_baseline(groups, parents, run, args.cpu_single_replicas, args.cpu_replicas_per_thread, threads,
+                           head_map)
         r1, t1 = cpu["single"]
         ra_, ta, n_cmp = cpu["all"]
         out["cpu_baseline"] = {
@@ -558,32 +562,35 @@ def main():
         # plain unbatched path on the headline: a 2000-step prefix (4 windows),
         # timed after a warm-up, extrapolated to the 2x10^4 steps
         Tp = 2000
-        plain = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=Tp // S, tsf=True,
-                            plain=True, device=dev)
-
-        def plain_pass():
-            plain.init_chains(parent)
-            plain.step(Tp)
-            m, s, tm, ts = plain.average_forces(tsf=True)
-            plain.bell_rates(m, run["k0"], run["x_dagger"], events=True)
-
-        plain_pass()
-        tp = time_once(plain_pass)
-        plain.sync_status()
-        pv = R * N * Tp / tp
         out["plain_path"] = {"workload": "large1000, plain path (one launch per EM step and group, bead "
-                                         "positions in HBM), first 2000 steps (4 windows), extrapolated",
-                             "value": pv, "ms_per_step_extrapolated": 1e3 * tp * T / Tp,
-                             "speedup_fused_over_plain": value / pv}
+                                         "positions in HBM), first 2000 steps (4 windows), extrapolated to "
+                                         "2x10^4; FP32 (positions lose digits at N = 1000) and FP64"}
+        for prec in (32, 64):
+            plain = ra.Replicas(groups, run["seed"], precision=prec, sample_every=S, max_windows=Tp // S,
+                                tsf=True, plain=True, device=dev, noise_map=head_map)
+
+            def plain_pass():
+                plain.init_chains(parent)
+                plain.step(Tp)
+                m, s, tm, ts = plain.average_forces(tsf=True)
+                plain.bell_rates(m, run["k0"], run["x_dagger"], events=True)
+
+            plain_pass()
+            tp = time_once(plain_pass)
+            plain.sync_status()
+            pv = R * N * Tp / tp
+            res = {"value": pv, "ms_per_step_extrapolated": 1e3 * tp * T / Tp, "speedup_fused_over_plain": value / pv}
+            if cpu is not None:
+                psmp, ptsmp = plain.samples(tsf=True)
+                res["accuracy_vs_oracle"] = {
+                    "rsf": accuracy(psmp[0][:, :n_cmp].cpu().numpy(), cpu["samples"][:Tp // S], 1),
+                    "tsf": accuracy(ptsmp[0][:, :n_cmp].cpu().numpy(), cpu["tsf_samples"][:Tp // S], 1)}
+                del psmp, ptsmp
+            out["plain_path"]["fp%d" % prec] = res
+            plain.close()
+            log("plain large1000 FP%d: %.1f ms for %d steps (x%.0f extrapolated)" % (prec, 1e3 * tp, Tp, T / Tp))
         if cpu is not None:
-            psmp, ptsmp = plain.samples(tsf=True)
-            pacc = accuracy(psmp[0][:, :n_cmp].cpu().numpy(), cpu["samples"][:Tp // S], 1)
-            ptacc = accuracy(ptsmp[0][:, :n_cmp].cpu().numpy(), cpu["tsf_samples"][:Tp // S], 1)
-            fused = accuracy(got[:Tp // S], cpu["samples"][:Tp // S], 1)
-            out["plain_path"]["accuracy_vs_oracle"] = {"rsf": pacc, "tsf": ptacc, "fused_rsf_same_windows": fused}
-            del psmp, ptsmp
-        plain.close()
-        log("plain large1000: %.1f ms for %d steps (x%.0f extrapolated)" % (1e3 * tp, Tp, T / Tp))
+            out["plain_path"]["fused_accuracy_same_windows"] = accuracy(got[:Tp // S], cpu["samples"][:Tp // S], 1)
     rep.close()
 
     if "fene50" in extras:

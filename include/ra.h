@@ -84,7 +84,7 @@ typedef enum { RA_QUIESCENT = 0, RA_UNIAXIAL = 1, RA_PLANAR = 2, RA_SHEAR = 3 } 
  * Flow: uniaxial kappa = rate*diag(1,-1/2,-1/2); planar rate*diag(1,-1,0);
  * shear v_x = rate * z (the paper's convention, Sec. II). */
 typedef struct {
-    int32_t  n_beads;      /* N, 2 <= N <= 1024 (FP64: N <= 256; pair and HI kernels: N <= 64) */
+    int32_t  n_beads;      /* N, 2 <= N <= 1024 (FP64 fused: N <= 256; pair and HI kernels: N <= 64) */
     int32_t  n_replicas;   /* R >= 1 */
     int32_t  spring;       /* ra_spring */
     int32_t  flow;         /* ra_flow */
@@ -160,8 +160,9 @@ RA_API ra_status ra_average_forces(ra_ctx* ctx, double* mean, double* std,
 /* Bell-type rates (Sec. III): rates[w][s] = k0 exp(x_dagger mean[w][s] / kT_g),
  * rate_sum[w][g] = sum over the springs of group g (its inverse is the mean
  * first-passage time to any event). events[w][s] (uint8, may be NULL) = 1
- * with probability 1 - exp(-rates * S * dt_g), from one tag-2 uniform per
- * (window, spring, group). mean: device [n_windows][sum_g(N_g-1)]. */
+ * with probability 1 - exp(-rates * S * dt_g), from one tag-2 Philox block per
+ * (window, spring, group): counter (w, j, 0, 2<<24 | stream_id), uniform
+ * u = (2m + 1) 2^-53 from the top 52 bits m of its first two words (hi:lo). mean: device [n_windows][sum_g(N_g-1)]. */
 RA_API ra_status ra_bell_rates(ra_ctx* ctx, const double* mean, int64_t n_windows,
                                double k0, double x_dagger, double* rates,
                                double* rate_sum, uint8_t* events);
@@ -221,7 +222,7 @@ RA_API ra_status ra_mftu(ra_ctx* ctx, const double* rate_sum, int64_t n_windows,
 /* MFTU by sampling unfolding events (Sec. III, Table 1), for n_trials
  * independent trials per group: window v = 0, 1, ... of a trial carries the
  * rates of sampled window v mod n_windows (the rate profile repeats), and
- * spring j of group g unfolds in window v when the tag-2 uniform of counter
+ * spring j of group g unfolds in window v when the tag-2 53-bit uniform of counter
  * (v, j, trial, 2<<24 | stream_id) is below 1 - exp(-rates[v mod W][j] S dt_g)
  * (trial 0 over the sampled windows draws exactly ra_bell_rates's events). A
  * trial's first-passage time is the end of its first window with any

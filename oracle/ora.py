@@ -55,6 +55,8 @@ def lib():
         L.rao_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
         L.rao_uniform.argtypes = [ctypes.c_uint32]
         L.rao_uniform.restype = ctypes.c_double
+        L.rao_uniform53.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.rao_uniform53.restype = ctypes.c_double
         L.rao_normals.argtypes = [ctypes.POINTER(ctypes.c_uint32), dp]
         L.rao_noise.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                 ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, dp]
@@ -124,6 +126,10 @@ def philox(ctr, key):
 
 def uniform(x):
     return lib().rao_uniform(int(x) & 0xFFFFFFFF)
+
+
+def uniform53(hi, lo):
+    return lib().rao_uniform53(int(hi) & 0xFFFFFFFF, int(lo) & 0xFFFFFFFF)
 
 
 def normals(words):

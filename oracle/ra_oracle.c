@@ -47,6 +47,16 @@ double rao_uniform(uint32_t x)
     return ((double)(x >> 9) + 0.5) * 0x1p-23;
 }
 
+/* Two 32-bit words -> uniform in (0,1) for unfolding-event draws: the top 52
+ * bits m of the 64-bit word hi:lo give u = (2m + 1) 2^-53, an odd multiple of
+ * 2^-53 (exact in binary64). Event probabilities per window reach 1e-7 and
+ * below, under the 2^-24 grid of the one-word map. */
+double rao_uniform53(uint32_t hi, uint32_t lo)
+{
+    uint64_t m = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+    return (double)(2 * m + 1) * 0x1p-53;
+}
+
 /* Box-Muller: three standard normals from four uniforms (the second radius
  * uses only its cosine branch). */
 void rao_normals(const uint32_t x[4], double xi[3])
@@ -766,7 +776,7 @@ int ra_oracle_bell_rates(rao_ctx* c, const double* mean, int64_t n_windows,
                     uint32_t x[4];
                     rao_philox4x32_10(ctr, key, x);
                     double p = -expm1(-k * c->sample_every * d->dt);
-                    events[o] = rao_uniform(x[0]) < p ? 1 : 0;
+                    events[o] = rao_uniform53(x[0], x[1]) < p ? 1 : 0;
                 }
             }
             if (rate_sum) rate_sum[w * c->n_groups + g] = sum;
@@ -871,7 +881,7 @@ int ra_oracle_mftu_events(const rao_ctx* c, const double* rates, int64_t n_windo
                                         ((uint32_t)RAO_TAG_EVENT << 24) | d->stream_id };
                     uint32_t x[4];
                     rao_philox4x32_10(ctr, key, x);
-                    if (rao_uniform(x[0]) < -expm1(-k * window_time)) first = v;
+                    if (rao_uniform53(x[0], x[1]) < -expm1(-k * window_time)) first = v;
                 }
             }
             if (first_window) first_window[(int64_t)t * c->n_groups + g] = first;

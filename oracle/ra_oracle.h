@@ -66,6 +66,7 @@ typedef struct {
 /* ---- primitives ------------------------------------------------------- */
 void   rao_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double rao_uniform(uint32_t x);
+double rao_uniform53(uint32_t hi, uint32_t lo);
 void   rao_normals(const uint32_t x[4], double xi[3]);
 void   rao_noise(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
                  uint32_t tag, uint32_t group, double xi[3]);

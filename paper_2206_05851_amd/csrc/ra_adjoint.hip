@@ -172,8 +172,8 @@ template <int M, bool FENE, int NMAP>
 __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G, int item, int k_first) {
     // kernel arguments into locals (the loops must not address the argument block)
     const int S = a.S, K = a.K;
-    const int64_t n_end = a.n_end, state_total = a.state_total, spr_total = a.spr_total;
-    const float* const ckpt = (const float*)a.ckpt;
+    const int64_t n_end = a.n_end, ckpt_total = a.ckpt_total, spr_total = a.spr_total;
+    const float* const ckpt = ckpt_item<const float, M>((const float*)a.ckpt, G, k_first);
     const double* const lam_mu = a.lam_mu;
     float* const seg = a.segbuf + a.seg_off[item];
     double* const partial = a.partial + 3 * item;
@@ -196,8 +196,8 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
         // step is rebuilt by one step from the last checkpoint; the sweep then
         // reads Q^n from checkpoint n (one step ahead), in the same order and
         // expressions as the segment loop below with segments of one step.
-        const float* cp = ckpt + (int64_t)(n_end - 1) * state_total;
-        load_lane<float, M>(qn, valid, cp, G, tg);
+        const float* cp = ckpt + (int64_t)(n_end - 1) * ckpt_total;
+        load_ckpt<float, M>(qn, valid, cp, G, tg);
         kc = slot_coef<float, M>(G, valid);
         s = qn;
         if constexpr (NMAP == 1) {
@@ -213,8 +213,8 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
         int w = (int)(n_end / S) - 1;
         for (int n = (int)n_end - 1; n >= 0; --n) {
             q = qn;
-            cp -= state_total;
-            if (n > 0) load_lane<float, M>(qn, valid, cp, G, tg);
+            cp -= ckpt_total;
+            if (n > 0) load_ckpt<float, M>(qn, valid, cp, G, tg);
             if (rr == 0) {
                 double dH = 0.0, db = 0.0;
                 inject<M, FENE>(s, valid, G, *ap, tg, w, lx, ly, lz, dH, db);
@@ -234,7 +234,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
     for (int sgi = (K == 1 && n_end > 0) ? -1 : n_seg - 1; sgi >= 0; --sgi) {
         const int s0 = sgi * K;
         const int s1 = (int)min(n_end, (int64_t)s0 + K);
-        load_lane<float, M>(s, valid, ckpt + (int64_t)sgi * state_total, G, tg);
+        load_ckpt<float, M>(s, valid, ckpt + (int64_t)sgi * ckpt_total, G, tg);
         kc = slot_coef<float, M>(G, valid);
         float* wp = seg;
         if constexpr (NMAP == 1) {

@@ -370,6 +370,49 @@ __device__ __forceinline__ void store_lane(const Lane<T, M>& s, const bool (&val
     }
 }
 
+// Checkpoint rows of one work item: [slot m][xyz][lane], U = P L lanes per
+// row, so each store or load instruction covers U consecutive values. Slots
+// that are not a spring of a replica hold 0.
+template <typename T, int M>
+__device__ __forceinline__ T* ckpt_item(T* base, const GroupDev& G, int k_first) {
+    return base + G.ck_off + (int64_t)(k_first / G.P) * (M * 3 * G.P * G.L);
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void store_ckpt(const Lane<T, M>& s, T* __restrict__ dst, const GroupDev& G) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int U = G.P * G.L;
+    if (lane < U) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            dst[(3 * m) * U + lane] = s.qx[m];
+            dst[(3 * m + 1) * U + lane] = s.qy[m];
+            dst[(3 * m + 2) * U + lane] = s.qz[m];
+        }
+    }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void load_ckpt(Lane<T, M>& s, bool (&valid)[M], const T* __restrict__ src,
+                                          const GroupDev& G, const TileGeom& tg) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int U = G.P * G.L;
+    const int nm1 = G.N - 1;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        valid[m] = tg.rep_ok && tg.j0 + m < nm1;
+        T x = (T)0, y = (T)0, z = (T)0;
+        if (valid[m] && lane < U) {
+            x = src[(3 * m) * U + lane];
+            y = src[(3 * m + 1) * U + lane];
+            z = src[(3 * m + 2) * U + lane];
+        }
+        s.qx[m] = x;
+        s.qy[m] = y;
+        s.qz[m] = z;
+    }
+}
+
 __device__ __forceinline__ void flush_clamps(int clamps, unsigned long long* counter) {
     if (clamps) atomicAdd(counter, (unsigned long long)clamps);
 }

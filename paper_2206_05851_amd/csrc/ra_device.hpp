@@ -85,6 +85,13 @@ __device__ __forceinline__ float u01_f32(uint32_t x) {
 __device__ __forceinline__ double u01_f64(uint32_t x) {
     return (double)((x >> 8) | 1u) * 0x1p-24;
 }
+// Unfolding-event uniform from two words: the top 52 bits m of hi:lo give
+// (2m + 1) 2^-53, exact in binary64; event probabilities per window reach
+// 1e-7 and below, under the 2^-24 grid of the one-word map.
+__device__ __forceinline__ double u01_f64_53(uint32_t hi, uint32_t lo) {
+    const uint64_t m = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+    return (double)(2 * m + 1) * 0x1p-53;
+}
 
 // Box-Muller, three normals from one Philox block: (r0 cos 2pi u1, r0 sin 2pi u1,
 // r1 cos 2pi u3), r = sqrt(-2 ln u). FP32 uses the hardware transcendentals:

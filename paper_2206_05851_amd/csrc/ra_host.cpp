@@ -36,7 +36,7 @@ struct ra_ctx {
     ColTile* dtiles = nullptr;
     int64_t* dpar_off = nullptr;
     int32_t* ditem_begin = nullptr;
-    int64_t state_total = 0, smp_total = 0, spr_total = 0, pos_total = 0;
+    int64_t state_total = 0, smp_total = 0, spr_total = 0, pos_total = 0, ckpt_total = 0;
     int64_t max_group_elems = 0;
     void* state = nullptr;          // fused path bond state
     void* pos[2] = {nullptr, nullptr};
@@ -152,7 +152,8 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
     }
     for (int i = 0; i < n; ++i) {
         const ra_chain_desc& d = g[i];
-        const int nmax = (n_pair || n_hi) ? WAVE : r->precision == 64 ? 256 : 1024;
+        // FP64 fused kernels hold up to 4 beads per lane; the plain path has no lane limit
+        const int nmax = (n_pair || n_hi) ? WAVE : (r->precision == 64 && !r->plain) ? 256 : 1024;
         const char* bad = nullptr;
         if (d.n_beads < 2 || d.n_beads > nmax) bad = "n_beads out of range";
         else if (d.n_replicas < 1) bad = "n_replicas < 1";
@@ -330,6 +331,8 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
         G.spr_off = c->spr_total;
         G.pos_off = c->pos_total;
         c->state_total += (int64_t)G.R * nm1 * 3;
+        G.ck_off = c->ckpt_total;   // checkpoint rows: [item][slot][xyz][P L lanes]
+        c->ckpt_total += (int64_t)((G.R + G.P - 1) / G.P) * G.M * 3 * G.P * G.L;
         c->smp_total += (int64_t)G.R * nm1;
         c->spr_total += nm1;
         c->pos_total += (int64_t)G.R * G.N * 3;
@@ -366,7 +369,7 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
         // interval that minimises checkpoints + segment buffer, sqrt(max_steps)
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
-        const double need = ((double)run->max_steps + 1.0) * (double)c->state_total * (double)esz;
+        const double need = ((double)run->max_steps + 1.0) * (double)c->ckpt_total * (double)esz;
         c->run.checkpoint_every =
             need <= 0.25 * (double)free_b ? 1 : std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, run->max_steps))));
     }
@@ -413,7 +416,7 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     if (c->run.checkpoint_every > 0) {
         const int K = c->run.checkpoint_every;
         c->n_ckpt = ((int64_t)run->max_steps + K - 1) / K + 1;
-        ALLOC(p8, c->n_ckpt * c->state_total * esz);
+        ALLOC(p8, c->n_ckpt * c->ckpt_total * esz);
         c->ckpt = p8;
         std::vector<int64_t> seg_off(c->hitems.size());
         int64_t tot = 0;
@@ -495,6 +498,7 @@ static FwdArgs fwd_args(const ra_ctx* c) {
     a.ckpt = c->ckpt;
     a.smp_total = c->smp_total;
     a.state_total = c->state_total;
+    a.ckpt_total = c->ckpt_total;
     a.step0 = c->dstep;
     a.status = c->status;
     a.clamps = c->clamps;
@@ -655,6 +659,7 @@ ra_status ra_backward(ra_ctx* c, const double* mean, const double* grad_mean, co
     a.key1 = (uint32_t)(c->run.seed >> 32);
     a.ckpt = c->ckpt;
     a.state_total = c->state_total;
+    a.ckpt_total = c->ckpt_total;
     a.n_end = c->step;
     a.lam_mu = c->lam_mu;
     a.spr_total = c->spr_total;

@@ -52,7 +52,9 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
     const int64_t lane_off = G.smp_off + (int64_t)tg.k * nm1 + tg.j0;
     T* smp_w = (T*)a.samples + (int64_t)(n0 / (uint32_t)S) * smp_total + lane_off;
     T* tsf_w = TSF ? (T*)a.tsf + (int64_t)(n0 / (uint32_t)S) * smp_total + lane_off : nullptr;
-    T* ck_w = K > 0 ? (T*)a.ckpt + (int64_t)((n0 + (uint32_t)K - 1) / (uint32_t)K) * state_total : nullptr;
+    const int64_t ckpt_total = a.ckpt_total;
+    T* ck_w = K > 0 ? ckpt_item<T, M>((T*)a.ckpt, G, k_first) + (int64_t)((n0 + (uint32_t)K - 1) / (uint32_t)K) * ckpt_total
+                    : nullptr;
     double* const tacc_g = TSF ? a.tsf_acc + lane_off : nullptr;
     int to_smp = S - (int)(n0 % (uint32_t)S);                              // steps to the next window end
     int to_ck = K > 0 ? (int)((K - (int)(n0 % (uint32_t)K)) % K) : INT32_MAX;  // steps to the next checkpoint
@@ -179,8 +181,8 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
     uint32_t n = n0;
     while (left > 0) {
         if (to_ck == 0) {                      // checkpoint before step n
-            store_lane<T, M>(s, valid, ck_w, G, tg);
-            ck_w += state_total;
+            store_ckpt<T, M>(s, ck_w, G);
+            ck_w += ckpt_total;
             to_ck = K;
         }
         int len = min(left, min(to_smp, to_ck));
@@ -565,7 +567,7 @@ __global__ __launch_bounds__(64) void bell_kernel(const GroupDev* __restrict__ g
         if (events) {
             const Words u = philox10((uint32_t)w, (uint32_t)j, 0u, (2u << 24) | (G.stream & 0xFFFFFFu), key0, key1);
             const double p = -expm1(-k * (double)S * G.dt);
-            events[o] = u01_f64(u.x) < p ? 1 : 0;
+            events[o] = u01_f64_53(u.x, u.y) < p ? 1 : 0;
         }
     }
     // fixed-order butterfly over the 64 lanes

@@ -30,9 +30,10 @@ struct FwdArgs {
     void* samples;             // T[max_windows][smp_total]
     void* tsf;                 // T[max_windows][smp_total] or nullptr
     double* tsf_acc;           // running window sums [smp_total] or nullptr
-    void* ckpt;                // T[n_ckpt][state_total] or nullptr
+    void* ckpt;                // T[n_ckpt][ckpt_total] or nullptr (per item: [M][3][lanes used])
     int64_t smp_total;         // sample elements per window
     int64_t state_total;       // bond-state elements
+    int64_t ckpt_total;        // elements per checkpoint
     const int64_t* step0;      // device: steps since init before this launch
     int64_t n_steps;
     int32_t* status;           // bit 0: invalid parent, bit 1: non-finite tension
@@ -45,8 +46,9 @@ struct AdjArgs {
     int32_t n_items;
     int32_t S, K;
     uint32_t key0, key1;
-    const void* ckpt;          // forward checkpoints T[n_ckpt][state_total]
+    const void* ckpt;          // forward checkpoints T[n_ckpt][ckpt_total]
     int64_t state_total;
+    int64_t ckpt_total;
     int64_t n_end;             // steps since init covered by the adjoint
     const double* lam_mu;      // dJ/d mean [W][spr_total]
     int64_t spr_total;

@@ -294,7 +294,7 @@ __global__ __launch_bounds__(64) void mftu_kernel(const double* __restrict__ rat
 
 // MFTU by sampling unfolding events, one wavefront per (trial, group): the
 // lanes cover the chain's springs; window v carries the rates of sampled
-// window v mod n_windows and spring j unfolds there when the tag-2 uniform of
+// window v mod n_windows and spring j unfolds there when the tag-2 53-bit uniform of
 // counter (v, j, trial, 2<<24 | stream) is below 1 - exp(-k S dt) (trial 0 over
 // the sampled windows draws exactly ra_bell_rates's events). The wave stops at
 // the first window with any unfolding (a wave vote) or after max_windows.
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(64) void first_event_kernel(const GroupDev* __restr
         for (int j = lane; j < nm1; j += WAVE) {
             const double k = rates[w * spr_total + G.spr_off + j];
             const Words u = philox10((uint32_t)v, (uint32_t)j, (uint32_t)trial, ctr3, keys);
-            hit |= u01_f64(u.x) < -expm1(-k * window_time);
+            hit |= u01_f64_53(u.x, u.y) < -expm1(-k * window_time);
         }
         if (__builtin_amdgcn_ballot_w64(hit) != 0) {
             first = v;

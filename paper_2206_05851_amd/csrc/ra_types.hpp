@@ -27,6 +27,8 @@ struct GroupDev {
     int64_t smp_off;         // first element of this group's [R][N-1] block in a window
     int64_t spr_off;         // first spring of this group in a profile row
     int64_t pos_off;         // first element of this group's [R][N][3] positions (plain path)
+    int64_t ck_off;          // first element of this group's work items in a checkpoint, whose
+                             // layout per item is [slot M][xyz][lane < P L] (lane-contiguous rows)
     // pair-interaction model (Sec. II collapsed polymer): spring 2 = rest-length
     // harmonic, F = H (|Q| - r0) Q/|Q|; LJ u [(rmin/r)^12 - 2 (rmin/r)^6] between
     // beads |i - j| >= 2, force (12u/r^2) [(rmin/r)^12 - (rmin/r)^6] (r_i - r_j)

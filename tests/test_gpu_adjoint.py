@@ -46,7 +46,7 @@ def _check(g_gpu, g_ref, rtol):
 
 @pytest.mark.parametrize("spring,flow,N,policy", [(wl.FENE, wl.UNIAXIAL, 12, 0), (wl.FENE, wl.SHEAR, 33, 0),
                                                   (wl.FENE, wl.SHEAR, 33, 1002), (wl.HOOKEAN, wl.PLANAR, 10, 1003),
-                                                  (wl.FENE, wl.PLANAR, 150, 0)])
+                                                  (wl.FENE, wl.PLANAR, 150, 0), (wl.FENE, wl.UNIAXIAL, 300, 0)])
 def test_adjoint_matches_oracle_tangents_200_steps(spring, flow, N, policy):
     # policy 0 is the cost model's tile; 1000 + m forces m beads per lane
     b = 40.0 if spring == wl.FENE else 0.0

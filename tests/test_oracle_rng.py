@@ -86,6 +86,28 @@ def test_uniform_map_exact_values():
         assert np.float32(u) == u                        # exact in binary32
 
 
+def test_event_uniform_exact_values():
+    # two words -> an odd multiple of 2^-53 from the top 52 bits of hi:lo
+    assert ora.uniform53(0, 0) == 2.0 ** -53
+    assert ora.uniform53(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0 ** -53
+    assert ora.uniform53(0x80000000, 0) == 0.5 + 2.0 ** -53
+    assert ora.uniform53(0, 0xFFF) == 2.0 ** -53               # low 12 bits ignored
+    assert ora.uniform53(0, 0x1000) == 3.0 * 2.0 ** -53
+    assert ora.uniform53(1, 0) == (2.0 * 2 ** 20 + 1) * 2.0 ** -53
+    rng = np.random.default_rng(4)
+    prev = 0.0
+    for w in np.sort(rng.integers(0, 2 ** 64, size=2000, dtype=np.uint64)):
+        u = ora.uniform53(int(w) >> 32, int(w) & 0xFFFFFFFF)
+        assert 0.0 < u < 1.0 and u >= prev
+        assert (u * 2.0 ** 53) % 2 == 1                       # odd multiple of 2^-53
+        prev = u
+    # a probability far below the one-word grid (2^-24 ~ 6e-8) is resolved:
+    # the fraction of 64-bit words mapped below p is p to within 2^-52
+    p = 1.3e-9
+    m_below = np.ceil(p * 2.0 ** 52 - 0.5)
+    assert abs(m_below / 2.0 ** 52 - p) <= 2.0 ** -52
+
+
 def test_philox_words_uniform_chi2():
     counts = np.zeros((4, 64))
     for i in range(20000):
