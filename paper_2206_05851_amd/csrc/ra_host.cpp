@@ -276,7 +276,7 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     int family = 4;
     for (int i = 0; i < n_groups; ++i)
         if (groups[i].n_beads > 4 * WAVE) family = 16;
-    if (run->precision == 64) family = 4;
+    if (run->precision == 64 && !run->plain) family = 4;   // the plain path only uses the tile for its work list
     const bool pair = is_pair_group(groups[0]);   // validated: all groups or none
     const bool hi = is_hi_group(groups[0]);
     if (pair) family = 2;
@@ -317,6 +317,13 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     if (run->noise_map != 0 && !run->plain && family != 4) {
         ra_destroy(c);
         return fail(nullptr, RA_EINVAL, "noise_map 1 needs at most 4 beads per lane (n_beads <= 256) on the fused path");
+    }
+
+    for (int i = 0; i < n_groups; ++i) {
+        if ((groups[i].n_beads + Ms[i] - 1) / Ms[i] > WAVE) {   // a replica must fit in one wavefront
+            ra_destroy(c);
+            return fail(nullptr, RA_EINVAL, "group " + std::to_string(i) + ": no tile holds its chain in a wavefront");
+        }
     }
 
     // layout

@@ -168,3 +168,16 @@ def test_static_run_rejections_on_host(lib):
     assert rc == -1 and "null" in msg
     rc, msg = call({}, {}, 10, outs=False)
     assert rc == -1 and "output" in msg
+
+
+def test_plain_fp64_long_chain_tile_on_host(lib):
+    # an FP64 plain-path context of 1000 beads is valid; its work list is laid
+    # out with a tile that holds the chain in one wavefront (on a host without
+    # a GPU the call then fails at allocation, with a code, not a crash)
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-only check")
+    rc, msg = _create(lib, dict(n_beads=1000, n_replicas=8), dict(precision=64, plain=1))
+    assert rc in (-2, -3), (rc, msg)
+    rc, msg = _create(lib, dict(n_beads=300), dict(precision=64))
+    assert rc == -1 and "n_beads" in msg
