@@ -523,7 +523,7 @@ def main():
                    "kernel_family": family, "noise_map": head_map},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_SLOTS / 1e12,
                      "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK_LANE_SLOTS,
-                     "traffic": traffic, "kernel": "fwd_kernel<float,16,2,%d>" % head_map, "kernel_ms": kernel_ms,
+                     "traffic": traffic, "kernel": "fwd_kernel<float,16,2,%d,1>" % head_map, "kernel_ms": kernel_ms,
                      "lane_slots_per_replica_bead_step": slots,
                      "replica_bead_steps_per_launch": work_per_step},
     }

@@ -149,14 +149,18 @@ __device__ __forceinline__ void gen_noise4_map1(Noise<T, M> (&e)[4], const Group
 }
 
 // G_j = g_j Q_j of slot m (spring factor evaluated once per slot and step).
-template <typename T, int M, bool FENE>
+// With TSF the slot's tension f = H g |Q| of the same state is added to
+// tsum[m] (Eq. 4, zero rest length): the step's force evaluation is the TSF
+// sample of the state it starts from, so no second spring-law evaluation is
+// needed for the time average.
+template <typename T, int M, bool FENE, bool TSF = false>
 __device__ __forceinline__ void slot_force(const Lane<T, M>& s, const GroupDev& G, int m, T& fx, T& fy, T& fz,
-                                           int& clamps) {
+                                           int& clamps, T* tsum = nullptr) {
     T g = (T)1;
-    if constexpr (FENE) {
-        const T q2 = fmadd(s.qx[m], s.qx[m], fmadd(s.qy[m], s.qy[m], s.qz[m] * s.qz[m]));
-        g = fene_g(s.qx[m], s.qy[m], s.qz[m], q2, (T)G.inv_q0sq, G.inv_q0sq_d, clamps);
-    }
+    T q2 = (T)0;
+    if constexpr (FENE || TSF) q2 = fmadd(s.qx[m], s.qx[m], fmadd(s.qy[m], s.qy[m], s.qz[m] * s.qz[m]));
+    if constexpr (FENE) g = fene_g(s.qx[m], s.qy[m], s.qz[m], q2, (T)G.inv_q0sq, G.inv_q0sq_d, clamps);
+    if constexpr (TSF) tsum[m] = fmadd(Co<T>{G}.H() * g, fast_sqrt(q2), tsum[m]);
     fx = g * s.qx[m];
     fy = g * s.qy[m];
     fz = g * s.qz[m];
@@ -193,15 +197,15 @@ template <int M> struct MaskedSlots { static constexpr bool value = M <= 4; };
 // spring of an active replica.
 // xnext(e0, en) gives the next lane's bead-0 normals (by DPP from e0 unless the
 // caller has them at hand, e.g. in LDS).
-template <typename T, int M, bool FENE, typename NoiseFn, typename NextFn>
+template <typename T, int M, bool FENE, bool TSF = false, typename NoiseFn, typename NextFn>
 __device__ __forceinline__ void physics_step_core(Lane<T, M>& s, NoiseFn&& xi, NextFn&& xnext,
                                                   const GroupDev& G, const bool (&valid)[M],
-                                                  const SlotCoef<T, M>& kc, int& clamps) {
+                                                  const SlotCoef<T, M>& kc, int& clamps, T* tsum = nullptr) {
     const Co<T> c{G};
     T f0x, f0y, f0z, flx, fly, flz;
-    slot_force<T, M, FENE>(s, G, 0, f0x, f0y, f0z, clamps);
+    slot_force<T, M, FENE, TSF>(s, G, 0, f0x, f0y, f0z, clamps, tsum);
     if constexpr (M > 1) {
-        slot_force<T, M, FENE>(s, G, M - 1, flx, fly, flz, clamps);
+        slot_force<T, M, FENE, TSF>(s, G, M - 1, flx, fly, flz, clamps, tsum);
     } else {
         flx = f0x; fly = f0y; flz = f0z;
     }
@@ -219,7 +223,7 @@ __device__ __forceinline__ void physics_step_core(Lane<T, M>& s, NoiseFn&& xi, N
         T Nx, Ny, Nz, Xx, Xy, Xz;     // G of slot m+1, xi of bead m+1
         if (m + 1 < M) {
             if (m + 1 == M - 1) { Nx = flx; Ny = fly; Nz = flz; }
-            else slot_force<T, M, FENE>(s, G, m + 1 < M ? m + 1 : m, Nx, Ny, Nz, clamps);
+            else slot_force<T, M, FENE, TSF>(s, G, m + 1 < M ? m + 1 : m, Nx, Ny, Nz, clamps, tsum);
             xi(m + 1, Xx, Xy, Xz);
         } else {
             Nx = fnx; Ny = fny; Nz = fnz;
@@ -249,48 +253,50 @@ __device__ __forceinline__ void physics_step_core(Lane<T, M>& s, NoiseFn&& xi, N
     }
 }
 
-template <typename T, int M, bool FENE, typename NoiseFn>
+template <typename T, int M, bool FENE, bool TSF = false, typename NoiseFn>
 __device__ __forceinline__ void physics_step_fn(Lane<T, M>& s, NoiseFn&& xi, const GroupDev& G,
                                                 const bool (&valid)[M], const SlotCoef<T, M>& kc,
-                                                int& clamps) {
-    physics_step_core<T, M, FENE>(
+                                                int& clamps, T* tsum = nullptr) {
+    physics_step_core<T, M, FENE, TSF>(
         s, xi,
         [](T ex, T ey, T ez, T& nx, T& ny, T& nz) {
             nx = from_next_lane(ex);
             ny = from_next_lane(ey);
             nz = from_next_lane(ez);
         },
-        G, valid, kc, clamps);
+        G, valid, kc, clamps, tsum);
 }
 
-template <typename T, int M, bool FENE>
+template <typename T, int M, bool FENE, bool TSF = false>
 __device__ __forceinline__ void physics_step(Lane<T, M>& s, const Noise<T, M>& e, const GroupDev& G,
-                                             const bool (&valid)[M], const SlotCoef<T, M>& kc, int& clamps) {
-    physics_step_fn<T, M, FENE>(
-        s, [&](int m, T& x, T& y, T& z) { x = e.x[m]; y = e.y[m]; z = e.z[m]; }, G, valid, kc, clamps);
+                                             const bool (&valid)[M], const SlotCoef<T, M>& kc, int& clamps,
+                                             T* tsum = nullptr) {
+    physics_step_fn<T, M, FENE, TSF>(
+        s, [&](int m, T& x, T& y, T& z) { x = e.x[m]; y = e.y[m]; z = e.z[m]; }, G, valid, kc, clamps, tsum);
 }
 
 // One full Euler-Maruyama step at global step n (noise + update).
-template <typename T, int M, bool FENE>
+template <typename T, int M, bool FENE, bool TSF = false>
 __device__ __forceinline__ void em_step(Lane<T, M>& s, const GroupDev& G, const bool (&valid)[M],
                                         const SlotCoef<T, M>& kc, uint32_t n, uint32_t bead0,
-                                        uint32_t replica, const RoundKeys& keys, int& clamps) {
-    physics_step_fn<T, M, FENE>(
+                                        uint32_t replica, const RoundKeys& keys, int& clamps, T* tsum = nullptr) {
+    physics_step_fn<T, M, FENE, TSF>(
         s,
         [&](int m, T& x, T& y, T& z) {
             normals3(philox10(n, bead0 + (uint32_t)m, replica, G.stream, keys), x, y, z);
         },
-        G, valid, kc, clamps);
+        G, valid, kc, clamps, tsum);
 }
 
 // One step at global step n under map 1 (noise from and into the carry).
-template <typename T, int M, bool FENE>
+template <typename T, int M, bool FENE, bool TSF = false>
 __device__ __forceinline__ void em_step_map1(Lane<T, M>& s, Carry<T, M>& cy, const GroupDev& G,
                                              const bool (&valid)[M], const SlotCoef<T, M>& kc, uint32_t n,
-                                             uint32_t bead0, uint32_t replica, const RoundKeys& keys, int& clamps) {
+                                             uint32_t bead0, uint32_t replica, const RoundKeys& keys, int& clamps,
+                                             T* tsum = nullptr) {
     Noise<T, M> e;
     gen_noise_map1<T, M>(e, cy, G, n, bead0, replica, keys);
-    physics_step<T, M, FENE>(s, e, G, valid, kc, clamps);
+    physics_step<T, M, FENE, TSF>(s, e, G, valid, kc, clamps, tsum);
 }
 
 // Tension f_j = H g_j |Q_j| (Eq. 4, zero rest length) of every slot.

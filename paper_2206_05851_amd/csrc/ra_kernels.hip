@@ -58,37 +58,54 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
     double* const tacc_g = TSF ? a.tsf_acc + lane_off : nullptr;
     int to_smp = S - (int)(n0 % (uint32_t)S);                              // steps to the next window end
     int to_ck = K > 0 ? (int)((K - (int)(n0 % (uint32_t)K)) % K) : INT32_MAX;  // steps to the next checkpoint
-    // TSF: per-step tensions are summed in registers over at most TSF_FLUSH
-    // steps and folded into the FP64 window sum in global memory only when a
-    // window is longer than that or continues in a later launch; a window that
-    // starts and ends within this launch and TSF_FLUSH steps is averaged from
-    // its register sum alone. Tensions are nonnegative, so a register sum of
-    // at most 512 terms carries a relative error below 511 ulp (3e-5).
+    // TSF: each step's force evaluation adds the tension of the state it
+    // starts from (slot_force), so a window's states n+1 .. n+S are the
+    // evaluations of steps n+1 .. n+S-1 plus the window-end state, which the
+    // sample computes anyway; the evaluation of step n (the previous window's
+    // last state) is cancelled by starting the sum at minus that tension.
+    // The sums stay in registers over at most TSF_FLUSH steps and are folded
+    // into the FP64 window sum in global memory only when a window is longer
+    // or continues in a later launch. Tensions are nonnegative, so a register
+    // sum of at most 512 terms (and the one cancelled term) carries a relative
+    // error of a few hundred ulp at most (below 3.1e-5).
     constexpr int TSF_FLUSH = 512;
+    // 6-16 beads per lane keep the separate tension pass after each step: their
+    // register budget (two wavefronts per SIMD) has no room for the fused sums
+    constexpr bool FUSED = TSF && M <= 4;
     T tpart[M];
+    T* const tsum = FUSED ? tpart : nullptr;
 #pragma unroll
     for (int m = 0; m < M; ++m) tpart[m] = (T)0;
+    if constexpr (FUSED) {
+        if (n0_64 % S == 0) {                // the launch starts a window
+            T f[M];
+            tensions<T, M, FENE>(s, G, f);
+#pragma unroll
+            for (int m = 0; m < M; ++m) tpart[m] = -f[m];
+        }
+    }
     // the window sum in global memory holds part of the current window: true
     // when the launch starts inside a window, and after every mid-window fold
     bool acc_live = (n0_64 % S) != 0;
-    auto flush_tsf = [&](bool window_end) {
+    // fend: the window-end tensions (window_end), which also start the next window's sum
+    auto flush_tsf = [&](bool window_end, const T (&fend)[M]) {
         if constexpr (TSF) {
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 if (valid[m]) {
                     const double acc = (acc_live ? tacc_g[m] : 0.0) + (double)tpart[m];
-                    if (window_end) tsf_w[m] = (T)(acc / (double)S);
+                    if (window_end) tsf_w[m] = (T)((acc + (FUSED ? (double)fend[m] : 0.0)) / (double)S);
                     else tacc_g[m] = acc;
                 }
-                tpart[m] = (T)0;
+                tpart[m] = (FUSED && window_end) ? -fend[m] : (T)0;
             }
             acc_live = !window_end;
         }
     };
     int clamps = 0;
-
+    // the separate pass: the tensions of the state after each step
     auto accumulate_tsf = [&]() {
-        if constexpr (TSF) {
+        if constexpr (TSF && !FUSED) {
             T f[M];
             tensions<T, M, FENE>(s, G, f);
 #pragma unroll
@@ -108,7 +125,7 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
         int i = 0;
         if constexpr (M == 1) {
             for (; i < len && ((n + (uint32_t)i) & 3u) != 0u; ++i) {
-                em_step_map1<T, M, FENE>(s, cy, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps);
+                em_step_map1<T, M, FENE, FUSED>(s, cy, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps, tsum);
                 accumulate_tsf();
             }
             if (i + 4 <= len) {
@@ -120,7 +137,7 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
                     gen_noise4_map1<T, M>(f, G, n + (uint32_t)(i + 4), bead0, rep, keys);
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        physics_step<T, M, FENE>(s, e[u], G, valid, kc, clamps);
+                        physics_step<T, M, FENE, FUSED>(s, e[u], G, valid, kc, clamps, tsum);
                         accumulate_tsf();
                     }
 #pragma unroll
@@ -132,8 +149,8 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
         // starts aligned (the carry is refilled before it is read); wider lanes
         // step through the carry from the start
         for (; i < len; ++i) {
-            em_step_map1<T, M, FENE>(s, cy, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps);
-            accumulate_tsf();
+            em_step_map1<T, M, FENE, FUSED>(s, cy, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps, tsum);
+                accumulate_tsf();
         }
     };
     auto run_steps = [&](uint32_t n, int len) {   // len steps starting at global step n
@@ -162,7 +179,7 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
                         gen_noise<T, M>(f[u], G, n + (uint32_t)(i + U + u), bead0, rep, keys);
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        physics_step<T, M, FENE>(s, e[u], G, valid, kc, clamps);
+                        physics_step<T, M, FENE, FUSED>(s, e[u], G, valid, kc, clamps, tsum);
                         accumulate_tsf();
                     }
 #pragma unroll
@@ -171,7 +188,7 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
             }
         }
         for (; i < len; ++i) {
-            em_step<T, M, FENE>(s, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps);
+            em_step<T, M, FENE, FUSED>(s, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps, tsum);
             accumulate_tsf();
         }
     };
@@ -204,14 +221,15 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
                     bad |= !__builtin_isfinite(f[m]);
                 }
             }
-            flush_tsf(true);
+            flush_tsf(true, f);
             to_flush = TSF_FLUSH;
             smp_w += smp_total;
             if constexpr (TSF) tsf_w += smp_total;
             if (bad) atomicOr(status, 2);
             to_smp = S;
         } else if (TSF && (to_flush == 0 || left == 0)) {
-            flush_tsf(false);
+            const T none[M] = {};
+            flush_tsf(false, none);
             to_flush = TSF_FLUSH;
         }
     }
@@ -238,36 +256,44 @@ __device__ __forceinline__ void run_forward(const FwdArgs& a, const GroupDev& Gm
     }
 }
 
-template <typename T, int M, int NMAP>
+// TSFK: 0 compiles the variants without TSF, 1 those with TSF (kernels of
+// their own, so the time-average sums do not raise the register budget of
+// runs without them), 2 both, chosen per context at run time (the RSF
+// cycle's dual launch: the parent keeps TSF, the replicas do not).
+template <typename T, int M, int NMAP, int TSFK>
 __device__ __forceinline__ void dispatch_spring(const FwdArgs& a, const GroupDev& G, int k_first, int64_t n0) {
     const bool tsf = a.tsf != nullptr;
+#define RA_FWD(FENE_, UK_, TSF_) run_forward<T, M, FENE_, UK_, TSF_, NMAP>(a, G, k_first, n0)
+#define RA_TSF(FENE_, UK_)                                        \
+    do {                                                          \
+        if constexpr (TSFK == 0) RA_FWD(FENE_, UK_, false);       \
+        else if constexpr (TSFK == 1) RA_FWD(FENE_, UK_, true);   \
+        else if (tsf) RA_FWD(FENE_, UK_, true);                   \
+        else RA_FWD(FENE_, UK_, false);                           \
+    } while (0)
     if constexpr (sizeof(T) == 8) {           // FP64 correctness path: fewer variants
-        if (G.spring == 1) {
-            if (tsf) run_forward<T, M, true, false, true, NMAP>(a, G, k_first, n0);
-            else run_forward<T, M, true, false, false, NMAP>(a, G, k_first, n0);
-        } else {
-            if (tsf) run_forward<T, M, false, false, true, NMAP>(a, G, k_first, n0);
-            else run_forward<T, M, false, false, false, NMAP>(a, G, k_first, n0);
-        }
+        if (G.spring == 1) RA_TSF(true, false);
+        else RA_TSF(false, false);
     } else {
         const bool uk = G.P == 1;
-#define RA_FWD(FENE_, UK_, TSF_) run_forward<T, M, FENE_, UK_, TSF_, NMAP>(a, G, k_first, n0)
         if (G.spring == 1) {
-            if (uk) { if (tsf) RA_FWD(true, true, true); else RA_FWD(true, true, false); }
-            else { if (tsf) RA_FWD(true, false, true); else RA_FWD(true, false, false); }
+            if (uk) RA_TSF(true, true);
+            else RA_TSF(true, false);
         } else {
-            if (uk) { if (tsf) RA_FWD(false, true, true); else RA_FWD(false, true, false); }
-            else { if (tsf) RA_FWD(false, false, true); else RA_FWD(false, false, false); }
+            if (uk) RA_TSF(false, true);
+            else RA_TSF(false, false);
         }
-#undef RA_FWD
     }
+#undef RA_TSF
+#undef RA_FWD
+    (void)tsf;
 }
 
 // WAVES_PER_EU is a register budget hint: family 4 needs none (about 100
 // VGPRs); family 16 is held to 2 resident waves per SIMD (256 registers), which
 // it fits without spilling — left alone the scheduler hoists all 16 Philox
 // chains and falls to 1 wave, and asking for 3-4 waves makes it spill.
-template <typename T, int FAMILY, int NMAP>
+template <typename T, int FAMILY, int NMAP, int TSFK>
 __device__ __forceinline__ void fwd_item(const FwdArgs& a, int item) {
     if (item >= a.n_items) return;
     if (*(const volatile int*)a.status & 1) return;   // invalid parent: no work
@@ -276,28 +302,28 @@ __device__ __forceinline__ void fwd_item(const FwdArgs& a, int item) {
     const int64_t n0 = *a.step0;
     if constexpr (FAMILY == 4) {
         switch (G.M) {
-        case 1: dispatch_spring<T, 1, NMAP>(a, G, it.k0, n0); break;
-        case 2: dispatch_spring<T, 2, NMAP>(a, G, it.k0, n0); break;
-        case 3: dispatch_spring<T, 3, NMAP>(a, G, it.k0, n0); break;
-        case 4: dispatch_spring<T, 4, NMAP>(a, G, it.k0, n0); break;
+        case 1: dispatch_spring<T, 1, NMAP, TSFK>(a, G, it.k0, n0); break;
+        case 2: dispatch_spring<T, 2, NMAP, TSFK>(a, G, it.k0, n0); break;
+        case 3: dispatch_spring<T, 3, NMAP, TSFK>(a, G, it.k0, n0); break;
+        case 4: dispatch_spring<T, 4, NMAP, TSFK>(a, G, it.k0, n0); break;
         default: break;
         }
     } else {
         switch (G.M) {
-        case 6: dispatch_spring<T, 6, 0>(a, G, it.k0, n0); break;
-        case 8: dispatch_spring<T, 8, 0>(a, G, it.k0, n0); break;
-        case 12: dispatch_spring<T, 12, 0>(a, G, it.k0, n0); break;
-        case 16: dispatch_spring<T, 16, 0>(a, G, it.k0, n0); break;
+        case 6: dispatch_spring<T, 6, 0, TSFK>(a, G, it.k0, n0); break;
+        case 8: dispatch_spring<T, 8, 0, TSFK>(a, G, it.k0, n0); break;
+        case 12: dispatch_spring<T, 12, 0, TSFK>(a, G, it.k0, n0); break;
+        case 16: dispatch_spring<T, 16, 0, TSFK>(a, G, it.k0, n0); break;
         default: break;
         }
     }
 }
 
-template <typename T, int FAMILY, int WAVES_PER_EU, int NMAP = 0>
+template <typename T, int FAMILY, int WAVES_PER_EU, int NMAP, int TSFK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 void fwd_kernel(FwdArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    fwd_item<T, FAMILY, NMAP>(a, (int)blockIdx.x * (int)(blockDim.x >> 6) + wave);
+    fwd_item<T, FAMILY, NMAP, TSFK>(a, (int)blockIdx.x * (int)(blockDim.x >> 6) + wave);
 }
 
 // Two contexts in one launch (the RSF cycle's replicas of window w and the
@@ -309,8 +335,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
 void fwd_dual_kernel(FwdArgs a, FwdArgs b, int blocks_a) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int wpb = (int)(blockDim.x >> 6);
-    if ((int)blockIdx.x < blocks_a) fwd_item<T, FAMILY, NMAP>(a, (int)blockIdx.x * wpb + wave);
-    else fwd_item<T, FAMILY, NMAP>(b, ((int)blockIdx.x - blocks_a) * wpb + wave);
+    if ((int)blockIdx.x < blocks_a) fwd_item<T, FAMILY, NMAP, 2>(a, (int)blockIdx.x * wpb + wave);
+    else fwd_item<T, FAMILY, NMAP, 2>(b, ((int)blockIdx.x - blocks_a) * wpb + wave);
 }
 
 __global__ void advance_kernel(int64_t* step, int64_t n) {
@@ -642,19 +668,25 @@ static dim3 grid1d(int64_t n, int block) {
 #define FAMILY16_WAVES 2
 #endif
 
+template <typename T, int FAMILY, int WPE, int NMAP>
+static void launch_fwd_tsf(const FwdArgs& a, dim3 grid, dim3 block, hipStream_t st) {
+    if (a.tsf) hipLaunchKernelGGL((fwd_kernel<T, FAMILY, WPE, NMAP, 1>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((fwd_kernel<T, FAMILY, WPE, NMAP, 0>), grid, block, 0, st, a);
+}
+
 hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves_per_block, int nmap,
                           hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
     const int wpb = waves_per_block;
     dim3 grid((a.n_items + wpb - 1) / wpb), block(WAVE * wpb);
     if (precision == 64) {
-        if (nmap == 1) hipLaunchKernelGGL((fwd_kernel<double, 4, 1, 1>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((fwd_kernel<double, 4, 1>), grid, block, 0, st, a);
+        if (nmap == 1) launch_fwd_tsf<double, 4, 1, 1>(a, grid, block, st);
+        else launch_fwd_tsf<double, 4, 1, 0>(a, grid, block, st);
     } else if (family == 4) {
-        if (nmap == 1) hipLaunchKernelGGL((fwd_kernel<float, 4, 1, 1>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((fwd_kernel<float, 4, 1>), grid, block, 0, st, a);
+        if (nmap == 1) launch_fwd_tsf<float, 4, 1, 1>(a, grid, block, st);
+        else launch_fwd_tsf<float, 4, 1, 0>(a, grid, block, st);
     } else {
-        hipLaunchKernelGGL((fwd_kernel<float, 16, FAMILY16_WAVES>), grid, block, 0, st, a);
+        launch_fwd_tsf<float, 16, FAMILY16_WAVES, 0>(a, grid, block, st);
     }
     return hipGetLastError();
 }
