@@ -21,15 +21,11 @@ template <> struct PairCo<float> {
     const GroupDev& G;
     __device__ float dtz() const { return G.dtz; }
     __device__ float r0() const { return G.r0; }
-    __device__ float lj12u() const { return G.lj12u; }
-    __device__ float ljr2() const { return G.ljr2; }
 };
 template <> struct PairCo<double> {
     const GroupDev& G;
     __device__ double dtz() const { return G.dtz_d; }
     __device__ double r0() const { return G.r0_d; }
-    __device__ double lj12u() const { return G.lj12u_d; }
-    __device__ double ljr2() const { return G.ljr2_d; }
 };
 
 // Force of the spring on bond Q acting on its first bead (toward the second).
@@ -110,8 +106,15 @@ __device__ __forceinline__ void run_pair(const FwdArgs& a, const GroupDev& Gm, i
     const T kx = bond_ok ? c.kx() : (T)0, ky = bond_ok ? c.ky() : (T)0, kz = bond_ok ? c.kz() : (T)0;
     const T kxz = bond_ok ? c.kxz() : (T)0;
     const T dtz = bond_ok ? pc.dtz() : (T)0, sg = bond_ok ? c.sigma() : (T)0;
-    const T lj12u = pc.lj12u(), ljr2 = pc.ljr2();
-    const int base = rep_ok ? seg * N : 0;   // LDS rows of this lane's replica
+    // LJ in units of rmin: positions scaled by 1/rmin, the pair sum scaled
+    // back by 12 u / rmin at the end
+    const T irm = (T)(1.0 / sqrt(G.ljr2_d)), ljf = (T)(G.lj12u_d / sqrt(G.ljr2_d));
+    // LDS rows of this lane's replica: its positions twice over (rows
+    // tb .. tb + 2N - 1), so that partner i + t is row tb + i + t for every
+    // t < N; lanes past the last segment read segment 0 and write nothing
+    const bool seg_ok = seg < G.P;
+    const bool one_seg = G.P == 1;
+    const int tb = seg_ok ? 2 * N * seg : 0;
     const RoundKeys keys = round_keys(a.key0, a.key1);
     const uint32_t n0 = (uint32_t)*a.step0;
     const int S = a.S;
@@ -132,39 +135,91 @@ __device__ __forceinline__ void run_pair(const FwdArgs& a, const GroupDev& Gm, i
         // previous replica, or lane -1, and contributes 0)
         T Fx = gx - from_prev_lane(gx), Fy = gy - from_prev_lane(gy), Fz = gz - from_prev_lane(gz);
         if constexpr (LJ) {
-            const T px = segment_scan(qx, i) - qx, py = segment_scan(qy, i) - qy, pz = segment_scan(qz, i) - qz;
-            xs[lane][0] = px;
-            xs[lane][1] = py;
-            xs[lane][2] = pz;
+            // one replica per wavefront (N > 32): the whole-wave DPP scan;
+            // else the segmented scan by lane shuffles
+            T sx, sy, sz;
+            if (one_seg) {
+                sx = wave_scan_incl(qx);
+                sy = wave_scan_incl(qy);
+                sz = wave_scan_incl(qz);
+            } else {
+                sx = segment_scan(qx, i);
+                sy = segment_scan(qy, i);
+                sz = segment_scan(qz, i);
+            }
+            const T px = (sx - qx) * irm, py = (sy - qy) * irm, pz = (sz - qz) * irm;
+            if (seg_ok) {
+                xs[tb + i][0] = px;
+                xs[tb + i][1] = py;
+                xs[tb + i][2] = pz;
+                xs[tb + i + N][0] = px;
+                xs[tb + i + N][1] = py;
+                xs[tb + i + N][2] = pz;
+            }
             // this wave alone uses its LDS rows: make the writes visible to
             // its own reads (and keep the next step's writes after them)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // Partners i + t (mod N) of the replica, read from the doubled
+            // table at rows i + t (no wrap test). t = 2 .. N - 2 are never
+            // bonded neighbours nor the bead itself, so that loop carries no
+            // mask; t = 1 and t = N - 1 meet the bonded neighbours except across
+            // the wrap-around (bead N-1 with bead 0), where the pair counts
+            // for N >= 3. In units of rmin: s = rmin^2 / r^2 is the reciprocal
+            // of the scaled r^2, and the pair term is s (s^6 - s^3) dx'.
+            const T* row = xs[tb + i];
             T lx = (T)0, ly = (T)0, lz = (T)0;
-            // unrolled by 8: eight independent reciprocal-and-multiply chains
-            // fill the issue slots of the single wavefront per SIMD (measured
-            // 4% faster than the compiler's 4; 16 is slower)
-#pragma unroll 8
-            for (int j = 0; j < N; ++j) {
-                const T dx = px - xs[base + j][0];
-                const T dy = py - xs[base + j][1];
-                const T dz = pz - xs[base + j][2];
-                // pairs |i - j| >= 2 of an existing replica only; for the
-                // others (the bead itself, bonded neighbours, lanes past the
-                // last replica) the coefficient is replaced by 0 below, which
-                // also discards the Inf/NaN of the self pair's 1/r^2
-                const int dj = j - i;
-                const bool use = rep_ok && (dj >= 2 || dj <= -2);
-                const T r2 = fmadd(dx, dx, fmadd(dy, dy, dz * dz));
-                const T inv = fast_rcp(r2);
-                const T s1 = ljr2 * inv;
-                const T s3 = s1 * s1 * s1;
-                const T cc = use ? lj12u * inv * fmadd(s3, s3, -s3) : (T)0;
-                lx = fmadd(cc, dx, lx);
-                ly = fmadd(cc, dy, ly);
-                lz = fmadd(cc, dz, lz);
+            const bool wrap_first = N >= 3 && i == nm1, wrap_last = N >= 3 && i == 0;
+            {
+                const T dx = px - row[4 * 1], dy = py - row[4 * 1 + 1], dz = pz - row[4 * 1 + 2];
+                const T s = fast_rcp(fmadd(dx, dx, fmadd(dy, dy, dz * dz)));
+                const T s3 = s * s * s;
+                // a select, not a product: drops the Inf/NaN of a coincident
+                // bonded neighbour
+                const T h = wrap_first ? s * fmadd(s3, s3, -s3) : (T)0;
+                lx = h * dx;
+                ly = h * dy;
+                lz = h * dz;
             }
+            // t = 2 .. N - 1 in blocks of 8 (independent reciprocal chains for
+            // the single wavefront per SIMD, all eight LDS reads in flight):
+            // whole blocks of t < N - 1 unmasked, then one block that holds
+            // t = N - 1 (the wrap-around pair of bead 0) and reads row N - 1
+            // with weight 0 past it
+            int t0 = 2;
+            for (; t0 + 8 <= nm1; t0 += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const T* r = row + 4 * (t0 + u);
+                    const T dx = px - r[0], dy = py - r[1], dz = pz - r[2];
+                    const T s = fast_rcp(fmadd(dx, dx, fmadd(dy, dy, dz * dz)));
+                    const T s3 = s * s * s;
+                    const T h = s * fmadd(s3, s3, -s3);
+                    lx = fmadd(h, dx, lx);
+                    ly = fmadd(h, dy, ly);
+                    lz = fmadd(h, dz, lz);
+                }
+            }
+            if (t0 <= nm1) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int t = t0 + u;
+                    const T* r = row + 4 * (t < nm1 ? t : nm1);
+                    const bool use = t < nm1 || (t == nm1 && wrap_last);
+                    const T dx = px - r[0], dy = py - r[1], dz = pz - r[2];
+                    const T s = fast_rcp(fmadd(dx, dx, fmadd(dy, dy, dz * dz)));
+                    const T s3 = s * s * s;
+                    // a select: drops the Inf/NaN of a coincident bonded neighbour
+                    const T h = use ? s * fmadd(s3, s3, -s3) : (T)0;
+                    lx = fmadd(h, dx, lx);
+                    ly = fmadd(h, dy, ly);
+                    lz = fmadd(h, dz, lz);
+                }
+            }
+            lx *= ljf;
+            ly *= ljf;
+            lz *= ljf;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -233,7 +288,7 @@ __device__ __forceinline__ void pair_item(const FwdArgs& a, int item, T (*xs)[4]
 
 template <typename T>
 __global__ __launch_bounds__(256) void fwd_pair_kernel(FwdArgs a) {
-    __shared__ T xs[4][WAVE][4];
+    __shared__ T xs[4][2 * WAVE][4];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     pair_item<T>(a, (int)blockIdx.x * (int)(blockDim.x >> 6) + wave, xs[wave]);
 }
@@ -241,7 +296,7 @@ __global__ __launch_bounds__(256) void fwd_pair_kernel(FwdArgs a) {
 // Two contexts in one launch (see fwd_dual_kernel): blocks [0, blocks_a) run a.
 template <typename T>
 __global__ __launch_bounds__(256) void fwd_pair_dual_kernel(FwdArgs a, FwdArgs b, int blocks_a) {
-    __shared__ T xs[4][WAVE][4];
+    __shared__ T xs[4][2 * WAVE][4];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int wpb = (int)(blockDim.x >> 6);
     if ((int)blockIdx.x < blocks_a) pair_item<T>(a, (int)blockIdx.x * wpb + wave, xs[wave]);

@@ -30,6 +30,17 @@ CASES = [
                                           lj_rmin=1.0)),
     ("harmonic, no LJ, N=64", lambda: wl.group(64, 3, 1e-5, wl.HARMONIC, 400.0, 0.0, wl.SHEAR, 30.0,
                                                rest_length=2.0)),
+    # each non-bonded pair is evaluated once, from the bead that reaches its
+    # partner in at most N/2 steps around the segment: odd N, a full
+    # wavefront (N = 64, the pairs at N/2 met from both ends), and the
+    # shortest chains (N = 3: one pair, reached across the wrap-around;
+    # N = 2: none)
+    ("paper N=13 odd, 4 replicas per wave", lambda: _paper_group(13, 9)),
+    ("paper N=64, full wavefront", lambda: _paper_group(64, 3)),
+    ("Hookean + LJ N=3", lambda: wl.group(3, 11, 1e-4, wl.HOOKEAN, 2.0, 0.0, wl.SHEAR, 1.0, lj_eps=0.5,
+                                          lj_rmin=1.0)),
+    ("Hookean + LJ N=2", lambda: wl.group(2, 40, 1e-4, wl.HOOKEAN, 2.0, 0.0, wl.SHEAR, 1.0, lj_eps=0.5,
+                                          lj_rmin=1.0)),
 ]
 
 
