@@ -16,6 +16,7 @@
 // and applies the bond-form update Q_j += dt kappa Q_j + (Y_{j+1} - Y_j), Y the
 // bead displacements without the flow term.
 #include "ra_chain.hpp"
+#include "ra_dpp.hpp"
 #include "ra_launch.hpp"
 
 namespace ra {
