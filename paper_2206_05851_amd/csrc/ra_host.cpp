@@ -820,9 +820,11 @@ ra_status ra_mftu_events(ra_ctx* c, const double* rates, int64_t n_windows, int3
         return fail(c, RA_EINVAL, "need n_windows >= 1, 1 <= n_trials <= 65535, 1 <= max_windows < 2^32");
     const int ng = (int)c->hgroups.size();
     if (ng > 65535) return fail(c, RA_EINVAL, "more than 65535 groups");
+    int max_springs = 1;
+    for (const auto& g : c->hgroups) max_springs = std::max(max_springs, g.N - 1);
     HIPCHK(c, launch_mftu_events(c->dgroups, ng, rates, n_windows, c->spr_total, n_trials, max_windows,
                                  c->run.sample_every, (uint32_t)c->run.seed, (uint32_t)(c->run.seed >> 32),
-                                 first_window, mftu, c->stream));
+                                 max_springs, first_window, mftu, c->stream));
     return RA_OK;
 }
 

@@ -119,6 +119,6 @@ hipError_t launch_block_sigma(const GroupDev* groups, const ColTile* tiles, int 
 hipError_t launch_mftu(const double* rate_sum, int64_t n_windows, int n_groups, double* mftu, hipStream_t st);
 hipError_t launch_mftu_events(const GroupDev* groups, int n_groups, const double* rates, int64_t n_windows,
                               int64_t spr_total, int n_trials, int64_t max_windows, int S, uint32_t key0,
-                              uint32_t key1, int64_t* first_window, double* mftu, hipStream_t st);
+                              uint32_t key1, int max_springs, int64_t* first_window, double* mftu, hipStream_t st);
 
 }  // namespace ra

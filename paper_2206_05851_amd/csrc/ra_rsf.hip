@@ -292,12 +292,89 @@ __global__ __launch_bounds__(64) void mftu_kernel(const double* __restrict__ rat
     if (threadIdx.x == 0) mftu[g] = 1.0 / (acc / (double)n_windows);
 }
 
-// MFTU by sampling unfolding events, one wavefront per (trial, group): the
-// lanes cover the chain's springs; window v carries the rates of sampled
-// window v mod n_windows and spring j unfolds there when the tag-2 53-bit uniform of
-// counter (v, j, trial, 2<<24 | stream) is below 1 - exp(-k S dt) (trial 0 over
-// the sampled windows draws exactly ra_bell_rates's events). The wave stops at
-// the first window with any unfolding (a wave vote) or after max_windows.
+// MFTU by sampling unfolding events. Window v carries the rates of sampled
+// window v mod n_windows, and spring j unfolds there when the tag-2 53-bit
+// uniform of counter (v, j, trial, 2<<24 | stream) is below 1 - exp(-k S dt)
+// (trial 0 over the sampled windows draws exactly ra_bell_rates's events).
+// The first window with any unfolding, or -1 after max_windows, is the trial's
+// first passage.
+//
+// The uniform is u = (2m + 1) 2^-53 with m the top 52 bits of its two words,
+// so u < p holds exactly when m is below the count of such m, ceil((p 2^53 - 1) / 2)
+// (0 when p 2^53 <= 1, 2^52 when p >= 1): p 2^53 is exact, and for
+// 1 < p 2^53 < 2^53 so are the subtraction and the halving. The per-draw test is
+// one 64-bit integer compare against a threshold computed once per (window,
+// spring) from the same FP64 expression.
+__device__ __forceinline__ uint64_t event_threshold(double p) {
+    const double x = p * 0x1p53;
+    if (!(x > 1.0)) return 0;   // no m, also for NaN
+    if (x >= 0x1p53) return (uint64_t)1 << 52;
+    return (uint64_t)ceil((x - 1.0) * 0.5);
+}
+
+// Thresholds in LDS, one workgroup of four wavefronts per (trial, group):
+// thread t takes window base + t, so lane order within a wavefront and the
+// wavefront index are window order; every thread draws all springs of its
+// window. The earliest window with a vote in any wavefront ends the trial for
+// the whole workgroup.
+constexpr int EVENT_THREADS = 256;
+constexpr size_t EVENT_LDS_MAX = 32 << 10;   // thresholds in LDS up to this size, else the kernel below
+
+__global__ __launch_bounds__(EVENT_THREADS) void first_event_lds_kernel(
+    const GroupDev* __restrict__ groups, const double* __restrict__ rates, int64_t n_windows, int64_t spr_total,
+    int64_t max_windows, int S, uint32_t key0, uint32_t key1, int64_t* __restrict__ first_window, int n_groups) {
+    extern __shared__ uint64_t thr[];   // [n_windows][N - 1]
+    __shared__ int64_t found[EVENT_THREADS / WAVE];
+    const int trial = blockIdx.x;
+    const int g = blockIdx.y;
+    const GroupDev& G = groups[g];
+    const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & (WAVE - 1);
+    const int nm1 = G.N - 1;
+    const double window_time = (double)S * G.dt;
+    const uint32_t ctr3 = (2u << 24) | (G.stream & 0xFFFFFFu);
+    const RoundKeys keys = round_keys<false>(key0, key1);
+    const int64_t n_thr = n_windows * nm1;
+    for (int64_t i = tid; i < n_thr; i += EVENT_THREADS) {
+        const int64_t w = i / nm1, j = i - w * nm1;
+        const double k = rates[w * spr_total + G.spr_off + j];
+        thr[i] = event_threshold(-expm1(-k * window_time));
+    }
+    __syncthreads();
+    const uint32_t nw = (uint32_t)n_windows;
+    for (int64_t base = 0; base < max_windows; base += EVENT_THREADS) {
+        const int64_t v = base + tid;
+        bool hit = false;
+        if (v < max_windows) {
+            const uint64_t* tw = thr + (int64_t)((uint32_t)v % nw) * nm1;
+            for (int j = 0; j < nm1; ++j) {
+                const Words u = philox10((uint32_t)v, (uint32_t)j, (uint32_t)trial, ctr3, keys);
+                const uint64_t m = ((uint64_t)u.x << 20) | (uint64_t)(u.y >> 12);
+                hit |= m < tw[j];
+            }
+        }
+        const uint64_t b = __builtin_amdgcn_ballot_w64(hit);
+        if (lane == 0) found[wv] = b ? base + WAVE * wv + __builtin_ctzll(b) : -1;
+        __syncthreads();
+        int64_t f = -1;
+#pragma unroll
+        for (int q = 0; q < EVENT_THREADS / WAVE; ++q) {
+            const int64_t x = found[q];
+            if (f < 0 && x >= 0) f = x;
+        }
+        __syncthreads();   // found[] is rewritten by the next round
+        if (f >= 0) {
+            if (tid == 0) first_window[(int64_t)trial * n_groups + g] = f;
+            return;
+        }
+    }
+    if (tid == 0) first_window[(int64_t)trial * n_groups + g] = -1;
+}
+
+// The same without the LDS table (chains whose thresholds do not fit): one
+// wavefront per (trial, group), the lanes cover the springs and the wave walks
+// the windows in order, the rate read and the FP64 test per draw.
 __global__ __launch_bounds__(64) void first_event_kernel(const GroupDev* __restrict__ groups,
                                                          const double* __restrict__ rates, int64_t n_windows,
                                                          int64_t spr_total, int64_t max_windows, int S,
@@ -417,10 +494,16 @@ hipError_t launch_block_sigma(const GroupDev* groups, const ColTile* tiles, int 
 
 hipError_t launch_mftu_events(const GroupDev* groups, int n_groups, const double* rates, int64_t n_windows,
                               int64_t spr_total, int n_trials, int64_t max_windows, int S, uint32_t key0,
-                              uint32_t key1, int64_t* first_window, double* mftu, hipStream_t st) {
+                              uint32_t key1, int max_springs, int64_t* first_window, double* mftu, hipStream_t st) {
     (void)hipGetLastError();   // report only this launch's own error
-    hipLaunchKernelGGL(first_event_kernel, dim3((unsigned)n_trials, (unsigned)n_groups), dim3(64), 0, st, groups,
-                       rates, n_windows, spr_total, max_windows, S, key0, key1, first_window, n_groups);
+    const size_t lds = (size_t)n_windows * (size_t)std::max(max_springs, 1) * sizeof(uint64_t);
+    if (n_windows <= 0xFFFFFFFFll && lds <= EVENT_LDS_MAX)
+        hipLaunchKernelGGL(first_event_lds_kernel, dim3((unsigned)n_trials, (unsigned)n_groups), dim3(EVENT_THREADS),
+                           lds, st, groups, rates, n_windows, spr_total, max_windows, S, key0, key1, first_window,
+                           n_groups);
+    else
+        hipLaunchKernelGGL(first_event_kernel, dim3((unsigned)n_trials, (unsigned)n_groups), dim3(64), 0, st, groups,
+                           rates, n_windows, spr_total, max_windows, S, key0, key1, first_window, n_groups);
     hipLaunchKernelGGL(mftu_events_kernel, dim3((unsigned)n_groups), dim3(64), 0, st, groups, first_window, n_trials,
                        max_windows, S, n_groups, mftu);
     return hipGetLastError();

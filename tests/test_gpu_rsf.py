@@ -142,6 +142,45 @@ def test_mftu_events_matches_oracle():
     rep.close()
 
 
+def test_mftu_events_threshold_edges_and_wide_chain_match_oracle():
+    # The event test as an integer threshold on the 52-bit uniform: rates of
+    # 0, below one 2^-53 step, ordinary, and large enough that 1 - exp(-k S dt)
+    # rounds to 1 (every draw an event), against the oracle's FP64 test on the
+    # same counters; and a chain whose per-window thresholds (599 springs x 8
+    # windows) exceed the LDS table, which takes the per-draw FP64 path.
+    import torch
+    from oracle import ora
+    from paper_2206_05851_amd import ra
+    S, W = 10, 8
+    rng = np.random.default_rng(11)
+    gs = [wl.group(9, 2, 1e-2, stream_id=4)]
+    rates = rng.uniform(0.0, 0.3, size=(W, 8))
+    rates[:, 0] = 0.0
+    rates[:, 1] = 1e-20
+    rates[3, 2] = 1e3
+    rates[5, :] = 1e-3
+    o = ora.Oracle(gs, 31, S, W)
+    rep = ra.Replicas(gs, 31, sample_every=S, max_windows=W)
+    announce("MFTU by events: threshold edges")
+    m_ref, f_ref = o.mftu_events(rates, 300, 50)
+    m, f = rep.mftu_events(torch.from_numpy(rates).cuda(), 300, 50)
+    assert np.array_equal(f.cpu().numpy(), f_ref)
+    assert np.allclose(m.cpu().numpy(), m_ref, rtol=1e-13, atol=0)
+    assert np.all(f_ref <= 3)   # window 3 holds a certain event
+    rep.close()
+    gw = [wl.group(600, 2, 1e-2, stream_id=9)]
+    rates = rng.uniform(0.0, 2e-3, size=(W, 599))
+    o = ora.Oracle(gw, 32, S, W)
+    rep = ra.Replicas(gw, 32, sample_every=S, max_windows=W)
+    announce("MFTU by events: 599 springs, per-draw path")
+    m_ref, f_ref = o.mftu_events(rates, 24, 40)
+    m, f = rep.mftu_events(torch.from_numpy(rates).cuda(), 24, 40)
+    assert np.array_equal(f.cpu().numpy(), f_ref)
+    assert np.allclose(m.cpu().numpy(), m_ref, rtol=1e-13, atol=0)
+    assert np.any(f_ref >= 0)
+    rep.close()
+
+
 def test_conformation_after_cycle_matches_oracle():
     gs = [wl.group(40, 16, 1e-4, wl.FENE, 1.0, 100.0, wl.SHEAR, wl.wi_to_rate(50.0, 40), stream_id=1),
           wl.group(7, 9, 1e-3, wl.HOOKEAN, 1.0, 0.0, wl.QUIESCENT, 0.0, stream_id=2)]
