@@ -97,6 +97,28 @@ __device__ __forceinline__ void inject(const Lane<float, M>& q, const bool (&val
     }
 }
 
+// FP32 partial sums of one reverse sweep (a segment, or one step when every
+// state is kept), turned into the (rate, H, b) gradient terms by rev_flush:
+//   rate: lambda . d(dt kappa Q)/d rate = dt (fx Sxx + fy Syy + fz Szz + fxz Sxz)
+//         with (fx, fy, fz, fxz) the flow pattern and S_ab = sum lambda_a Q_b;
+//   H:    dtz (S1 + S2), b: -cF S2 / b, with S1 = sum g mu.Q and
+//         S2 = sum g^2 s mu.Q (s and the 2/Q0^2 term are 0 on the guard and
+//         for Hookean springs).
+struct RevSums {
+    float sxx, syy, szz, sxz, s1, s2;
+};
+
+__device__ __forceinline__ void rev_flush(const RevSums& r, const GroupDev& G, double& gr, double& gH, double& gb) {
+    const double dt = G.dt;
+    double pr = 0.0;
+    if (G.flow == 1) pr = dt * ((double)r.sxx - 0.5 * ((double)r.syy + (double)r.szz));
+    else if (G.flow == 2) pr = dt * ((double)r.sxx - (double)r.syy);
+    else if (G.flow == 3) pr = dt * (double)r.sxz;
+    gr += pr;
+    gH += (G.dt / G.zeta) * ((double)r.s1 + (double)r.s2);
+    if (G.spring == 1) gb += -(double)G.cF * (double)r.s2 / G.b;
+}
+
 // Reverse step through Phi at the state q = Q^n; lambda holds lambda^{n+1}.
 // kc.cF is 0 on slots that are not a spring of an active replica: their
 // lambda starts at 0, gets no injection, and with a zero coefficient on the
@@ -104,17 +126,8 @@ __device__ __forceinline__ void inject(const Lane<float, M>& q, const bool (&val
 // nothing to the theta sums either).
 template <int M, bool FENE>
 __device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const SlotCoef<float, M>& kc, const GroupDev& G,
-                                             float (&lx)[M], float (&ly)[M], float (&lz)[M], float& gr,
-                                             float& gH, float& gb) {
-    const float kx = G.kx, ky = G.ky, kz = G.kz, kxz = G.kxz, cF = G.cF;
-    // d(dt kappa)/d rate, per flow
-    float px = 0.f, py = 0.f, pz = 0.f, pxz = 0.f;
-    const float dt = (float)G.dt;
-    if (G.flow == 1) { px = dt; py = -0.5f * dt; pz = -0.5f * dt; }
-    else if (G.flow == 2) { px = dt; py = -dt; }
-    else if (G.flow == 3) { pxz = dt; }
-    const float dtz = (float)(G.dt / G.zeta);
-    const float inv_b = FENE ? 1.0f / (float)G.b : 0.0f;
+                                             float (&lx)[M], float (&ly)[M], float (&lz)[M], RevSums& r) {
+    const float kx = G.kx, ky = G.ky, kz = G.kz, kxz = G.kxz;
     const float plx = from_prev_lane(lx[M - 1]), ply = from_prev_lane(ly[M - 1]), plz = from_prev_lane(lz[M - 1]);
     const float nlx = from_next_lane(lx[0]), nly = from_next_lane(ly[0]), nlz = from_next_lane(lz[0]);
     float ux[M], uy[M], uz[M];
@@ -136,26 +149,26 @@ __device__ __forceinline__ void reverse_step(const Lane<float, M>& q, const Slot
         bool smooth;
         factor_gs<FENE>(q.qx[m], q.qy[m], q.qz[m], G, g, s, smooth);
         const float Qx = q.qx[m], Qy = q.qy[m], Qz = q.qz[m];
-        // theta terms with lambda^{n+1}
-        gr += fmadd(lx[m], fmadd(px, Qx, pxz * Qz), fmadd(ly[m], py * Qy, lz[m] * pz * Qz));
+        // rate terms with lambda^{n+1}
+        r.sxx = fmadd(lx[m], Qx, r.sxx);
+        r.syy = fmadd(ly[m], Qy, r.syy);
+        r.szz = fmadd(lz[m], Qz, r.szz);
+        r.sxz = fmadd(lx[m], Qz, r.sxz);
         const float muQ = fmadd(ux[m], Qx, fmadd(uy[m], Qy, uz[m] * Qz));
-        // off the guard s and 2/Q0^2 enter dG/dQ and dG/dtheta; on it (and
-        // for Hookean springs) both are 0 and only g remains
-        const float se = (FENE && smooth) ? s : 0.0f;
-        const float e2 = (FENE && smooth) ? 2.0f * G.inv_q0sq : 0.0f;
-        const float wH = dtz * g * fmadd(g, se, 1.0f);
-        const float wb = -cF * g * g * (se * inv_b);
-        gH = fmadd(wH, muQ, gH);
-        gb = fmadd(wb, muQ, gb);
-        // lambda^n = lambda + (dt kappa)^T lambda + cF J mu
-        const float ex = g * g * e2 * muQ;
-        const float jx = fmadd(g, ux[m], ex * Qx);
-        const float jy = fmadd(g, uy[m], ex * Qy);
-        const float jz = fmadd(g, uz[m], ex * Qz);
-        const float cFm = kc.cF[m];
-        const float nx = lx[m] + fmadd(kx, lx[m], cFm * jx);
-        const float ny = ly[m] + fmadd(ky, ly[m], cFm * jy);
-        const float nz = lz[m] + fmadd(kz, lz[m], fmadd(kxz, lx[m], cFm * jz));
+        // lambda^n = lambda + (dt kappa)^T lambda + cF J mu with
+        // J mu = g mu + (2 g^2 / Q0^2) (Q.mu) Q off the guard, g mu on it
+        const float cg = kc.cF[m] * g;
+        const float t = g * muQ;
+        r.s1 += t;
+        float ce = 0.0f;
+        if constexpr (FENE) {
+            const float ge = g * t;
+            r.s2 = fmadd(ge, smooth ? s : 0.0f, r.s2);
+            ce = kc.cF[m] * (smooth ? ge * (2.0f * G.inv_q0sq) : 0.0f);
+        }
+        const float nx = lx[m] + fmadd(kx, lx[m], fmadd(cg, ux[m], ce * Qx));
+        const float ny = ly[m] + fmadd(ky, ly[m], fmadd(cg, uy[m], ce * Qy));
+        const float nz = lz[m] + fmadd(kz, lz[m], fmadd(kxz, lx[m], fmadd(cg, uz[m], ce * Qz)));
         lx[m] = nx;
         ly[m] = ny;
         lz[m] = nz;
@@ -211,6 +224,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
         }
         int rr = (int)(n_end % S);
         int w = (int)(n_end / S) - 1;
+        RevSums rs{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         for (int n = (int)n_end - 1; n >= 0; --n) {
             q = qn;
             cp -= ckpt_total;
@@ -222,11 +236,13 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
                 gb += db;
                 --w;
             }
-            float pr = 0.0f, pH = 0.0f, pb = 0.0f;
-            reverse_step<M, FENE>(q, kc, G, lx, ly, lz, pr, pH, pb);
-            gr += (double)pr;
-            gH += (double)pH;
-            gb += (double)pb;
+            reverse_step<M, FENE>(q, kc, G, lx, ly, lz, rs);
+            // FP32 partials over at most 128 steps, as the segments below hold
+            // theirs over one checkpoint interval
+            if ((n & 127) == 0) {
+                rev_flush(rs, G, gr, gH, gb);
+                rs = RevSums{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            }
             s = q;
             rr = rr == 0 ? S - 1 : rr - 1;
         }
@@ -257,7 +273,7 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
         // rr = (n + 1) mod S, w = window of state n + 1 when rr == 0
         int rr = s1 % S;
         int w = s1 / S - 1;
-        float pr = 0.0f, pH = 0.0f, pb = 0.0f;   // FP32 partials of this segment
+        RevSums rs{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // FP32 partials of this segment
         const float* rp = seg + (int64_t)(s1 - 1 - s0) * STRIDE;
         seg_load<M>(rp, 0, qn, lane);           // Q^{s1-1}, loaded one step ahead
         for (int n = s1 - 1; n >= s0; --n) {
@@ -271,13 +287,11 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
                 gb += db;
                 --w;
             }
-            reverse_step<M, FENE>(q, kc, G, lx, ly, lz, pr, pH, pb);
+            reverse_step<M, FENE>(q, kc, G, lx, ly, lz, rs);
             s = q;
             rr = rr == 0 ? S - 1 : rr - 1;
         }
-        gr += (double)pr;
-        gH += (double)pH;
-        gb += (double)pb;
+        rev_flush(rs, G, gr, gH, gb);
     }
     (void)spr_total;
     (void)lam_mu;
