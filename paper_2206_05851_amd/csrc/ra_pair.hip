@@ -6,8 +6,9 @@
 // One bead per lane, P = floor(64/N) replicas per wavefront (N <= 64). The
 // state stays the bond vectors Q_j (as in the chain kernels, so FP32 keeps
 // bond-scale precision however far the chain drifts in the flow); the bead
-// positions relative to bead 0 are rebuilt every step by a segmented wave
-// scan of the bonds and shared through LDS for the O(N^2) pair forces. The
+// positions relative to bead 0 are rebuilt every step by a wave scan of the
+// bonds (DPP with one replica per wavefront, lane shuffles per segment with
+// several) and shared through LDS for the O(N^2) pair forces. The
 // bond update is the difference of the bead updates of beads j+1 and j:
 //   Q_j' = Q_j + dt kappa Q_j + (dt/zeta) (F_{j+1} - F_j) + sigma (xi_{j+1} - xi_j)
 // with F_i the total force on bead i (springs + LJ).
