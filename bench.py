@@ -180,6 +180,77 @@ def cpu_baseline(groups, parents, run, single_replicas, per_thread, threads, noi
             "samples": smp, "tsf_samples": tsmp}
 
 
+def oracle_all_cores(jobs, threads):
+    """Run oracle jobs (callables returning the replica*bead*steps they did)
+    on a pool of host threads; returns (work, seconds)."""
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        work = sum(ex.map(lambda f: f(), jobs))
+    return work, time.perf_counter() - t0
+
+
+def oracle_job(group, parent, run, k_begin, k_end, noise_map, tangents=False):
+    """One oracle run of replicas [k_begin, k_end) of one chain: clone, all
+    steps, replica averages (and the gradient by forward-mode tangents)."""
+    def job():
+        import numpy as np
+        from oracle import ora
+        S = run["sample_every"]
+        o = ora.Oracle([group], run["seed"], S, run["steps"] // S, tangents=tangents, noise_map=noise_map)
+        o.set_replicas(0, k_begin, k_end)
+        o.init_chains([parent])
+        o.step(run["steps"])
+        m, _ = o.average_forces()
+        if tangents:
+            o.backward(np.ones_like(m), None, run["k0"], run["x_dagger"])
+        o.close()
+        return (k_end - k_begin) * group["n_beads"] * run["steps"]
+    return job
+
+
+def oracle_rates(threads, noise_map, gpu):
+    """The FP64 oracle on all host threads (replicas or whole chains split
+    over the threads) for the correctness and measurement workloads besides
+    the headline: rouse_fp64_small, fene50 and adjoint100 (gradient) in
+    full, batched512 on its first 16 chains (extrapolated by work). gpu maps
+    a workload to the GPU's rate for the same quantity, when bench.py
+    measured it."""
+    from paper_2206_05851_amd import workloads as wl
+
+    def split(groups, parents, run, nm, tangents=False):
+        jobs = []
+        for g, p in zip(groups, parents):
+            R = g["n_replicas"]
+            parts = min(R, 4 * threads)
+            for i in range(parts):
+                kb, ke = R * i // parts, R * (i + 1) // parts
+                if ke > kb:
+                    jobs.append(oracle_job(g, p, run, kb, ke, nm, tangents))
+        return jobs
+
+    res = {"cores": threads, "unit": "replica·bead·steps/s", "kind": "oracle (FP64, threads over replicas)"}
+    cases = [("rouse_fp64_small", wl.rouse_fp64_small(), 0, False, "all 64 replicas x 5000 steps"),
+             ("fene50", wl.fene50(), noise_map, False, "all 1024 replicas x 10^4 steps"),
+             ("adjoint100_gradient", wl.adjoint100(), noise_map, True,
+              "all 4096 replicas x 2000 steps, forward with tangents + gradient"),
+             ("batched512_first16", None, noise_map, False,
+              "chains 0..15 of 512 in full, their replicas split over the threads; a rate per "
+              "replica*bead*step, which extrapolates by work to all 512 chains")]
+    for name, wload, nm, tangents, sample in cases:
+        if wload is None:
+            groups, parents, run = wl.batched512()
+            groups, parents = groups[:16], parents[:16]
+        else:
+            groups, parents, run = wload
+        log("oracle on %d threads: %s" % (threads, name))
+        work, secs = oracle_all_cores(split(groups, parents, run, nm, tangents), threads)
+        res[name] = {"value": work / secs, "seconds": secs, "sample": sample}
+        if name in gpu:
+            res[name]["gpu_value"] = gpu[name]
+            res[name]["gpu_over_oracle"] = gpu[name] / (work / secs)
+    return res
+
+
 def accuracy(got, ref, first_windows):
     """Max relative errors: every sample, and the replica-mean profile of the
     compared replicas, over all windows and over the first windows."""
@@ -441,7 +512,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="plain,fene50,adjoint,batched,rsf50,sigma_sweep,collapsed50,hi50",
+    ap.add_argument("--extras", default="plain,fene50,adjoint,batched,rsf50,sigma_sweep,collapsed50,hi50,"
+                                      "oracle_rates",
                     help="comma-separated extra workloads to measure")
     ap.add_argument("--cpu-single-replicas", type=int, default=2,
                     help="oracle replicas on one thread (all 2 x 10^4 steps)")
@@ -621,6 +693,20 @@ def main():
                                          args.noise_map if rname == "rsf50" else 0)
     if "sigma_sweep" in extras:
         out["sigma_sweep"] = sigma_sweep_bench(dev, args.noise_map)
+    if "oracle_rates" in extras and not args.no_cpu_baseline:
+        gpu = {}
+        if "fene50" in out:
+            gpu["fene50"] = out["fene50"]["value"]
+        if "adjoint" in out:
+            a100 = out["adjoint"]["every_100"]
+            gpu["adjoint100_gradient"] = (out["adjoint"]["value"] * a100["backward_ms"]
+                                          / (a100["backward_ms"] + a100["forward_ms"]))
+        if "batched" in out:
+            gpu["batched512_first16"] = out["batched"]["value"]
+        out["oracle_rates"] = oracle_rates(max(1, min(16, cpu_cores())), args.noise_map, gpu)
+        out["oracle_rates"]["note"] = ("gpu_value: fene50 whole pass; adjoint100 forward + backward (checkpoints "
+                                       "every 100 steps); batched512: all 512 chains on the GPU against the "
+                                       "oracle's per-bead-step rate on the first 16")
     out["roofline_fractions"] = {"slots_per_replica_bead_step": SLOTS_PER_BEAD_STEP, "frac": fracs}
 
     if args.copy_calibration:
