@@ -82,13 +82,31 @@ FWD_SOURCES = ("ra_kernels.hip", "ra_chain.hpp", "ra_device.hpp", "ra_types.hpp"
                "ra_host.cpp", "ra_tune.cpp", "ra_tune.hpp")
 
 
-def fwd_sources_digest():
+def fwd_sources_digest(files=FWD_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in FWD_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2206_05851_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+# The pair kernel's lane-slots per replica*bead*step on collapsed50 (N = 50):
+# non-transcendental VALU instructions per wavefront-step (one bead per lane)
+# of fwd_pair_dual_kernel<float>, from rocprofv3 --pmc SQ_INSTS_VALU
+# SQ_INSTS_VALU_TRANS_F32 SQ_WAVES: (636,828,191 - 43,547,252) / 1001 wavefronts
+# / 750 steps. It holds for the pair kernel sources with this digest only.
+PAIR_SOURCES = ("ra_pair.hip", "ra_chain.hpp", "ra_device.hpp", "ra_dpp.hpp")
+PAIR_SLOTS = {"sha256": "31f8ee07c936b759b63ae8146dded2f6d62e929c16019ae0eace274b0415b73d",
+              "slots": (636828191.0 - 43547252.0) / 1001 / 750}
+FP32_VECTOR_PEAK = 157.3e12   # FLOP/s, packed FP32 included
+
+
+def hi_flops_per_replica_step(n_beads):
+    """Dense linear algebra of one HI step on the 3N x 3N tensor: Cholesky
+    n^3/3, the drift D F 2 n^2 and the displacement L xi n^2 flops."""
+    n = 3 * n_beads
+    return n ** 3 / 3.0 + 3.0 * n * n
 
 
 def log(msg):
@@ -318,8 +336,66 @@ def rsf_cycle_bench(workload, desc, dev, name, noise_map=0):
     res["mftu_events"] = dict(ev, trials=1024, max_windows=1 << 20, ms=1e3 * t_ev)
     rpar.close()
     rrep.close()
+    # roofline over the whole cycle's wall time (forward launches, re-clones,
+    # the parent, the estimators): a lower bound on the kernels' own fraction
+    g0 = rg[0]
+    if g0.get("hi_radius", 0.0) > 0.0:
+        reps = (g0["n_replicas"] + 1) * rS * rW / t   # replica-steps/s, the parent included
+        flops = hi_flops_per_replica_step(g0["n_beads"])
+        res["roofline"] = {"bound": "fp32_vector", "unit": "TFLOP/s", "peak": FP32_VECTOR_PEAK / 1e12,
+                           "achieved": flops * reps / 1e12, "frac": flops * reps / FP32_VECTOR_PEAK,
+                           "flops_per_replica_step": flops,
+                           "note": "dense linear algebra of the step (Cholesky n^3/3, D F 2n^2, L xi n^2, "
+                                   "n = 3N) over the cycle's wall time; 51 chains occupy 51 of 256 CUs"}
+    else:
+        pair = g0.get("lj_eps", 0.0) > 0.0 or g0["spring"] == 2
+        if pair:
+            slots = PAIR_SLOTS["slots"] if fwd_sources_digest(PAIR_SOURCES) == PAIR_SLOTS["sha256"] else None
+        else:
+            slots = SLOTS_PER_BEAD_STEP[noise_map]
+        rate = (g0["n_replicas"] + 1) * g0["n_beads"] * rS * rW / t
+        res["roofline"] = {"bound": "alu", "unit": "T VALU lane-slots/s", "peak": VALU_PEAK_LANE_SLOTS / 1e12,
+                           "lane_slots_per_replica_bead_step": slots,
+                           "achieved": None if slots is None else slots * rate / 1e12,
+                           "frac": None if slots is None else slots * rate / VALU_PEAK_LANE_SLOTS,
+                           "note": "over the cycle's wall time, the parent included; "
+                                   + ("pair kernel slots measured by counters at N = 50" if pair
+                                      else "the chain kernels' slot count")}
     log("%s: %.2f ms per cycle (%.1f us per window)" % (name, 1e3 * t, 1e6 * t / rW))
     return res
+
+
+def oracle_cycle_rates(workload, threads, reps_per_thread, windows):
+    """The oracle's RSF cycle (parent with noise tag 1, replicas re-cloned
+    every window) on a bounded sample: replicas [0, reps_per_thread) on one
+    thread, and reps_per_thread per thread on all threads (each thread runs
+    its own copy of the parent). Rates count replica*bead*steps only."""
+    from oracle import ora
+    groups, parents, run = workload
+    g = groups[0]
+    S, P = run["sample_every"], run["parent_steps"]
+
+    def job(k0):
+        op = ora.Oracle([dict(g, n_replicas=1)], run["seed"], P, windows, tsf=True)
+        op.set_tag(ora.TAG_PARENT)
+        op.init_chains(parents)
+        orr = ora.Oracle(groups, run["seed"], S, windows)
+        orr.set_replicas(0, k0, k0 + reps_per_thread)
+        orr.rsf_cycle(op, windows, P)
+        orr.average_forces()
+        op.close()
+        orr.close()
+        return reps_per_thread * g["n_beads"] * S * windows
+
+    t0 = time.perf_counter()
+    w1 = job(0)
+    t1 = time.perf_counter() - t0
+    work, ta = oracle_all_cores([lambda i=i: job(i * reps_per_thread) for i in range(threads)], threads)
+    return {"kind": "oracle", "unit": "replica·bead·steps/s", "cores": threads,
+            "value": work / ta, "seconds": ta, "single_thread": {"value": w1 / t1, "seconds": t1},
+            "sample": "RSF cycle of %d windows: the parent and %d replicas per thread (%d on %d threads; "
+                      "one thread for the single-thread rate), replica work only" % (
+                          windows, reps_per_thread, reps_per_thread * threads, threads)}
 
 
 def sigma_sweep_bench(dev, noise_map):
@@ -691,6 +767,13 @@ def main():
             # noise map 1 covers the chain model only (not the pair and HI models)
             out[rname] = rsf_cycle_bench(getattr(wl, rname)(), rdesc, dev, rname,
                                          args.noise_map if rname == "rsf50" else 0)
+            fracs[rname + "_cycle"] = out[rname]["roofline"]["frac"]
+            if not args.no_cpu_baseline:
+                reps, wins = {"rsf50": (4, 20), "collapsed50": (2, 20), "hi50": (1, 4)}[rname]
+                log("oracle %s cycle: %d replicas per thread, %d windows" % (rname, reps, wins))
+                out[rname]["oracle"] = oracle_cycle_rates(getattr(wl, rname)(), max(1, min(16, cpu_cores())),
+                                                          reps, wins)
+                out[rname]["oracle"]["gpu_over_oracle"] = out[rname]["value"] / out[rname]["oracle"]["value"]
     if "sigma_sweep" in extras:
         out["sigma_sweep"] = sigma_sweep_bench(dev, args.noise_map)
     if "oracle_rates" in extras and not args.no_cpu_baseline:
