@@ -76,8 +76,8 @@ SLOTS_PER_BEAD_STEP = {0: 40 + 8 + 5 + 31, 1: 30 + 6 + 4.5 + 31}
 # device copy in the same runs). Valid only for the kernel sources they were
 # taken on: the digest of those sources is recorded with the figure, and
 # traffic is reported as null when the sources have changed since.
-FWD_TRAFFIC = {"sha256": "736cde0051eea821bfa7421c31ed16b0e22b2ab46741f735d93ecf5dc862a85d", "noise_map": 0,
-               "bytes": (48766.354 * 2.0 + 2656047.896) * 1024}
+FWD_TRAFFIC = {"sha256": "904dca16b443cfa9feeefeed62d37958a7099853fa9ff4bfe094287f32986c35", "noise_map": 0,
+               "bytes": (48762.958 * 2.0 + 2656055.333) * 1024}
 FWD_SOURCES = ("ra_kernels.hip", "ra_chain.hpp", "ra_device.hpp", "ra_types.hpp", "ra_launch.hpp",
                "ra_host.cpp", "ra_tune.cpp", "ra_tune.hpp")
 

@@ -250,7 +250,9 @@ RA_API ra_status ra_mftu_events(ra_ctx* ctx, const double* rates, int64_t n_wind
 RA_API ra_status ra_conformation(ra_ctx* ctx, double* dbar, double* d_bead, double* rg2, double* src_rg2);
 
 /* Synchronise the context's stream and report device-side errors:
- * RA_EINVAL (invalid parent), RA_EUNSTABLE (non-finite tension) or RA_OK. */
+ * RA_EINVAL (invalid parent), RA_EUNSTABLE (non-finite tension, or a
+ * non-positive pivot in the Cholesky factorization of the RPY tensor of a
+ * hydrodynamic-interaction group) or RA_OK. */
 RA_API ra_status ra_sync_status(ra_ctx* ctx);
 
 /* Host copy of the per-group FENE guard counts (synchronises). out: host int64[n_groups]. */

@@ -844,6 +844,7 @@ ra_status ra_sync_status(ra_ctx* c) {
     HIPCHK(c, hipMemcpy(&s, c->status, sizeof s, hipMemcpyDeviceToHost));
     if (s & 1) return fail(c, RA_EINVAL, "invalid parent chain: FENE bond at or beyond Q0, or non-finite coordinate");
     if (s & 2) return fail(c, RA_EUNSTABLE, "non-finite tension sampled");
+    if (s & 4) return fail(c, RA_EUNSTABLE, "non-positive pivot in the Cholesky factorization of the RPY tensor");
     return RA_OK;
 }
 
