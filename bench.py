@@ -70,7 +70,9 @@ VALU_PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
 #   Philox 40 x 3/4 = 30; uniform maps 8 x 3/4 = 6; Box-Muller with both outputs
 #   of the second pair (2 log scalings + 4 radius products) x 3/4 = 4.5;
 #   FENE bond update 31.
-SLOTS_PER_BEAD_STEP = {0: 40 + 8 + 5 + 31, 1: 30 + 6 + 4.5 + 31}
+# Noise map 2 (beads in groups of four, three blocks per group and step) draws
+# and transforms the same 3/4 block per bead-step as map 1.
+SLOTS_PER_BEAD_STEP = {0: 40 + 8 + 5 + 31, 1: 30 + 6 + 4.5 + 31, 2: 30 + 6 + 4.5 + 31}
 # HBM bytes per launch of the headline's forward kernel, read with rocprofv3
 # counters (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, both factors from a 1 GiB
 # device copy in the same runs). Valid only for the kernel sources they were
@@ -196,6 +198,19 @@ def cpu_baseline(groups, parents, run, single_replicas, per_thread, threads, noi
     tsmp = np.concatenate([p[2] for p in parts], axis=1) if parts[0][2] is not None else None
     return {"single": (single_replicas * N * T / t1, t1), "all": (n_all * N * T / tall, tall, n_all),
             "samples": smp, "tsf_samples": tsmp}
+
+
+def oracle_samples(groups, parents, run, n_replicas, threads, noise_map):
+    """Per-replica samples of replicas [0, n_replicas) of a one-group workload
+    (the oracle's whole pass, replicas split over host threads)."""
+    import numpy as np
+    per = -(-n_replicas // threads)
+    edges = [(k, min(k + per, n_replicas)) for k in range(0, n_replicas, per)]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda e: oracle_range(groups, parents, run, e[0], e[1], noise_map), edges))
+    smp = np.concatenate([p[1] for p in parts], axis=1)
+    tsmp = np.concatenate([p[2] for p in parts], axis=1) if parts[0][2] is not None else None
+    return smp, tsmp
 
 
 def oracle_all_cores(jobs, threads):
@@ -598,7 +613,10 @@ def main():
     ap.add_argument("--noise-map", type=int, default=1, choices=(0, 1),
                     help="ra_run_desc.noise_map of fene50, its plain path, the adjoint, batched and rsf50 "
                          "(1: four normals per Philox block, three blocks per four bead-steps; the headline's "
-                         "16 beads per lane run noise map 0)")
+                         "16 beads per lane take --head-map)")
+    ap.add_argument("--head-map", type=int, default=2, choices=(0, 2),
+                    help="ra_run_desc.noise_map of the headline (16 beads per lane: map 0, one Philox block per "
+                         "bead-step, or map 2, three blocks per four beads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -620,7 +638,7 @@ def main():
     R, N, T, S = g["n_replicas"], g["n_beads"], run["steps"], run["sample_every"]
     W = T // S
     parent = torch.from_numpy(np.ascontiguousarray(parents[0]).reshape(-1)).to(dev)
-    head_map = 0   # noise map 1 is compiled for at most 4 beads per lane
+    head_map = args.head_map   # noise map 1 is compiled for at most 4 beads per lane
     rep = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W, tsf=True, device=dev,
                       noise_map=head_map)
     outs = [torch.empty((W, N - 1), dtype=torch.float64, device=dev) for _ in range(4)]
@@ -711,13 +729,22 @@ def main():
     if "plain" in extras:
         # plain unbatched path on the headline: a 2000-step prefix (4 windows),
         # timed after a warm-up, extrapolated to the 2x10^4 steps
+        # The plain kernel (one thread per bead) runs noise map 0, its cheapest:
+        # under map 2 each bead's thread would draw its group's three blocks.
         Tp = 2000
+        plain_map = 0
         out["plain_path"] = {"workload": "large1000, plain path (one launch per EM step and group, bead "
                                          "positions in HBM), first 2000 steps (4 windows), extrapolated to "
-                                         "2x10^4; FP32 (positions lose digits at N = 1000) and FP64"}
+                                         "2x10^4; FP32 (positions lose digits at N = 1000) and FP64; noise "
+                                         "map 0 (one Philox block per bead-step, the plain kernel's cheapest)",
+                             "noise_map": plain_map}
+        plain_ref = None
+        if cpu is not None:
+            plain_ref = oracle_samples(groups, parents, dict(run, steps=Tp), n_cmp, max(1, min(16, cpu_cores())),
+                                       plain_map)
         for prec in (32, 64):
             plain = ra.Replicas(groups, run["seed"], precision=prec, sample_every=S, max_windows=Tp // S,
-                                tsf=True, plain=True, device=dev, noise_map=head_map)
+                                tsf=True, plain=True, device=dev, noise_map=plain_map)
 
             def plain_pass():
                 plain.init_chains(parent)
@@ -730,11 +757,11 @@ def main():
             plain.sync_status()
             pv = R * N * Tp / tp
             res = {"value": pv, "ms_per_step_extrapolated": 1e3 * tp * T / Tp, "speedup_fused_over_plain": value / pv}
-            if cpu is not None:
+            if plain_ref is not None:
                 psmp, ptsmp = plain.samples(tsf=True)
                 res["accuracy_vs_oracle"] = {
-                    "rsf": accuracy(psmp[0][:, :n_cmp].cpu().numpy(), cpu["samples"][:Tp // S], 1),
-                    "tsf": accuracy(ptsmp[0][:, :n_cmp].cpu().numpy(), cpu["tsf_samples"][:Tp // S], 1)}
+                    "rsf": accuracy(psmp[0][:, :n_cmp].cpu().numpy(), plain_ref[0], 1),
+                    "tsf": accuracy(ptsmp[0][:, :n_cmp].cpu().numpy(), plain_ref[1], 1)}
                 del psmp, ptsmp
             out["plain_path"]["fp%d" % prec] = res
             plain.close()

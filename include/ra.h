@@ -126,7 +126,12 @@ typedef struct {
                                    second pair): steps 4m..4m+2 use the first three of
                                    their own block, step 4m+3 the fourth normals of those
                                    three blocks (three blocks per four steps). Chain
-                                   model only, at most 4 beads per lane (FP32 N <= 256) */
+                                   model only, at most 4 beads per lane (FP32 N <= 256);
+                                   2: the beads of a step in groups of four, bead 4q + r
+                                   takes normal r of the blocks with bead word 3q + c as
+                                   its component c (three blocks per four beads). Chain
+                                   model only, fused path with 8-16 beads per lane (FP32,
+                                   a group with N > 256) or the plain path; no adjoint */
 } ra_run_desc;
 
 /* Create a context: validates every descriptor (RA_EINVAL with nothing

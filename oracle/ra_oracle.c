@@ -99,11 +99,28 @@ void rao_noise(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
  * block per (step, bead), rao_noise. Map 1: the block of step n gives four
  * normals; steps n = 4m, 4m+1, 4m+2 take the first three of their own block,
  * and step 4m+3 takes the fourth normals of the blocks of steps 4m, 4m+1 and
- * 4m+2 (x, y, z in that order). Every step still gets three independent
- * standard normals, from three blocks per four steps. */
+ * 4m+2 (x, y, z in that order). Map 2: the beads of a step form groups of
+ * four, bead = 4q + r; the blocks with the bead word 3q, 3q+1 and 3q+2 give
+ * four normals each, and bead 4q + r takes normal r of block 3q + c as its
+ * component c (x, y, z for c = 0, 1, 2). Under every map each (step, bead)
+ * gets three independent standard normals; maps 1 and 2 use three blocks per
+ * four bead-steps. */
 void rao_noise_mapped(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
                       uint32_t tag, uint32_t group, int32_t map, double xi[3])
 {
+    if (map == 2) {
+        uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+        uint32_t q = bead / 4u, r = bead % 4u;
+        for (uint32_t c = 0; c < 3; ++c) {
+            uint32_t ctr[4] = { step, 3u * q + c, replica, (tag << 24) | (group & 0xFFFFFFu) };
+            uint32_t x[4];
+            double four[4];
+            rao_philox4x32_10(ctr, key, x);
+            rao_normals4(x, four);
+            xi[c] = four[r];
+        }
+        return;
+    }
     if (map == 0 || step % 4u != 3u) {
         rao_noise(seed, step, bead, replica, tag, group, xi);
         return;
@@ -258,7 +275,7 @@ struct rao_ctx {
     int64_t* clamps;       /* per group */
     double*  src;          /* [g][i][3] conformation the replicas were last cloned from */
     uint32_t tag;          /* noise tag of this context's trajectories */
-    int32_t  noise_map;    /* 0 or 1, see rao_noise_mapped */
+    int32_t  noise_map;    /* 0, 1 or 2, see rao_noise_mapped */
     int64_t  step;         /* steps taken since init */
     int64_t  n_windows;
     int      initialised;
@@ -430,7 +447,7 @@ int ra_oracle_set_tag(rao_ctx* c, uint32_t tag)
 
 int ra_oracle_set_noise_map(rao_ctx* c, int32_t map)
 {
-    if (!c || (map != 0 && map != 1)) return fail(c, RAO_EINVAL, "noise map must be 0 or 1");
+    if (!c || map < 0 || map > 2) return fail(c, RAO_EINVAL, "noise map must be 0, 1 or 2");
     c->noise_map = map;
     return RAO_OK;
 }

@@ -72,8 +72,9 @@ void   rao_noise(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
                  uint32_t tag, uint32_t group, double xi[3]);
 /* xi[0..2] as rao_normals, xi[3] = r1 sin(2 pi u3) */
 void   rao_normals4(const uint32_t x[4], double xi[4]);
-/* per-bead normals of one step under noise map 0 (rao_noise) or 1 (four
- * normals per block; step 4m+3 takes the fourth normals of steps 4m..4m+2) */
+/* per-bead normals of one step under noise map 0 (rao_noise), 1 (four
+ * normals per block; step 4m+3 takes the fourth normals of steps 4m..4m+2)
+ * or 2 (bead 4q + r takes normal r of the blocks with bead word 3q + c) */
 void   rao_noise_mapped(uint64_t seed, uint32_t step, uint32_t bead, uint32_t replica,
                         uint32_t tag, uint32_t group, int32_t map, double xi[3]);
 /* spring force F (on bead j, toward bead j+1), factor g (F = H g Q), tension f;
@@ -117,7 +118,7 @@ int  ra_oracle_backward(rao_ctx* c, const double* grad_mean, const double* grad_
                         double k0, double x_dagger, double* grad_params);
 /* noise tag of the context's trajectories: RAO_TAG_REPLICA (default) or RAO_TAG_PARENT */
 int  ra_oracle_set_tag(rao_ctx* c, uint32_t tag);
-/* noise map of the context's trajectories: 0 (default) or 1, see rao_noise_mapped */
+/* noise map of the context's trajectories: 0 (default), 1 or 2, see rao_noise_mapped */
 int  ra_oracle_set_noise_map(rao_ctx* c, int32_t map);
 /* RSF re-clone (Sec. II): every replica restarts from parent_xyz; the step
  * count (a multiple of S) is kept, and so are earlier windows */

@@ -299,6 +299,47 @@ __device__ __forceinline__ void em_step_map1(Lane<T, M>& s, Carry<T, M>& cy, con
     physics_step<T, M, FENE, TSF>(s, e, G, valid, kc, clamps, tsum);
 }
 
+// Noise map 2, for lanes of a multiple of four beads (the lane's first bead
+// is then a multiple of four too): the beads are taken in groups of four,
+// j = 4q + r, and the three blocks of counters (step, 3q + c, replica,
+// tag|group), c = 0, 1, 2, give four normals each; bead 4q + r takes normal r
+// of block c as its component c. Three blocks serve four bead-steps, as under
+// map 1, but with no carry from step to step. The step's Philox blocks are
+// drawn first (integer work with twelve independent chains at 16 beads per
+// lane) and each group's Box-Muller transform runs when the update reaches
+// the group's first bead, which spreads the transcendentals over the step
+// (measured on 16 beads per lane: 2% faster than transforming all twelve
+// blocks up front, 4% faster than drawing and transforming each group at its
+// first bead).
+template <typename T, int M, bool FENE, bool TSF = false>
+__device__ __forceinline__ void em_step_map2(Lane<T, M>& s, const GroupDev& G, const bool (&valid)[M],
+                                             const SlotCoef<T, M>& kc, uint32_t n, uint32_t bead0,
+                                             uint32_t replica, const RoundKeys& keys, int& clamps,
+                                             T* tsum = nullptr) {
+    static_assert(M % 4 == 0, "noise map 2 takes the beads of a lane in groups of four");
+    Words w[M / 4][3];
+#pragma unroll
+    for (int g = 0; g < M / 4; ++g) {
+        const uint32_t b = 3u * ((bead0 >> 2) + (uint32_t)g);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w[g][c] = philox10(n, b + (uint32_t)c, replica, G.stream, keys);
+    }
+    T gx[4], gy[4], gz[4];
+    physics_step_fn<T, M, FENE, TSF>(
+        s,
+        [&](int m, T& x, T& y, T& z) {
+            if ((m & 3) == 0) {
+                normals4(w[m >> 2][0], gx[0], gx[1], gx[2], gx[3]);
+                normals4(w[m >> 2][1], gy[0], gy[1], gy[2], gy[3]);
+                normals4(w[m >> 2][2], gz[0], gz[1], gz[2], gz[3]);
+            }
+            x = gx[m & 3];
+            y = gy[m & 3];
+            z = gz[m & 3];
+        },
+        G, valid, kc, clamps, tsum);
+}
+
 // Tension f_j = H g_j |Q_j| (Eq. 4, zero rest length) of every slot.
 template <typename T, int M, bool FENE>
 __device__ __forceinline__ void tensions(const Lane<T, M>& s, const GroupDev& G, T (&f)[M]) {

@@ -120,7 +120,11 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
         why = "tile_policy must be 0 (cost model), 1 (autotune) or 1000 + m (m beads per lane)";
         return RA_EINVAL;
     }
-    if (r->noise_map != 0 && r->noise_map != 1) { why = "noise_map must be 0 or 1"; return RA_EINVAL; }
+    if (r->noise_map < 0 || r->noise_map > 2) { why = "noise_map must be 0, 1 or 2"; return RA_EINVAL; }
+    if (r->noise_map == 2 && r->checkpoint_every != 0) {
+        why = "the adjoint (checkpoint_every != 0) takes noise map 0 or 1";
+        return RA_EINVAL;
+    }
     const int wpb = r->waves_per_block ? r->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4) { why = "waves_per_block must be 0, 1, 2 or 4"; return RA_EINVAL; }
     int n_pair = 0, n_hi = 0;
@@ -143,7 +147,7 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
         return RA_EINVAL;
     }
     if ((n_pair > 0 || n_hi > 0) && r->noise_map != 0) {
-        why = "noise_map 1 covers the free-draining Hookean and FENE chain model only";
+        why = "noise_map 1 and 2 cover the free-draining Hookean and FENE chain model only";
         return RA_EINVAL;
     }
     if ((n_pair > 0 || n_hi > 0) && r->plain) {
@@ -302,7 +306,9 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     }
     for (int i = 0; i < n_groups; ++i) {
         int forced = run->tile_policy > 1000 ? run->tile_policy - 1000 : 0;
-        Ms[i] = (pair || hi) ? 1 : choose_beads_per_lane(groups[i].n_beads, groups[i].n_replicas, family, forced);
+        Ms[i] = (pair || hi) ? 1
+                             : choose_beads_per_lane(groups[i].n_beads, groups[i].n_replicas, family, forced,
+                                                     run->noise_map);
     }
     if (run->tile_policy == 1 && !run->plain && !pair && !hi) {
         int wpb = run->waves_per_block;   // 0: the tuner chooses the workgroup size too
@@ -314,9 +320,14 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
         }
     }
     c->family = family;
-    if (run->noise_map != 0 && !run->plain && family != 4) {
+    if (run->noise_map == 1 && !run->plain && family != 4) {
         ra_destroy(c);
         return fail(nullptr, RA_EINVAL, "noise_map 1 needs at most 4 beads per lane (n_beads <= 256) on the fused path");
+    }
+    if (run->noise_map == 2 && !run->plain && family != 16) {
+        ra_destroy(c);
+        return fail(nullptr, RA_EINVAL, "noise_map 2 needs 8-16 beads per lane on the fused path: precision 32 and a "
+                                        "group with n_beads > 256");
     }
 
     for (int i = 0; i < n_groups; ++i) {

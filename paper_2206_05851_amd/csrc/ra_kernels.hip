@@ -158,6 +158,13 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
             run_steps_map1(n, len);
             return;
         }
+        if constexpr (NMAP == 2) {
+            for (int i = 0; i < len; ++i) {
+                em_step_map2<T, M, FENE, FUSED>(s, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps, tsum);
+                accumulate_tsf();
+            }
+            return;
+        }
         int i = 0;
         if constexpr (U > 1) {
             // software pipeline: the noise of block b+1 is generated in the same
@@ -242,8 +249,9 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
 // every iteration (measured: one extra vector load per step). Wider lanes keep
 // the reference, as the copy would not fit their register budget.
 // Noise map 1 is compiled for 1-4 beads per lane only (the host rejects it
-// for wider lanes, whose register budget has no room for the carry), in
-// kernels of its own, so each map gets its own register allocation.
+// for wider lanes, whose register budget has no room for the carry), noise
+// map 2 for 8, 12 and 16 beads per lane only, each in kernels of its own, so
+// each map gets its own register allocation.
 template <typename T, int M, bool FENE, bool UNIFORM_K, bool TSF, int NMAP>
 __device__ __forceinline__ void run_forward(const FwdArgs& a, const GroupDev& Gm, int k_first, int64_t n0_64) {
     const int gidx = (int)(&Gm - a.groups);
@@ -251,8 +259,8 @@ __device__ __forceinline__ void run_forward(const FwdArgs& a, const GroupDev& Gm
         const GroupDev G = Gm;
         run_forward_impl<T, M, FENE, UNIFORM_K, TSF, NMAP>(a, G, gidx, k_first, n0_64);
     } else {
-        static_assert(NMAP == 0, "noise map 1 is compiled for 1-4 beads per lane");
-        run_forward_impl<T, M, FENE, UNIFORM_K, TSF, 0>(a, Gm, gidx, k_first, n0_64);
+        static_assert(NMAP != 1, "noise map 1 is compiled for 1-4 beads per lane");
+        run_forward_impl<T, M, FENE, UNIFORM_K, TSF, NMAP>(a, Gm, gidx, k_first, n0_64);
     }
 }
 
@@ -306,6 +314,13 @@ __device__ __forceinline__ void fwd_item(const FwdArgs& a, int item) {
         case 2: dispatch_spring<T, 2, NMAP, TSFK>(a, G, it.k0, n0); break;
         case 3: dispatch_spring<T, 3, NMAP, TSFK>(a, G, it.k0, n0); break;
         case 4: dispatch_spring<T, 4, NMAP, TSFK>(a, G, it.k0, n0); break;
+        default: break;
+        }
+    } else if constexpr (NMAP == 2) {   // the host picks 8, 12 or 16 beads per lane under map 2
+        switch (G.M) {
+        case 8: dispatch_spring<T, 8, 2, TSFK>(a, G, it.k0, n0); break;
+        case 12: dispatch_spring<T, 12, 2, TSFK>(a, G, it.k0, n0); break;
+        case 16: dispatch_spring<T, 16, 2, TSFK>(a, G, it.k0, n0); break;
         default: break;
         }
     } else {
@@ -465,6 +480,16 @@ __global__ __launch_bounds__(256) void plain_step_kernel(const GroupDev* __restr
         normals4(philox10(n - 3u, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), a_, b_, c_, ex);
         normals4(philox10(n - 2u, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), a_, b_, c_, ey);
         normals4(philox10(n - 1u, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), a_, b_, c_, ez);
+    } else if (G.nmap == 2) {              // map 2: normal i mod 4 of the blocks 3 (i / 4) + c
+        const uint32_t b = 3u * ((uint32_t)i >> 2);
+        const int r = i & 3;
+        T v[4];
+        normals4(philox10(n, b, (uint32_t)k, G.stream, key0, key1), v[0], v[1], v[2], v[3]);
+        ex = r == 0 ? v[0] : r == 1 ? v[1] : r == 2 ? v[2] : v[3];
+        normals4(philox10(n, b + 1u, (uint32_t)k, G.stream, key0, key1), v[0], v[1], v[2], v[3]);
+        ey = r == 0 ? v[0] : r == 1 ? v[1] : r == 2 ? v[2] : v[3];
+        normals4(philox10(n, b + 2u, (uint32_t)k, G.stream, key0, key1), v[0], v[1], v[2], v[3]);
+        ez = r == 0 ? v[0] : r == 1 ? v[1] : r == 2 ? v[2] : v[3];
     } else {
         normals3(philox10(n, (uint32_t)i, (uint32_t)k, G.stream, key0, key1), ex, ey, ez);
     }
@@ -686,7 +711,8 @@ hipError_t launch_forward(const FwdArgs& a, int precision, int family, int waves
         if (nmap == 1) launch_fwd_tsf<float, 4, 1, 1>(a, grid, block, st);
         else launch_fwd_tsf<float, 4, 1, 0>(a, grid, block, st);
     } else {
-        launch_fwd_tsf<float, 16, FAMILY16_WAVES, 0>(a, grid, block, st);
+        if (nmap == 2) launch_fwd_tsf<float, 16, FAMILY16_WAVES, 2>(a, grid, block, st);
+        else launch_fwd_tsf<float, 16, FAMILY16_WAVES, 0>(a, grid, block, st);
     }
     return hipGetLastError();
 }
@@ -705,7 +731,8 @@ hipError_t launch_forward_dual(const FwdArgs& a, const FwdArgs& b, int precision
         if (nmap == 1) hipLaunchKernelGGL((fwd_dual_kernel<float, 4, 1, 1>), grid, block, 0, st, a, b, ba);
         else hipLaunchKernelGGL((fwd_dual_kernel<float, 4, 1>), grid, block, 0, st, a, b, ba);
     } else {
-        hipLaunchKernelGGL((fwd_dual_kernel<float, 16, FAMILY16_WAVES>), grid, block, 0, st, a, b, ba);
+        if (nmap == 2) hipLaunchKernelGGL((fwd_dual_kernel<float, 16, FAMILY16_WAVES, 2>), grid, block, 0, st, a, b, ba);
+        else hipLaunchKernelGGL((fwd_dual_kernel<float, 16, FAMILY16_WAVES>), grid, block, 0, st, a, b, ba);
     }
     return hipGetLastError();
 }

@@ -113,10 +113,12 @@ extern "C" ra_status ra_run_static(const ra_chain_desc* group, const ra_run_desc
     if (W > 65535) return fail_static(RA_EINVAL, "ra_run_static: more than 65535 windows");
 
     const int family = (d.n_beads > 4 * WAVE && run->precision == 32) ? 16 : 4;
-    if (run->noise_map != 0 && family != 4)
+    if (run->noise_map == 1 && family != 4)
         return fail_static(RA_EINVAL, "ra_run_static: noise_map 1 needs n_beads <= 256");
+    if (run->noise_map == 2 && family != 16)
+        return fail_static(RA_EINVAL, "ra_run_static: noise_map 2 needs n_beads > 256 at precision 32");
     const int forced = run->tile_policy > 1000 ? run->tile_policy - 1000 : 0;
-    const int M = choose_beads_per_lane(d.n_beads, d.n_replicas, family, forced);
+    const int M = choose_beads_per_lane(d.n_beads, d.n_replicas, family, forced, run->noise_map);
     GroupDev G = make_group(d, M, 0, run->noise_map);
     const int64_t nm1 = d.n_beads - 1;
     G.state_off = 0;

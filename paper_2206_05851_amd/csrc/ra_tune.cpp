@@ -21,15 +21,17 @@ const std::vector<int>& family_beads_per_lane(int family) {
 
 static bool legal(int n_beads, int M) { return (n_beads + M - 1) / M <= 64; }
 
-int choose_beads_per_lane(int n_beads, int n_replicas, int family, int forced) {
+bool map_allows(int nmap, int M) { return nmap != 2 || M % 4 == 0; }
+
+int choose_beads_per_lane(int n_beads, int n_replicas, int family, int forced, int nmap) {
     const auto& cand = family_beads_per_lane(family);
-    if (forced > 0 && legal(n_beads, forced))
+    if (forced > 0 && legal(n_beads, forced) && map_allows(nmap, forced))
         for (int m : cand)
             if (m == forced) return m;
     int best = -1;
     long long best_cost = 0;
     for (int M : cand) {
-        if (!legal(n_beads, M)) continue;
+        if (!legal(n_beads, M) || !map_allows(nmap, M)) continue;
         const int L = (n_beads + M - 1) / M;
         const int P = 64 / L;
         const long long cost = (long long)M * ((n_replicas + P - 1) / P);
@@ -174,7 +176,7 @@ ra_status autotune_tiles(const std::vector<ra_chain_desc>& descs, const ra_run_d
             if (it == table.end()) {
                 Entry best{Ms[i], -1.0};
                 for (int M : family_beads_per_lane(family)) {
-                    if (!legal(d.n_beads, M)) continue;
+                    if (!legal(d.n_beads, M) || !map_allows(run.noise_map, M)) continue;
                     const double ms = time_tile(d, run, M, wpb, stream);
                     if (ms < 0) { why = "timing run failed"; return RA_EDEVICE; }
                     if (best.ms_per_replica < 0 || ms < best.ms_per_replica) best = Entry{M, ms};

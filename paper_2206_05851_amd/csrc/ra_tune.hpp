@@ -15,8 +15,10 @@ const std::vector<int>& family_beads_per_lane(int family);
 // Cost model: a wavefront of P = floor(64 / ceil(N/M)) replicas costs M lane
 // slots per bead-step, so a group costs M * ceil(R/P); the cheapest legal M
 // wins, ties going to the smaller M (more wavefronts in flight). `forced`
-// (> 0) is used when it is legal for N.
-int choose_beads_per_lane(int n_beads, int n_replicas, int family, int forced);
+// (> 0) is used when it is legal for N and the noise map. Noise map 2 takes
+// only multiples of four (map_allows).
+bool map_allows(int nmap, int M);
+int choose_beads_per_lane(int n_beads, int n_replicas, int family, int forced, int nmap);
 
 // Times every legal M for each distinct (N, spring) of the batch with a short
 // run of the fused kernel that fills every SIMD four times and keeps the

@@ -90,7 +90,11 @@ def _create(lib, desc_kw, run_kw):
     (dict(hi_radius=0.5, n_beads=65), {}, "n_beads"),
     (dict(hi_radius=0.5), dict(checkpoint_every=10), "adjoint"),
     (dict(hi_radius=0.5), dict(plain=1), "plain"),
+    ({}, dict(noise_map=3), "noise_map"),
+    ({}, dict(noise_map=-1), "noise_map"),
     ({}, dict(noise_map=2), "noise_map"),
+    (dict(n_beads=300), dict(noise_map=2, checkpoint_every=10), "adjoint"),
+    (dict(spring=2, rest_length=2.0), dict(noise_map=2), "noise_map"),
     (dict(n_beads=300), dict(noise_map=1), "noise_map"),
     (dict(spring=2, rest_length=2.0), dict(noise_map=1), "noise_map"),
     (dict(hi_radius=0.5), dict(noise_map=1), "noise_map"),
@@ -159,6 +163,7 @@ def test_static_run_rejections_on_host(lib):
         (dict(spring=2, rest_length=2.0), {}, 10, "chain model"),
         (dict(hi_radius=0.5), {}, 10, "chain model"),
         (dict(n_beads=300), dict(noise_map=1), 10, "noise_map"),
+        ({}, dict(noise_map=2), 10, "noise_map"),
         (dict(n_beads=1), {}, 10, "n_beads"),
     ]
     for desc_kw, run_kw, n, frag in cases:

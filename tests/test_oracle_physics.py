@@ -99,7 +99,8 @@ def test_centre_of_mass_moves_with_flow_only():
 
 # ---- stochastic Hookean dynamics: exact EM moments -------------------------------
 @pytest.mark.parametrize("flow,rate,noise_map", [(ora.UNIAXIAL, 0.5, 0), (ora.SHEAR, 4.0, 0),
-                                                (ora.UNIAXIAL, 0.5, 1), (ora.SHEAR, 4.0, 1)])
+                                                (ora.UNIAXIAL, 0.5, 1), (ora.SHEAR, 4.0, 1),
+                                                (ora.UNIAXIAL, 0.5, 2), (ora.SHEAR, 4.0, 2)])
 def test_hookean_moments_match_exact_em_recursion(flow, rate, noise_map):
     # the exact recursion holds only for independent standard normals at
     # every (step, bead, component): both noise maps must give them

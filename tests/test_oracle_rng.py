@@ -187,6 +187,61 @@ def test_noise_map_one_definition():
         assert np.isclose(four[3], ref[0], rtol=1e-13, atol=1e-13)
 
 
+def _four_normals_py(words):
+    # Box-Muller of both pairs, from the word map written out with math
+    import math
+    u = [((w >> 9) + 0.5) * 2.0 ** -23 for w in words]
+    r0 = math.sqrt(-2.0 * math.log(u[0]))
+    r1 = math.sqrt(-2.0 * math.log(u[2]))
+    return [r0 * math.cos(2.0 * math.pi * u[1]), r0 * math.sin(2.0 * math.pi * u[1]),
+            r1 * math.cos(2.0 * math.pi * u[3]), r1 * math.sin(2.0 * math.pi * u[3])]
+
+
+def test_noise_map_two_definition():
+    # map 2: bead 4q + r takes normal r of the blocks with bead word 3q + c as
+    # its component c; the step word is the step itself (no carry over steps)
+    seed = 0x0F1E2D3C4B5A6978
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    rng = np.random.default_rng(8)
+    for _ in range(200):
+        step = int(rng.integers(0, 2 ** 32))
+        q, r = int(rng.integers(0, 256)), int(rng.integers(0, 4))
+        rep, grp = (int(v) for v in rng.integers(0, 1000, size=2))
+        tag = int(rng.integers(0, 2))
+        got = ora.noise(seed, step, 4 * q + r, rep, tag, grp, noise_map=2)
+        ref = [_four_normals_py(philox_py((step, 3 * q + c, rep, (tag << 24) | grp), key))[r] for c in range(3)]
+        assert np.allclose(got, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_noise_map_two_uses_each_normal_once():
+    # the 12 normals of a group's three blocks go to 12 distinct (bead, component)
+    # slots, and neighbouring groups draw from disjoint blocks: over a chain of
+    # 40 beads every normal of blocks 0..29 is used exactly once
+    seed, step, rep, tag, grp = 77, 5, 9, 0, 3
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    pool = np.array([_four_normals_py(philox_py((step, b, rep, (tag << 24) | grp), key)) for b in range(30)])
+    used = np.array([ora.noise(seed, step, j, rep, tag, grp, noise_map=2) for j in range(40)])
+    assert np.allclose(np.sort(used.ravel()), np.sort(pool.ravel()), rtol=1e-13, atol=1e-13)
+    assert len(np.unique(np.round(used.ravel(), 12))) == 120
+
+
+def test_noise_map_two_is_standard_and_uncorrelated():
+    xs = np.array([ora.noise(13, step, bead, 2, 0, 1, noise_map=2) for step in range(300) for bead in range(40)])
+    for a in range(3):
+        col = xs[:, a]
+        assert stats.kstest(col, "norm").pvalue > 1e-4
+        assert abs(col.mean()) < 5 / np.sqrt(len(col))
+        assert abs(col.var() - 1.0) < 5 * np.sqrt(2.0 / len(col))
+    c = np.corrcoef(xs.T)
+    assert np.max(np.abs(c - np.eye(3))) < 5 / np.sqrt(len(xs))
+    # beads 4q and 4q + 1 share their radii (one Box-Muller pair per block and
+    # component): their normals are still uncorrelated
+    x = xs.reshape(300, 40, 3)
+    a, b = x[:, 0::4, :].ravel(), x[:, 1::4, :].ravel()
+    assert abs(np.corrcoef(a, b)[0, 1]) < 5 / np.sqrt(len(a))
+    assert abs(np.corrcoef(a ** 2, b ** 2)[0, 1]) < 5 / np.sqrt(len(a))
+
+
 def test_fourth_normals_are_standard_and_independent_of_the_third():
     # (r1 cos 2 pi u3, r1 sin 2 pi u3) is a Box-Muller pair: both N(0,1),
     # uncorrelated, and their squares sum to r1^2 ~ Exp(mean 2)

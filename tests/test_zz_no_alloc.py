@@ -52,6 +52,24 @@ def test_static_run_equals_context_path_two_calls(noise_map):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_static_run_noise_map_two_two_calls():
+    # noise map 2 on the wide-lane kernels: a 1000-bead chain, then a smaller
+    # 300-bead one; both equal the context path
+    w = wl.group(1000, 16, 5e-5, wl.FENE, 1.0, 400.0, wl.UNIAXIAL, wl.wi_to_rate(10.0, 1000), stream_id=1)
+    pw = wl.equilibrium_parent(1000, wl.FENE, 1.0, 400.0, seed=105)
+    s = wl.group(300, 24, 5e-5, wl.FENE, 1.0, 150.0, wl.SHEAR, 20.0, stream_id=2)
+    ps = wl.equilibrium_parent(300, wl.FENE, 1.0, 150.0, seed=9)
+    announce("static run, noise map 2: call 1 N=1000 R=16 1000 steps")
+    a = _static(w, pw, 3, 1000, 500, noise_map=2)
+    announce("static run, noise map 2: call 2 N=300 R=24 200 steps")
+    b = _static(s, ps, 6, 200, 100, noise_map=2)
+    ca = _context(w, pw, 3, 1000, 500, noise_map=2)
+    cb = _context(s, ps, 6, 200, 100, noise_map=2)
+    for x, y in ((a, ca), (b, cb)):
+        assert np.all(np.isfinite(x[0])) and np.all(x[1] > 0)
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
 def test_static_run_fp64_wide_lanes_and_errors():
     import torch
     from paper_2206_05851_amd import ra
