@@ -69,9 +69,12 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
     // sum of at most 512 terms (and the one cancelled term) carries a relative
     // error of a few hundred ulp at most (below 3.1e-5).
     constexpr int TSF_FLUSH = 512;
-    // 6-16 beads per lane keep the separate tension pass after each step: their
-    // register budget (two wavefronts per SIMD) has no room for the fused sums
-    constexpr bool FUSED = TSF && M <= 4;
+    // 6-16 beads per lane under noise map 0 keep the separate tension pass after
+    // each step: their register budget (two wavefronts per SIMD) has no room for
+    // the fused sums beside sixteen Philox chains. Under map 2 (twelve chains)
+    // the fused sums fit; the spills they cause sit outside the step loop, and
+    // the 16-bead kernel is 4% faster than with the separate pass.
+    constexpr bool FUSED = TSF && (M <= 4 || NMAP == 2);
     T tpart[M];
     T* const tsum = FUSED ? tpart : nullptr;
 #pragma unroll
