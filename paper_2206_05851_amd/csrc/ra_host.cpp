@@ -258,6 +258,13 @@ void ra_destroy(ra_ctx* c) {
 
 ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups, const ra_run_desc* run,
                     void* hip_stream) {
+    return ra::create_context(out, groups, n_groups, run, hip_stream, 0);
+}
+
+}  // extern "C"
+
+ra_status ra::create_context(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups, const ra_run_desc* run,
+                             void* hip_stream, int force_family) {
     if (!out) return fail(nullptr, RA_EINVAL, "out is null");
     *out = nullptr;
     std::string why;
@@ -281,6 +288,7 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     for (int i = 0; i < n_groups; ++i)
         if (groups[i].n_beads > 4 * WAVE) family = 16;
     if (run->precision == 64 && !run->plain) family = 4;   // the plain path only uses the tile for its work list
+    if (force_family == 16 && run->precision == 32 && !run->plain) family = 16;   // a tuner probe of a batch's group
     const bool pair = is_pair_group(groups[0]);   // validated: all groups or none
     const bool hi = is_hi_group(groups[0]);
     if (pair) family = 2;
@@ -481,6 +489,8 @@ ra_status ra_create(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups,
     *out = c;
     return RA_OK;
 }
+
+extern "C" {
 
 ra_status ra_init_chains(ra_ctx* c, const double* parent_xyz) {
     if (!c) return fail(nullptr, RA_EINVAL, "null context");

@@ -18,6 +18,12 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
 GroupDev make_group(const ra_chain_desc& d, int M, int tag, int nmap);
 // Text returned by ra_last_error(NULL) on this thread.
 void set_global_error(const std::string& msg);
+// ra_create, with force_family = 16 selecting the 6-16 beads-per-lane kernels
+// (FP32 fused path) even when every chain has at most 256 beads; 0 chooses as
+// ra_create does. The autotuner times one group of a wide-lane batch this way,
+// so the probe runs the kernels the batch will run.
+ra_status create_context(ra_ctx** out, const ra_chain_desc* groups, int32_t n_groups, const ra_run_desc* run,
+                         void* hip_stream, int force_family);
 
 struct FwdArgs {
     const GroupDev* groups;

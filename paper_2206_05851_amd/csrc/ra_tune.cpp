@@ -2,6 +2,8 @@
 // the launch's wavefronts per workgroup.
 #include "ra_tune.hpp"
 
+#include "ra_launch.hpp"
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -92,11 +94,12 @@ void append_cache_file(const std::string& path, const Key& k, const Entry& e) {
     f << buf;
 }
 
-// Time 96 fused steps of one group with a forced tile M and enough replicas
+// Time 96 fused steps of one group with a forced tile M of the batch's kernel
+// family (a short chain in a wide-lane batch runs the wide-lane kernels) and enough replicas
 // to give every SIMD TUNE_WAVES_PER_SIMD wavefronts of that packing, so the
 // candidates are ranked by throughput (as in a saturated batch), not by the
 // latency of a few wavefronts. Returns ms per replica, or -1.
-double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int M, int wpb, hipStream_t st) {
+double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int family, int M, int wpb, hipStream_t st) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
@@ -114,7 +117,7 @@ double time_tile(const ra_chain_desc& d, const ra_run_desc& run, int M, int wpb,
     r.waves_per_block = wpb;
     r.noise_map = run.noise_map;
     ra_ctx* ctx = nullptr;
-    if (ra_create(&ctx, &g, 1, &r, st) != RA_OK) return -1.0;
+    if (create_context(&ctx, &g, 1, &r, st, family) != RA_OK) return -1.0;
     // straight parent along x; its bonds stay inside the FENE extension
     // (half of Q0 = sqrt(b kT/H), at most 0.5), so the timed kernel does the
     // work of a valid chain
@@ -177,7 +180,7 @@ ra_status autotune_tiles(const std::vector<ra_chain_desc>& descs, const ra_run_d
                 Entry best{Ms[i], -1.0};
                 for (int M : family_beads_per_lane(family)) {
                     if (!legal(d.n_beads, M) || !map_allows(run.noise_map, M)) continue;
-                    const double ms = time_tile(d, run, M, wpb, stream);
+                    const double ms = time_tile(d, run, family, M, wpb, stream);
                     if (ms < 0) { why = "timing run failed"; return RA_EDEVICE; }
                     if (best.ms_per_replica < 0 || ms < best.ms_per_replica) best = Entry{M, ms};
                 }

@@ -163,3 +163,26 @@ def test_map2_plain_path_matches_oracle(precision, tol):
         rep.sync_status()
         o = run_oracle([g], [parent], 5, 100, 50, noise_map=2)
         assert rel_err(smp, o.samples()[0]) < tol
+
+
+def test_map2_autotuner_picks_whole_groups(tmp_path, monkeypatch):
+    # tile_policy 1 under map 2 times only 8, 12 and 16 beads per lane (whole
+    # groups of four), the short chain too, on the batch's wide-lane kernels;
+    # whatever it picks, the results are the cost model's bits
+    import torch
+    monkeypatch.setenv("RA_AUTOTUNE_CACHE", str(tmp_path / "t.jsonl"))
+    gs = [wl.group(300, 8, 5e-5, wl.FENE, 1.0, 150.0, wl.SHEAR, 20.0, stream_id=1),
+          wl.group(700, 3, 5e-5, wl.FENE, 1.0, 300.0, wl.UNIAXIAL, wl.wi_to_rate(5.0, 700), stream_id=2),
+          wl.group(40, 20, 1e-4, wl.HOOKEAN, 1.0, 0.0, wl.PLANAR, 0.3, stream_id=3)]
+    ps = [wl.equilibrium_parent(g["n_beads"], g["spring"], g["H"], g["b"], seed=60 + i) for i, g in enumerate(gs)]
+    announce("noise map 2 autotuner")
+    tuned = run_gpu(gs, ps, 8, 100, 50, tile_policy=1, noise_map=2)
+    cost = run_gpu(gs, ps, 8, 100, 50, noise_map=2)
+    assert all(m in (8, 12, 16) for m in tuned.tile_info()[0])
+    for x, y in zip(tuned.samples(), cost.samples()):
+        assert bool(torch.equal(x, y))
+    tuned.sync_status()
+    cost.sync_status()
+    lines = (tmp_path / "t.jsonl").read_text().splitlines()
+    assert len(lines) == 9                        # 3 lengths x 3 workgroup sizes
+    assert all('"noise_map": 2' in ln and '"family": 16' in ln for ln in lines)
