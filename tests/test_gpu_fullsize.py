@@ -113,18 +113,21 @@ def test_batched512_full_size(noise_map):
     check_profile_is_reduction(mean.cpu().numpy(), std.cpu().numpy(), smp)
 
 
-def test_large1000_full_size():
+@pytest.mark.parametrize("noise_map", [0, 2])
+def test_large1000_full_size(noise_map):
+    # the headline's launch (16 beads per lane, TSF; bench.py times noise map 2)
     groups, parents, run = wl.large1000()
     steps, S = run["steps"], run["sample_every"]
-    announce("large1000 full: R=8192 N=1000 %d steps, TSF" % steps)
-    rep = run_gpu(groups, parents, run["seed"], steps, S, tsf=True)
+    announce("large1000 full: R=8192 N=1000 %d steps, TSF, noise map %d" % (steps, noise_map))
+    rep = run_gpu(groups, parents, run["seed"], steps, S, tsf=True, noise_map=noise_map)
+    assert rep.tile_info() == ([16], [1])
     mean, std, tm, ts = rep.average_forces(tsf=True)
     rates, rsum, ev = rep.bell_rates(mean, run["k0"], run["x_dagger"], events=True)
     smp, tsmp = rep.samples(tsf=True)
     smp = smp[0][:, [0, 8191]].cpu().numpy()
     tsmp = tsmp[0][:, [0, 8191]].cpu().numpy()
     rep.sync_status()
-    ref = oracle_replicas(groups, parents, run["seed"], steps, S, [(0, 0), (0, 8191)], tsf=True)
+    ref = oracle_replicas(groups, parents, run["seed"], steps, S, [(0, 0), (0, 8191)], tsf=True, noise_map=noise_map)
     for i, k in enumerate((0, 8191)):
         s, t = ref[(0, k)]
         e1 = rel_err(smp[:, i], s)
