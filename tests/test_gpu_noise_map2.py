@@ -57,13 +57,15 @@ def test_map2_tiles_bitwise_equal_and_match_oracle():
     rep0.sync_status()
 
 
-@pytest.mark.parametrize("N,M", [(1000, 16), (1024, 16), (512, 8)])
-def test_map2_long_chains_match_oracle(N, M):
+@pytest.mark.parametrize("N,M,R", [(1000, 16, 6), (1024, 16, 6), (512, 8, 6), (257, 12, 1), (257, 8, 3)])
+def test_map2_long_chains_match_oracle(N, M, R):
     # the headline's chain length, the longest chain of the family (all 64
-    # lanes full) and the longest at 8 beads per lane
-    g = wl.group(N, 6, 5e-5, wl.FENE, 1.0, 400.0, wl.UNIAXIAL, wl.wi_to_rate(10.0, N), stream_id=2)
+    # lanes full), the longest at 8 beads per lane, and the shortest chain
+    # the wide-lane family takes (one bead in its last group of four), with a
+    # single replica and with three packed into one wavefront
+    g = wl.group(N, R, 5e-5, wl.FENE, 1.0, 400.0, wl.UNIAXIAL, wl.wi_to_rate(10.0, N), stream_id=2)
     parent = wl.equilibrium_parent(N, wl.FENE, 1.0, 400.0, seed=N + 1)
-    announce("noise map 2 N=%d M=%d R=6 200 steps" % (N, M))
+    announce("noise map 2 N=%d M=%d R=%d 200 steps" % (N, M, R))
     rep = run_gpu([g], [parent], 4, 200, 100, noise_map=2, tile_policy=1000 + M)
     assert rep.tile_info()[0] == [M]
     mean, std = rep.average_forces()
@@ -71,7 +73,12 @@ def test_map2_long_chains_match_oracle(N, M):
     rep.sync_status()
     o = run_oracle([g], [parent], 4, 200, 100, noise_map=2)
     rm, rs = o.average_forces()
-    e = (rel_err(smp, o.samples()[0]), rel_err(mean.cpu().numpy(), rm), rel_err(std.cpu().numpy(), rs))
+    if R == 1:   # one replica: no spread on either side
+        assert np.all(std.cpu().numpy() == 0) and np.all(rs == 0)
+        rs_err = 0.0
+    else:
+        rs_err = rel_err(std.cpu().numpy(), rs)
+    e = (rel_err(smp, o.samples()[0]), rel_err(mean.cpu().numpy(), rm), rs_err)
     announce("N=%d rel err samples %.2e mean %.2e std %.2e" % ((N,) + e))
     assert max(e) < TOL32
 
