@@ -603,8 +603,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="plain,fene50,adjoint,batched,rsf50,sigma_sweep,collapsed50,hi50,"
-                                      "oracle_rates",
+    ap.add_argument("--extras", default="other_map,plain,fene50,adjoint,batched,rsf50,sigma_sweep,collapsed50,"
+                                      "hi50,oracle_rates",
                     help="comma-separated extra workloads to measure")
     ap.add_argument("--cpu-single-replicas", type=int, default=2,
                     help="oracle replicas on one thread (all 2 x 10^4 steps)")
@@ -726,6 +726,39 @@ def main():
             % (acc["samples"], acc["samples_first"], acc["profile"], tacc["samples"]))
 
     extras = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
+    if "other_map" in extras:
+        # the same headline pass under the other noise map the wide lanes take
+        # (three timed passes after one warm-up), for comparison
+        om = 0 if head_map == 2 else 2
+        rep_o = ra.Replicas(groups, run["seed"], precision=32, sample_every=S, max_windows=W, tsf=True,
+                            device=dev, noise_map=om)
+        timer_o = EventTimer(torch.cuda.current_stream())
+
+        def pass_o(record):
+            rep_o.init_chains(parent)
+            if record:
+                timer_o.run(lambda: rep_o.step(T))
+            else:
+                rep_o.step(T)
+            m, s, tm, ts = rep_o.average_forces(tsf=True)
+            return rep_o.bell_rates(m, run["k0"], run["x_dagger"], events=True)
+
+        pass_o(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            pass_o(True)
+        torch.cuda.synchronize()
+        to = (time.perf_counter() - t0) / 3
+        rep_o.sync_status()
+        kms_o = timer_o.mean_ms()
+        out["headline_other_noise_map"] = {
+            "noise_map": om, "ms_per_step": 1e3 * to, "kernel_ms": kms_o, "value": work_per_step / to,
+            "lane_slots_per_replica_bead_step": SLOTS_PER_BEAD_STEP[om],
+            "roofline_frac": roofline_frac(SLOTS_PER_BEAD_STEP[om], work_per_step, kms_o * 1e-3),
+            "note": "the headline pass under the other noise map of the 16-beads-per-lane kernels, 3 timed passes"}
+        rep_o.close()
+        log("large1000 under noise map %d: %.1f ms per pass, kernel %.1f ms" % (om, 1e3 * to, kms_o))
     if "plain" in extras:
         # plain unbatched path on the headline: a 2000-step prefix (4 windows),
         # timed after a warm-up, extrapolated to the 2x10^4 steps
