@@ -75,13 +75,14 @@ VALU_PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
 SLOTS_PER_BEAD_STEP = {0: 40 + 8 + 5 + 31, 1: 30 + 6 + 4.5 + 31, 2: 30 + 6 + 4.5 + 31}
 # HBM bytes per launch of the headline's forward kernel, read with rocprofv3
 # counters (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, both factors from a 1 GiB
-# device copy in the same runs). Valid only for the kernel sources they were
-# taken on: the digest of those sources is recorded with the figure, and
-# traffic is reported as null when the sources have changed since.
-FWD_TRAFFIC = {"sha256": "045c5654a2ee4e11f7c9933544659166dd8ea4cc52e1ea01166fbfe5e309fa18", "noise_map": 2,
-               "bytes": (48783.375 * 2.0 + 2655981.344) * 1024}
-FWD_SOURCES = ("ra_kernels.hip", "ra_chain.hpp", "ra_device.hpp", "ra_types.hpp", "ra_launch.hpp",
-               "ra_host.cpp", "ra_tune.cpp", "ra_tune.hpp")
+# device copy in the same runs). Valid only for the kernel they were taken on:
+# the digest of the kernel's sources (device code and its argument block), the
+# launch tile (beads per lane, replicas per wavefront, kernel family) and the
+# noise map are recorded with the figure, and traffic is reported as null when
+# any of them differs.
+FWD_TRAFFIC = {"sha256": "0fa2f8f9f0803c1f59de859579778bddcf5df2164d66974a03d7f2e8030197b7", "noise_map": 2,
+               "tile": (16, 1, 16), "bytes": (48783.375 * 2.0 + 2655981.344) * 1024}
+FWD_SOURCES = ("ra_kernels.hip", "ra_chain.hpp", "ra_device.hpp", "ra_types.hpp", "ra_launch.hpp")
 
 
 def fwd_sources_digest(files=FWD_SOURCES):
@@ -676,7 +677,8 @@ def main():
     tiles = rep.tile_info()
     family = rep.kernel_family()
     traffic = (FWD_TRAFFIC["bytes"] if FWD_TRAFFIC["sha256"] and fwd_sources_digest() == FWD_TRAFFIC["sha256"]
-               and FWD_TRAFFIC.get("noise_map") == head_map else None)
+               and FWD_TRAFFIC.get("noise_map") == head_map
+               and FWD_TRAFFIC.get("tile") == (tiles[0][0], tiles[1][0], family) else None)
     out = {
         "metric": METRIC, "value": value, "unit": "replica·bead·steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,

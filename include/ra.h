@@ -131,7 +131,7 @@ typedef struct {
                                    takes normal r of the blocks with bead word 3q + c as
                                    its component c (three blocks per four beads). Chain
                                    model only, fused path with 8-16 beads per lane (FP32,
-                                   a group with N > 256) or the plain path; no adjoint */
+                                   a group with N > 256) or the plain path */
 } ra_run_desc;
 
 /* Create a context: validates every descriptor (RA_EINVAL with nothing

@@ -218,6 +218,9 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
             init_carry<float, M>(cy, G, (uint32_t)(n_end - 1), (uint32_t)tg.j0, (uint32_t)tg.k, keys);
             em_step_map1<float, M, FENE>(s, cy, G, valid, kc, (uint32_t)(n_end - 1), (uint32_t)tg.j0, (uint32_t)tg.k,
                                          keys, dummy);
+        } else if constexpr (NMAP == 2) {
+            em_step_map2<float, M, FENE>(s, G, valid, kc, (uint32_t)(n_end - 1), (uint32_t)tg.j0, (uint32_t)tg.k, keys,
+                                         dummy);
         } else {
             em_step<float, M, FENE>(s, G, valid, kc, (uint32_t)(n_end - 1), (uint32_t)tg.j0, (uint32_t)tg.k, keys,
                                     dummy);
@@ -260,6 +263,13 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
                 seg_store<M>(wp, 0, s, lane);
                 wp += STRIDE;
                 em_step_map1<float, M, FENE>(s, cy, G, valid, kc, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, keys,
+                                             dummy);
+            }
+        } else if constexpr (NMAP == 2) {
+            for (int n = s0; n < s1; ++n) {
+                seg_store<M>(wp, 0, s, lane);
+                wp += STRIDE;
+                em_step_map2<float, M, FENE>(s, G, valid, kc, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, keys,
                                              dummy);
             }
         } else {
@@ -322,9 +332,9 @@ void adjoint_kernel(AdjArgs a, int item_begin, int item_end) {
         if (Gl.spring == 1) run_adjoint<M, true, NMAP>(a, Gl, item, it.k0);
         else run_adjoint<M, false, NMAP>(a, Gl, item, it.k0);
     } else {   // noise map 1 is not compiled for wider lanes (rejected on the host)
-        static_assert(NMAP == 0, "noise map 1 is compiled for 1-4 beads per lane");
-        if (G.spring == 1) run_adjoint<M, true, 0>(a, G, item, it.k0);
-        else run_adjoint<M, false, 0>(a, G, item, it.k0);
+        static_assert(NMAP != 1, "noise map 1 is compiled for 1-4 beads per lane");
+        if (G.spring == 1) run_adjoint<M, true, NMAP>(a, G, item, it.k0);
+        else run_adjoint<M, false, NMAP>(a, G, item, it.k0);
     }
 }
 
@@ -389,6 +399,15 @@ hipError_t launch_adjoint(const AdjArgs& a, int M, int item_begin, int item_end,
         case 2: hipLaunchKernelGGL((adjoint_kernel<2, 1>), grid, block, 0, st, a, item_begin, item_end); break;
         case 3: hipLaunchKernelGGL((adjoint_kernel<3, 1>), grid, block, 0, st, a, item_begin, item_end); break;
         case 4: hipLaunchKernelGGL((adjoint_kernel<4, 1>), grid, block, 0, st, a, item_begin, item_end); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (nmap == 2) {   // whole groups of four beads per lane: 8, 12 or 16
+        switch (M) {
+        case 8: hipLaunchKernelGGL((adjoint_kernel<8, 2>), grid, block, 0, st, a, item_begin, item_end); break;
+        case 12: hipLaunchKernelGGL((adjoint_kernel<12, 2>), grid, block, 0, st, a, item_begin, item_end); break;
+        case 16: hipLaunchKernelGGL((adjoint_kernel<16, 2>), grid, block, 0, st, a, item_begin, item_end); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

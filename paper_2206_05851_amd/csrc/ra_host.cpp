@@ -121,10 +121,6 @@ ra_status validate(const ra_chain_desc* g, int32_t n, const ra_run_desc* r, std:
         return RA_EINVAL;
     }
     if (r->noise_map < 0 || r->noise_map > 2) { why = "noise_map must be 0, 1 or 2"; return RA_EINVAL; }
-    if (r->noise_map == 2 && r->checkpoint_every != 0) {
-        why = "the adjoint (checkpoint_every != 0) takes noise map 0 or 1";
-        return RA_EINVAL;
-    }
     const int wpb = r->waves_per_block ? r->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4) { why = "waves_per_block must be 0, 1, 2 or 4"; return RA_EINVAL; }
     int n_pair = 0, n_hi = 0;

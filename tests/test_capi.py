@@ -93,7 +93,7 @@ def _create(lib, desc_kw, run_kw):
     ({}, dict(noise_map=3), "noise_map"),
     ({}, dict(noise_map=-1), "noise_map"),
     ({}, dict(noise_map=2), "noise_map"),
-    (dict(n_beads=300), dict(noise_map=2, checkpoint_every=10), "adjoint"),
+    (dict(n_beads=300), dict(noise_map=2, checkpoint_every=10, precision=64), "adjoint"),
     (dict(spring=2, rest_length=2.0), dict(noise_map=2), "noise_map"),
     (dict(n_beads=300), dict(noise_map=1), "noise_map"),
     (dict(spring=2, rest_length=2.0), dict(noise_map=1), "noise_map"),

@@ -193,3 +193,30 @@ def test_map2_autotuner_picks_whole_groups(tmp_path, monkeypatch):
     lines = (tmp_path / "t.jsonl").read_text().splitlines()
     assert len(lines) == 9                        # 3 lengths x 3 workgroup sizes
     assert all('"noise_map": 2' in ln and '"family": 16' in ln for ln in lines)
+
+
+@pytest.mark.parametrize("M,K", [(16, 50), (12, 7), (8, -1)])
+def test_map2_adjoint_matches_oracle_tangents(M, K):
+    # the adjoint's segment recompute under map 2 on every wide tile; K = 7
+    # starts segments mid-window, K = -1 keeps every state (no recompute)
+    import torch
+    N, R, steps, S = 300, 24, 200, 50
+    g = wl.group(N, R, 5e-5, wl.FENE, 1.3, 120.0, wl.UNIAXIAL, wl.wi_to_rate(3.0, N), stream_id=3)
+    parent = wl.equilibrium_parent(N, wl.FENE, 1.3, 120.0, seed=33)
+    rng = np.random.default_rng(M)
+    W = steps // S
+    gm = rng.normal(size=(W, N - 1))
+    gr = rng.normal(size=(W, N - 1)) * 1e5
+    announce("noise map 2 adjoint N=%d M=%d K=%d" % (N, M, K))
+    rep = run_gpu([g], [parent], 11, steps, S, checkpoint_every=K, max_steps=steps, noise_map=2,
+                  tile_policy=1000 + M)
+    assert rep.tile_info()[0] == [M]
+    mean, _ = rep.average_forces()
+    g_gpu = rep.backward(mean, torch.from_numpy(gm).cuda(), torch.from_numpy(gr).cuda(), 1e-6, 0.1).cpu().numpy()
+    rep.sync_status()
+    o = run_oracle([g], [parent], 11, steps, S, tangents=True, noise_map=2)
+    g_ref = o.backward(gm, gr, 1e-6, 0.1)
+    scale = np.maximum(np.abs(g_ref), 1e-3 * np.max(np.abs(g_ref)))
+    err = np.max(np.abs(g_gpu - g_ref) / scale)
+    announce("noise map 2 adjoint max rel err %.2e" % err)
+    assert err < 1e-4, (g_gpu, g_ref)
