@@ -80,8 +80,8 @@ SLOTS_PER_BEAD_STEP = {0: 40 + 8 + 5 + 31, 1: 30 + 6 + 4.5 + 31, 2: 30 + 6 + 4.5
 # launch tile (beads per lane, replicas per wavefront, kernel family) and the
 # noise map are recorded with the figure, and traffic is reported as null when
 # any of them differs.
-FWD_TRAFFIC = {"sha256": "0fa2f8f9f0803c1f59de859579778bddcf5df2164d66974a03d7f2e8030197b7", "noise_map": 2,
-               "tile": (16, 1, 16), "bytes": (48783.375 * 2.0 + 2655981.344) * 1024}
+FWD_TRAFFIC = {"sha256": "272ed74a652b3751cae7697fa7eac13bab2d1a186905b123852f67431a7c2499", "noise_map": 2,
+               "tile": (16, 1, 16), "bytes": (48781.396 * 2.0 + 2655972.604) * 1024}
 FWD_SOURCES = ("ra_kernels.hip", "ra_chain.hpp", "ra_device.hpp", "ra_types.hpp", "ra_launch.hpp")
 
 
@@ -100,7 +100,7 @@ def fwd_sources_digest(files=FWD_SOURCES):
 # SQ_INSTS_VALU_TRANS_F32 SQ_WAVES: (636,828,191 - 43,547,252) / 1001 wavefronts
 # / 750 steps. It holds for the pair kernel sources with this digest only.
 PAIR_SOURCES = ("ra_pair.hip", "ra_chain.hpp", "ra_device.hpp", "ra_dpp.hpp")
-PAIR_SLOTS = {"sha256": "798084c404025a9af2163212cb468ef7d27f1998a6d7691dc9afd54e2ea2babc",
+PAIR_SLOTS = {"sha256": "ad605e15eed9f61ce0d2c49a4d6ed60cbfd68a769bb007705ed98ffad3646d11",
               "slots": (636828191.0 - 43547252.0) / 1001 / 750}
 FP32_VECTOR_PEAK = 157.3e12   # FLOP/s, packed FP32 included
 

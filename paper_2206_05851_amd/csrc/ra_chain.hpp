@@ -133,21 +133,6 @@ __device__ __forceinline__ void init_carry(Carry<T, M>& cy, const GroupDev& G, u
     }
 }
 
-// Map 1, four steps n..n+3 with n a multiple of 4: three blocks per slot.
-template <typename T, int M>
-__device__ __forceinline__ void gen_noise4_map1(Noise<T, M> (&e)[4], const GroupDev& G, uint32_t n, uint32_t bead0,
-                                                uint32_t replica, const RoundKeys& keys) {
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        normals4(philox10(n, bead0 + (uint32_t)m, replica, G.stream, keys), e[0].x[m], e[0].y[m], e[0].z[m],
-                 e[3].x[m]);
-        normals4(philox10(n + 1u, bead0 + (uint32_t)m, replica, G.stream, keys), e[1].x[m], e[1].y[m], e[1].z[m],
-                 e[3].y[m]);
-        normals4(philox10(n + 2u, bead0 + (uint32_t)m, replica, G.stream, keys), e[2].x[m], e[2].y[m], e[2].z[m],
-                 e[3].z[m]);
-    }
-}
-
 // G_j = g_j Q_j of slot m (spring factor evaluated once per slot and step).
 // With TSF the slot's tension f = H g |Q| of the same state is added to
 // tsum[m] (Eq. 4, zero rest length): the step's force evaluation is the TSF

@@ -116,9 +116,12 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
         }
     };
     // noise map 1: with one bead per lane the steps run in aligned groups of
-    // four (three blocks generated ahead, as in the pipeline below); a run's
-    // unaligned head and its tail, and wider lanes, take the carry step by
-    // step. The carry lives for the whole launch (built once for its first
+    // four. The next group's three Philox blocks are drawn at the top of each
+    // group (integer work independent of the steps), and each step transforms
+    // the block it uses just before it, which spreads the transcendentals
+    // over the group (3.5% faster on fene50 than transforming the next
+    // group's blocks along with their draw). A run's unaligned head and its
+    // tail, and wider lanes, take the carry step by step. The carry lives for the whole launch (built once for its first
     // step): segments follow each other in step order, an aligned group
     // neither needs nor changes it, and a partial group is always stepped
     // through the carry, so it holds the current group's fourth normals.
@@ -132,19 +135,31 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
                 accumulate_tsf();
             }
             if (i + 4 <= len) {
-                Noise<T, M> e[4];
-                gen_noise4_map1<T, M>(e, G, n + (uint32_t)i, bead0, rep, keys);
+                Words w[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) w[q] = philox10(n + (uint32_t)(i + q), bead0, rep, G.stream, keys);
                 for (; i + 4 <= len; i += 4) {
                     asm volatile(".p2align 6");
-                    Noise<T, M> f[4];
-                    gen_noise4_map1<T, M>(f, G, n + (uint32_t)(i + 4), bead0, rep, keys);
+                    Words nw[3];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        physics_step<T, M, FENE, FUSED>(s, e[u], G, valid, kc, clamps, tsum);
+                    for (int q = 0; q < 3; ++q)
+                        nw[q] = philox10(n + (uint32_t)(i + 4 + q), bead0, rep, G.stream, keys);
+                    Noise<T, M> e3;
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        Noise<T, M> e;
+                        T d;
+                        normals4(w[u], e.x[0], e.y[0], e.z[0], d);
+                        if (u == 0) e3.x[0] = d;
+                        if (u == 1) e3.y[0] = d;
+                        if (u == 2) e3.z[0] = d;
+                        physics_step<T, M, FENE, FUSED>(s, e, G, valid, kc, clamps, tsum);
                         accumulate_tsf();
                     }
+                    physics_step<T, M, FENE, FUSED>(s, e3, G, valid, kc, clamps, tsum);
+                    accumulate_tsf();
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) e[u] = f[u];
+                    for (int q = 0; q < 3; ++q) w[q] = nw[q];
                 }
             }
         }
