@@ -189,7 +189,33 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
             // basic block as the updates of block b, so the scheduler can fill the
             // update chain's latencies with independent Philox work (one spare
             // block of noise is generated past the end and discarded)
-            if (U <= len) {
+            if constexpr (M == 1) {
+                // one bead per lane: the next U steps' blocks are drawn ahead and
+                // each step transforms its own block just before it (6% faster
+                // on fene50 than transforming along with the draw; with two beads
+                // per lane the draw-and-transform pipeline below is 2% faster)
+                if (U <= len) {
+                    Words w[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) w[u] = philox10(n + (uint32_t)u, bead0, rep, G.stream, keys);
+                    for (; i + U <= len; i += U) {
+                        asm volatile(".p2align 6");
+                        Words nw[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            nw[u] = philox10(n + (uint32_t)(i + U + u), bead0, rep, G.stream, keys);
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            Noise<T, M> e;
+                            normals3(w[u], e.x[0], e.y[0], e.z[0]);
+                            physics_step<T, M, FENE, FUSED>(s, e, G, valid, kc, clamps, tsum);
+                            accumulate_tsf();
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; ++u) w[u] = nw[u];
+                    }
+                }
+            } else if (U <= len) {
                 Noise<T, M> e[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) gen_noise<T, M>(e[u], G, n + (uint32_t)u, bead0, rep, keys);
