@@ -259,7 +259,47 @@ __device__ __forceinline__ void run_adjoint(const AdjArgs& a, const GroupDev& G,
         if constexpr (NMAP == 1) {
             Carry<float, M> cy;
             init_carry<float, M>(cy, G, (uint32_t)s0, (uint32_t)tg.j0, (uint32_t)tg.k, keys);
-            for (int n = s0; n < s1; ++n) {
+            int n = s0;
+            if constexpr (M <= 2) {
+                // aligned groups of four steps as in the forward: the group's
+                // three blocks per slot drawn first, each step's transform just
+                // before the step (the same normals as the carry gives)
+                for (; n < s1 && (n & 3) != 0; ++n) {
+                    seg_store<M>(wp, 0, s, lane);
+                    wp += STRIDE;
+                    em_step_map1<float, M, FENE>(s, cy, G, valid, kc, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k,
+                                                 keys, dummy);
+                }
+                for (; n + 4 <= s1; n += 4) {
+                    Words w[3][M];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+#pragma unroll
+                        for (int m = 0; m < M; ++m)
+                            w[q][m] = philox10((uint32_t)(n + q), (uint32_t)tg.j0 + (uint32_t)m, (uint32_t)tg.k, G.stream,
+                                               keys);
+                    Noise<float, M> e3;
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        Noise<float, M> e;
+#pragma unroll
+                        for (int m = 0; m < M; ++m) {
+                            float d;
+                            normals4(w[u][m], e.x[m], e.y[m], e.z[m], d);
+                            if (u == 0) e3.x[m] = d;
+                            if (u == 1) e3.y[m] = d;
+                            if (u == 2) e3.z[m] = d;
+                        }
+                        seg_store<M>(wp, 0, s, lane);
+                        wp += STRIDE;
+                        physics_step<float, M, FENE>(s, e, G, valid, kc, dummy);
+                    }
+                    seg_store<M>(wp, 0, s, lane);
+                    wp += STRIDE;
+                    physics_step<float, M, FENE>(s, e3, G, valid, kc, dummy);
+                }
+            }
+            for (; n < s1; ++n) {
                 seg_store<M>(wp, 0, s, lane);
                 wp += STRIDE;
                 em_step_map1<float, M, FENE>(s, cy, G, valid, kc, (uint32_t)n, (uint32_t)tg.j0, (uint32_t)tg.k, keys,

@@ -115,13 +115,14 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
             for (int m = 0; m < M; ++m) tpart[m] += f[m];
         }
     };
-    // noise map 1: with one bead per lane the steps run in aligned groups of
-    // four. The next group's three Philox blocks are drawn at the top of each
-    // group (integer work independent of the steps), and each step transforms
-    // the block it uses just before it, which spreads the transcendentals
-    // over the group (3.5% faster on fene50 than transforming the next
-    // group's blocks along with their draw). A run's unaligned head and its
-    // tail, and wider lanes, take the carry step by step. The carry lives for the whole launch (built once for its first
+    // noise map 1: with one or two beads per lane the steps run in aligned
+    // groups of four. The next group's three Philox blocks per slot are drawn
+    // at the top of each group (integer work independent of the steps), and
+    // each step transforms the blocks it uses just before it, which spreads
+    // the transcendentals over the group (against transforming the next
+    // group's blocks along with their draw, 3.5% faster on fene50; against
+    // the carry, 5% faster on two beads per lane). A run's unaligned head and
+    // its tail, and wider lanes, take the carry step by step. The carry lives for the whole launch (built once for its first
     // step): segments follow each other in step order, an aligned group
     // neither needs nor changes it, and a partial group is always stepped
     // through the carry, so it holds the current group's fourth normals.
@@ -129,46 +130,56 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
     if constexpr (NMAP == 1) init_carry<T, M>(cy, G, n0, bead0, rep, keys);
     auto run_steps_map1 = [&](uint32_t n, int len) {
         int i = 0;
-        if constexpr (M == 1) {
+        if constexpr (M <= 2) {
             for (; i < len && ((n + (uint32_t)i) & 3u) != 0u; ++i) {
                 em_step_map1<T, M, FENE, FUSED>(s, cy, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps, tsum);
                 accumulate_tsf();
             }
             if (i + 4 <= len) {
-                Words w[3];
+                Words w[3][M];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) w[q] = philox10(n + (uint32_t)(i + q), bead0, rep, G.stream, keys);
+                for (int q = 0; q < 3; ++q)
+#pragma unroll
+                    for (int m = 0; m < M; ++m)
+                        w[q][m] = philox10(n + (uint32_t)(i + q), bead0 + (uint32_t)m, rep, G.stream, keys);
                 for (; i + 4 <= len; i += 4) {
                     asm volatile(".p2align 6");
-                    Words nw[3];
+                    Words nw[3][M];
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
-                        nw[q] = philox10(n + (uint32_t)(i + 4 + q), bead0, rep, G.stream, keys);
+#pragma unroll
+                        for (int m = 0; m < M; ++m)
+                            nw[q][m] = philox10(n + (uint32_t)(i + 4 + q), bead0 + (uint32_t)m, rep, G.stream, keys);
                     Noise<T, M> e3;
 #pragma unroll
                     for (int u = 0; u < 3; ++u) {
                         Noise<T, M> e;
-                        T d;
-                        normals4(w[u], e.x[0], e.y[0], e.z[0], d);
-                        if (u == 0) e3.x[0] = d;
-                        if (u == 1) e3.y[0] = d;
-                        if (u == 2) e3.z[0] = d;
+#pragma unroll
+                        for (int m = 0; m < M; ++m) {
+                            T d;
+                            normals4(w[u][m], e.x[m], e.y[m], e.z[m], d);
+                            if (u == 0) e3.x[m] = d;
+                            if (u == 1) e3.y[m] = d;
+                            if (u == 2) e3.z[m] = d;
+                        }
                         physics_step<T, M, FENE, FUSED>(s, e, G, valid, kc, clamps, tsum);
                         accumulate_tsf();
                     }
                     physics_step<T, M, FENE, FUSED>(s, e3, G, valid, kc, clamps, tsum);
                     accumulate_tsf();
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) w[q] = nw[q];
+                    for (int q = 0; q < 3; ++q)
+#pragma unroll
+                        for (int m = 0; m < M; ++m) w[q][m] = nw[q][m];
                 }
             }
         }
-        // the rest: with one bead per lane a tail of at most three steps that
-        // starts aligned (the carry is refilled before it is read); wider lanes
-        // step through the carry from the start
+        // the rest: with one or two beads per lane a tail of at most three
+        // steps that starts aligned (the carry is refilled before it is read);
+        // wider lanes step through the carry from the start
         for (; i < len; ++i) {
             em_step_map1<T, M, FENE, FUSED>(s, cy, G, valid, kc, n + (uint32_t)i, bead0, rep, keys, clamps, tsum);
-                accumulate_tsf();
+            accumulate_tsf();
         }
     };
     auto run_steps = [&](uint32_t n, int len) {   // len steps starting at global step n
