@@ -122,10 +122,11 @@ __device__ __forceinline__ void run_forward_impl(const FwdArgs& a, const GroupDe
     // the transcendentals over the group (against transforming the next
     // group's blocks along with their draw, 3.5% faster on fene50; against
     // the carry, 5% faster on two beads per lane). A run's unaligned head and
-    // its tail, and wider lanes, take the carry step by step. The carry lives for the whole launch (built once for its first
-    // step): segments follow each other in step order, an aligned group
-    // neither needs nor changes it, and a partial group is always stepped
-    // through the carry, so it holds the current group's fourth normals.
+    // its tail, and wider lanes, take the carry step by step. The carry lives
+    // for the whole launch (built once for its first step): segments follow
+    // each other in step order, an aligned group neither needs nor changes
+    // it, and a partial group is always stepped through the carry, so it
+    // holds the current group's fourth normals.
     [[maybe_unused]] Carry<T, M> cy;
     if constexpr (NMAP == 1) init_carry<T, M>(cy, G, n0, bead0, rep, keys);
     auto run_steps_map1 = [&](uint32_t n, int len) {
